@@ -1,0 +1,795 @@
+// C ABI of libcpr: context, workspaces and the per-mode schedule of
+// randomized CP-ALS (Alg. 1 with the three steps of Section 4 per mode):
+//   sample (pseudo-inverse, draws, merge) -> sampled MTTKRP -> solve
+//   (U_j = M G^+ with refinement, sigma, renormalisation, Gram, sampler).
+// Everything is enqueued on the context's stream; only calls documented as
+// synchronising wait for it.
+#include "internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+
+using namespace cpr;
+
+namespace {
+
+struct ProfEv {
+  int phase;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct cp_ctx {
+  int N = 0, R = 0, sampler = 0, precision = 0, F = 16;
+  bool f64 = true;
+  int64_t nnz = 0, max_J = 0;
+  int64_t dims[MAXN] = {};
+  hipStream_t s = nullptr;
+  std::string msg;
+  uint32_t *d_err = nullptr;
+  int64_t *d_dims = nullptr;
+  int32_t *coo_idx = nullptr;
+  void *coo_val = nullptr;
+  double normT2 = 0;
+  ModeIndex ix[MAXN];
+  void *U[MAXN] = {};
+  double *G[MAXN] = {};
+  double *sigma = nullptr;
+  double *lev[MAXN] = {}, *cdf[MAXN] = {}, *Zd[MAXN] = {};
+  int64_t *last[MAXN] = {};
+  double *tree[MAXN] = {};
+  int64_t P2[MAXN] = {};
+  double *Gfull = nullptr, *Gp = nullptr, *ggt = nullptr, *trace = nullptr;
+  double *pv_scratch = nullptr, *Gp1 = nullptr, *Gfull1 = nullptr;
+  int32_t *sidx = nullptr;
+  double *prob = nullptr;
+  void *h = nullptr;
+  SampleWork w{};
+  void *M = nullptr;
+  double *X = nullptr, *partial = nullptr;
+  void *tmp = nullptr;
+  double *d_fit = nullptr, *fit_partial = nullptr;
+  int64_t max_I = 0, max_cols = 0;
+  int sampled_mode = -1, mttkrp_mode = -1;
+  int64_t cur_J = 0;
+  bool factor_set[MAXN] = {};
+  bool prof = false;
+  std::vector<ProfEv> evs;
+  size_t ev_used = 0;
+  std::vector<void *> allocs;
+
+  size_t tsize() const { return f64 ? 8 : 4; }
+};
+
+namespace {
+
+struct Fail {
+  cp_status st;
+  std::string msg;
+};
+
+void require(bool ok, cp_status st, const char *msg) {
+  if (!ok) throw Fail{st, msg};
+}
+
+void hip_ok(hipError_t e, const char *what) {
+  if (e != hipSuccess)
+    throw Fail{CP_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename P>
+void dalloc(cp_ctx *c, P **p, size_t bytes) {
+  void *q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess)
+    throw Fail{CP_ENOMEM, "device allocation failed"};
+  c->allocs.push_back(q);
+  *p = static_cast<P *>(q);
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+class PhaseScope {
+ public:
+  PhaseScope(cp_ctx *c, int ph) : c_(c), ph_(ph) {
+    if (!c_->prof) return;
+    if (c_->ev_used == c_->evs.size()) {
+      ProfEv e{ph, nullptr, nullptr};
+      hip_ok(hipEventCreate(&e.a), "hipEventCreate");
+      hip_ok(hipEventCreate(&e.b), "hipEventCreate");
+      c_->evs.push_back(e);
+    }
+    idx_ = c_->ev_used++;
+    c_->evs[idx_].phase = ph;
+    hip_ok(hipEventRecord(c_->evs[idx_].a, c_->s), "hipEventRecord");
+  }
+  ~PhaseScope() {
+    if (c_->prof && idx_ != (size_t)-1) (void)hipEventRecord(c_->evs[idx_].b, c_->s);
+  }
+
+ private:
+  cp_ctx *c_;
+  int ph_;
+  size_t idx_ = (size_t)-1;
+};
+
+ModeList make_ml(cp_ctx *c, int j) {
+  ModeList ml;
+  std::memset(&ml, 0, sizeof(ml));
+  uint64_t st = 1;
+  for (int k = 0; k < c->N; ++k) {
+    if (k == j) continue;
+    const int q = ml.n++;
+    ml.mode[q] = k;
+    ml.G[q] = c->G[k];
+    ml.U[q] = c->U[k];
+    ml.I[q] = c->dims[k];
+    ml.stride[q] = st;
+    st *= (uint64_t)c->dims[k];
+    ml.lev[q] = c->lev[k];
+    ml.cdf[q] = c->cdf[k];
+    ml.Z[q] = c->Zd[k];
+    ml.last[q] = c->last[k];
+    ml.tree[q] = c->tree[k];
+    ml.P2[q] = c->P2[k];
+    ml.Ggt[q] = c->ggt ? c->ggt + (int64_t)q * c->R * c->R : nullptr;
+  }
+  return ml;
+}
+
+ModeList make_ml_all(cp_ctx *c) {
+  ModeList ml;
+  std::memset(&ml, 0, sizeof(ml));
+  for (int k = 0; k < c->N; ++k) {
+    ml.mode[k] = k;
+    ml.G[k] = c->G[k];
+    ml.U[k] = c->U[k];
+    ml.I[k] = c->dims[k];
+  }
+  ml.n = c->N;
+  return ml;
+}
+
+cp_status read_errors(cp_ctx *c) {
+  uint32_t e = 0;
+  hip_ok(hipMemcpyAsync(&e, c->d_err, 4, hipMemcpyDeviceToHost, c->s),
+         "hipMemcpyAsync");
+  hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+  if (!e) return CP_OK;
+  const uint32_t zero = 0;
+  hip_ok(hipMemcpyAsync(c->d_err, &zero, 4, hipMemcpyHostToDevice, c->s),
+         "hipMemcpyAsync");
+  hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+  std::string m = "device reported:";
+  if (e & ERR_INDEX) m += " index out of range;";
+  if (e & ERR_DUP) m += " duplicate coordinate tuple;";
+  if (e & ERR_UNIFORM) m += " uniform outside [0,1);";
+  if (e & ERR_ZERO_MASS) m += " zero sampling mass;";
+  if (e & ERR_NONFINITE) m += " non-finite value;";
+  if (e & ERR_PINV) m += " pseudo-inverse did not converge;";
+  if (e & ERR_CAPACITY) m += " capacity exceeded;";
+  cp_status st = CP_EINVAL;
+  if (e & (ERR_NONFINITE | ERR_PINV)) st = CP_ENUMERIC;
+  if (e & ERR_ZERO_MASS) st = CP_EDEGENERATE;
+  if (e & (ERR_INDEX | ERR_DUP | ERR_UNIFORM | ERR_CAPACITY)) st = CP_EINVAL;
+  throw Fail{st, m};
+}
+
+template <typename F>
+cp_status guard(cp_ctx *c, F &&fn) {
+  try {
+    fn();
+    if (c) c->msg.clear();
+    return CP_OK;
+  } catch (const Fail &f) {
+    if (c) c->msg = f.msg;
+    return f.st;
+  } catch (const HipFail &h) {
+    if (c)
+      c->msg = std::string("HIP launch error: ") + hipGetErrorString(h.e) +
+               " at " + h.file + ":" + std::to_string(h.line);
+    return CP_EHIP;
+  } catch (const std::bad_alloc &) {
+    if (c) c->msg = "host allocation failed";
+    return CP_ENOMEM;
+  }
+}
+
+void check_mode(cp_ctx *c, int mode) {
+  require(mode >= 0 && mode < c->N, CP_EINVAL, "mode out of range");
+}
+
+void check_factors(cp_ctx *c) {
+  for (int k = 0; k < c->N; ++k)
+    require(c->factor_set[k], CP_ESTATE, "cp_set_factor not called for every mode");
+}
+
+template <typename T>
+void rebuild_sampler(cp_ctx *c, int k) {
+  PhaseScope ps(c, PH_SAMPLER_BUILD);
+  const T *U = static_cast<const T *>(c->U[k]);
+  if (c->sampler == CP_SAMPLER_ARLS_LEV) {
+    ModeList m1;
+    std::memset(&m1, 0, sizeof(m1));
+    m1.n = 1;
+    m1.G[0] = c->G[k];
+    hadamard_pinv(m1, c->R, c->Gfull1, c->Gp1, nullptr, nullptr, c->pv_scratch,
+                  c->d_err, c->s);
+    arls_build<T>(U, c->dims[k], c->R, c->Gp1, c->lev[k], c->cdf[k], c->Zd[k],
+                  c->last[k], c->tmp, c->d_err, c->s);
+  } else if (c->sampler == CP_SAMPLER_STS) {
+    sts_build<T>(U, c->dims[k], c->R, c->F, c->P2[k], c->tree[k], c->s);
+  }
+}
+
+template <typename T>
+void do_set_factor(cp_ctx *c, int mode, const double *Uin) {
+  const int64_t I = c->dims[mode];
+  normalize_in_place<T>(Uin, I, c->R, static_cast<T *>(c->U[mode]), c->partial,
+                        c->d_err, c->s);
+  {
+    PhaseScope ps(c, PH_GRAM);
+    gram<T>(static_cast<T *>(c->U[mode]), I, c->R, c->G[mode], c->tmp, c->s);
+  }
+  rebuild_sampler<T>(c, mode);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(MAXR), 0, c->s, c->sigma,
+                     (int64_t)c->R, 1.0);
+  CPR_LAUNCH_CHECK();
+}
+
+void pinv_for(cp_ctx *c, const ModeList &ml, bool sts) {
+  PhaseScope ps(c, PH_PINV);
+  hadamard_pinv(ml, c->R, c->Gfull, c->Gp, sts ? c->ggt : nullptr, c->trace,
+                c->pv_scratch, c->d_err, c->s);
+}
+
+template <typename T>
+void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
+  const ModeList ml = make_ml(c, mode);
+  const bool sts = c->sampler == CP_SAMPLER_STS;
+  pinv_for(c, ml, sts);
+  {
+    PhaseScope ps(c, PH_SAMPLE);
+    if (sts)
+      sts_draw<T>(ml, J, c->R, c->F, uni, c->Gp, c->trace, c->sidx, c->prob,
+                  static_cast<T *>(c->h), c->d_err, c->s);
+    else
+      arls_draw<T>(ml, J, c->R, uni, c->sidx, c->prob, static_cast<T *>(c->h),
+                   c->d_err, c->s);
+  }
+  {
+    PhaseScope ps(c, PH_DEDUP);
+    lookup_columns(ml, J, c->sidx, c->ix[mode].col_key, c->ix[mode].n_cols,
+                   c->w, c->s);
+    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
+  }
+  c->sampled_mode = mode;
+  c->mttkrp_mode = -1;
+  c->cur_J = J;
+}
+
+template <typename T>
+void do_set_samples(cp_ctx *c, int mode, int64_t J, const int32_t *idx,
+                    const double *prob) {
+  const ModeList ml = make_ml(c, mode);
+  pinv_for(c, ml, false);
+  hip_ok(hipMemcpyAsync(c->sidx, idx, J * (c->N - 1) * 4,
+                        hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+  hip_ok(hipMemcpyAsync(c->prob, prob, J * 8, hipMemcpyDeviceToDevice, c->s),
+         "hipMemcpyAsync");
+  set_sample_rows<T>(ml, J, c->R, c->sidx, static_cast<T *>(c->h), c->d_err,
+                     c->s);
+  {
+    PhaseScope ps(c, PH_DEDUP);
+    lookup_columns(ml, J, c->sidx, c->ix[mode].col_key, c->ix[mode].n_cols,
+                   c->w, c->s);
+    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
+  }
+  c->sampled_mode = mode;
+  c->mttkrp_mode = -1;
+  c->cur_J = J;
+}
+
+template <typename T>
+void do_mttkrp(cp_ctx *c, int mode) {
+  const ModeIndex &ix = c->ix[mode];
+  T *M = static_cast<T *>(c->M);
+  PhaseScope ps(c, PH_MTTKRP);
+  zero_fill<T>(M, c->dims[mode] * c->R, c->s);
+  if (c->sampler == CP_SAMPLER_EXACT) {
+    const ModeList ml = make_ml(c, mode);
+    exact_mttkrp<T>(ml, ix.n_cols, ix.col_key, ix.col_ptr, ix.row,
+                    static_cast<const T *>(ix.val), c->R, M, c->s);
+  } else {
+    sampled_mttkrp<T>(c->w, c->cur_J, ix.col_ptr, ix.row,
+                      static_cast<const T *>(ix.val),
+                      static_cast<const T *>(c->h), c->R, M, c->s);
+  }
+  c->mttkrp_mode = mode;
+}
+
+template <typename T>
+void do_solve(cp_ctx *c, int mode) {
+  const int64_t I = c->dims[mode];
+  {
+    PhaseScope ps(c, PH_SOLVE);
+    const int nblk = solve_blocks(I);
+    solve_rows<T>(static_cast<const T *>(c->M), I, c->R, c->Gfull, c->Gp, c->X,
+                  c->partial, nblk, c->w.stats + 3, c->s);
+    finish_normalize<T>(c->X, I, c->R, c->partial, nblk, c->sigma,
+                        static_cast<T *>(c->U[mode]), c->d_err, c->s);
+  }
+  {
+    PhaseScope ps(c, PH_GRAM);
+    gram<T>(static_cast<const T *>(c->U[mode]), I, c->R, c->G[mode], c->tmp,
+            c->s);
+  }
+  rebuild_sampler<T>(c, mode);
+  c->sampled_mode = -1;
+  c->mttkrp_mode = -1;
+}
+
+template <typename T>
+void do_fit(cp_ctx *c, double *fit) {
+  const ModeList ml = make_ml_all(c);
+  const int nb = fit_blocks(c->nnz);
+  {
+    PhaseScope ps(c, PH_FIT);
+    fit_inner<T>(c->coo_idx, static_cast<const T *>(c->coo_val), c->nnz, c->N,
+                 ml, c->sigma, c->R, c->fit_partial, nb, c->s);
+    fit_finish(ml, c->N, c->R, c->sigma, c->fit_partial, nb, c->normT2,
+               c->d_fit, c->s);
+  }
+  hip_ok(hipMemcpyAsync(fit, c->d_fit, 8, hipMemcpyDeviceToHost, c->s),
+         "hipMemcpyAsync");
+  read_errors(c);
+}
+
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
+  c->N = t->N;
+  c->R = cfg->R;
+  c->sampler = cfg->sampler;
+  c->precision = cfg->precision;
+  c->F = cfg->sts_leaf ? cfg->sts_leaf : 16;
+  c->f64 = (c->precision == CP_FP64);
+  c->nnz = t->nnz;
+  c->max_J = cfg->max_J;
+  const int N = c->N, R = c->R;
+  for (int k = 0; k < N; ++k) c->dims[k] = t->dims[k];
+  dalloc(c, &c->d_err, 4);
+  dalloc(c, &c->d_dims, N * 8);
+  hip_ok(hipMemsetAsync(c->d_err, 0, 4, c->s), "hipMemsetAsync");
+  hip_ok(hipMemcpyAsync(c->d_dims, c->dims, N * 8, hipMemcpyHostToDevice, c->s),
+         "hipMemcpyAsync");
+  validate_coo(t->idx, t->val, t->val_is_fp64, t->nnz, N, c->d_dims, c->d_err,
+               c->s);
+  read_errors(c);
+  // COO copy for the fit, values in the path's precision
+  dalloc(c, &c->coo_idx, (size_t)t->nnz * N * 4);
+  hip_ok(hipMemcpyAsync(c->coo_idx, t->idx, (size_t)t->nnz * N * 4,
+                        hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+  dalloc(c, &c->coo_val, (size_t)t->nnz * c->tsize());
+  for (int k = 0; k < N; ++k) {
+    std::string e = build_mode_index(t->idx, t->val, t->val_is_fp64, t->nnz, N,
+                                     c->dims, k, c->f64, c->ix[k], c->d_err,
+                                     c->s);
+    if (c->ix[k].row) c->allocs.push_back(c->ix[k].row);
+    if (c->ix[k].val) c->allocs.push_back(c->ix[k].val);
+    if (c->ix[k].col_key) c->allocs.push_back(c->ix[k].col_key);
+    if (c->ix[k].col_ptr) c->allocs.push_back(c->ix[k].col_ptr);
+    if (!e.empty())
+      throw Fail{e.find("63 bits") != std::string::npos ? CP_EUNSUPPORTED
+                                                         : CP_ENOMEM, e};
+    read_errors(c);
+    c->max_cols = std::max(c->max_cols, c->ix[k].n_cols);
+    c->max_I = std::max(c->max_I, c->dims[k]);
+  }
+  // values of the COO copy, in the path's precision
+  convert_values(t->val, t->val_is_fp64, c->coo_val, c->f64, t->nnz, c->s);
+  c->normT2 = sum_squares(c->coo_val, c->f64, c->nnz, c->s);
+  require(c->normT2 > 0, CP_EINVAL, "tensor has zero norm");
+
+  const size_t ts = c->tsize();
+  for (int k = 0; k < N; ++k) {
+    const int64_t I = c->dims[k];
+    dalloc(c, &c->U[k], (size_t)I * R * ts);
+    dalloc(c, &c->G[k], (size_t)R * R * 8);
+    if (c->sampler == CP_SAMPLER_ARLS_LEV) {
+      dalloc(c, &c->lev[k], I * 8);
+      dalloc(c, &c->cdf[k], I * 8);
+      dalloc(c, &c->Zd[k], 8);
+      dalloc(c, &c->last[k], 8);
+    } else if (c->sampler == CP_SAMPLER_STS) {
+      c->P2[k] = next_pow2((I + c->F - 1) / c->F);
+      dalloc(c, &c->tree[k], (size_t)2 * c->P2[k] * sts_packed(R) * 8);
+    }
+  }
+  dalloc(c, &c->sigma, R * 8);
+  dalloc(c, &c->Gfull, R * R * 8);
+  dalloc(c, &c->Gp, R * R * 8);
+  dalloc(c, &c->Gfull1, R * R * 8);
+  dalloc(c, &c->Gp1, R * R * 8);
+  dalloc(c, &c->pv_scratch, R * R * 8);
+  dalloc(c, &c->ggt, (size_t)(N - 1) * R * R * 8);
+  dalloc(c, &c->trace, 8);
+  const int64_t J = std::max<int64_t>(c->max_J, 1);
+  dalloc(c, &c->sidx, (size_t)J * (N - 1) * 4);
+  dalloc(c, &c->prob, J * 8);
+  dalloc(c, &c->h, (size_t)J * R * ts);
+  dalloc(c, &c->w.col_id, J * 4);
+  dalloc(c, &c->w.owner, c->max_cols * 4);
+  dalloc(c, &c->w.dupcnt, J * 4);
+  dalloc(c, &c->w.uq_s, J * 4);
+  dalloc(c, &c->w.uq_cid, J * 4);
+  dalloc(c, &c->w.uq_cnt, J * 4);
+  dalloc(c, &c->w.uq_w, J * 8);
+  dalloc(c, &c->w.uq_off, (J + 1) * 8);
+  dalloc(c, &c->w.counts, 16);
+  dalloc(c, &c->w.stats, 4 * 8);
+  zero_fill<int64_t>(c->w.stats, 4, c->s);
+  dalloc(c, &c->M, (size_t)c->max_I * R * ts);
+  dalloc(c, &c->X, (size_t)c->max_I * R * 8);
+  dalloc(c, &c->partial, (size_t)(1024 + 2) * R * 8);
+  dalloc(c, &c->tmp, std::max(gram_temp_bytes(c->max_I, R),
+                              256 + scan_temp_bytes(c->max_I)));
+  dalloc(c, &c->d_fit, 4 * 8);
+  dalloc(c, &c->fit_partial, fit_blocks(c->nnz) * 8);
+  hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(c->max_cols, 256)), dim3(256),
+                     0, c->s, c->w.owner, c->max_cols, INT_MAX);
+  zero_fill<int32_t>(c->w.dupcnt, J, c->s);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(MAXR), 0, c->s, c->sigma,
+                     (int64_t)R, 1.0);
+  CPR_LAUNCH_CHECK();
+  read_errors(c);
+}
+
+void destroy_ctx(cp_ctx *c) {
+  if (!c) return;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  for (void *p : c->allocs) (void)hipFree(p);
+  for (auto &e : c->evs) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+cp_status cp_init(const cp_tensor *t, const cp_config *cfg, void *stream,
+                  cp_ctx **out) {
+  if (!out) return CP_EINVAL;
+  *out = nullptr;
+  if (!t || !cfg || !t->dims || !t->idx || !t->val) return CP_EINVAL;
+  if (t->N < 3 || t->N > MAXN || t->nnz < 1 || t->nnz >= (int64_t(1) << 32))
+    return CP_EINVAL;
+  for (int k = 0; k < t->N; ++k)
+    if (t->dims[k] < 1 || t->dims[k] >= (int64_t(1) << 31)) return CP_EINVAL;
+  if (cfg->R < 1 || cfg->R > MAXR) return CP_EINVAL;
+  if (cfg->sampler < 0 || cfg->sampler > 2) return CP_EINVAL;
+  if (cfg->precision < 0 || cfg->precision > 2) return CP_EINVAL;
+  if (cfg->sampler != CP_SAMPLER_EXACT &&
+      (cfg->max_J < 1 || cfg->max_J > INT_MAX))
+    return CP_EINVAL;
+  if (cfg->sts_leaf != 0 && cfg->sts_leaf != 16 && cfg->sts_leaf != 32 &&
+      cfg->sts_leaf != 64)
+    return CP_EINVAL;
+  if (cfg->precision == CP_MIXED) return CP_EUNSUPPORTED;
+  if (cfg->sampler == CP_SAMPLER_STS && cfg->R > 64) return CP_EUNSUPPORTED;
+  cp_ctx *c = new (std::nothrow) cp_ctx;
+  if (!c) return CP_ENOMEM;
+  c->s = static_cast<hipStream_t>(stream);
+  cp_status st = guard(c, [&] { init_ctx(c, t, cfg); });
+  if (st != CP_OK) {
+    // keep the message reachable through a minimal context
+    std::string m = c->msg;
+    destroy_ctx(c);
+    c = new (std::nothrow) cp_ctx;
+    if (c) {
+      c->msg = m;
+      c->s = static_cast<hipStream_t>(stream);
+      c->N = 0;
+    }
+    *out = c;
+    return st;
+  }
+  *out = c;
+  return CP_OK;
+}
+
+cp_status cp_set_factor(cp_ctx *c, int32_t mode, const double *U) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    require(U != nullptr, CP_EINVAL, "null factor");
+    if (c->f64) do_set_factor<double>(c, mode, U);
+    else do_set_factor<float>(c, mode, U);
+    c->factor_set[mode] = true;
+    c->sampled_mode = c->mttkrp_mode = -1;
+  });
+}
+
+cp_status cp_set_sigma(cp_ctx *c, const double *sigma) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    require(sigma != nullptr, CP_EINVAL, "null sigma");
+    hip_ok(hipMemcpyAsync(c->sigma, sigma, c->R * 8, hipMemcpyDeviceToDevice,
+                          c->s), "hipMemcpyAsync");
+  });
+}
+
+cp_status cp_sample(cp_ctx *c, int32_t mode, int64_t J, const double *uni,
+                    int32_t *idx_out, double *prob_out) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    check_factors(c);
+    require(c->sampler != CP_SAMPLER_EXACT, CP_EINVAL,
+            "the exact sampler draws nothing");
+    require(J >= 1 && J <= c->max_J, CP_EINVAL, "J outside [1, max_J]");
+    require(uni != nullptr, CP_EINVAL, "null uniforms");
+    if (c->f64) do_sample<double>(c, mode, J, uni);
+    else do_sample<float>(c, mode, J, uni);
+    if (idx_out)
+      hip_ok(hipMemcpyAsync(idx_out, c->sidx, J * (c->N - 1) * 4,
+                            hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+    if (prob_out)
+      hip_ok(hipMemcpyAsync(prob_out, c->prob, J * 8, hipMemcpyDeviceToDevice,
+                            c->s), "hipMemcpyAsync");
+  });
+}
+
+cp_status cp_set_samples(cp_ctx *c, int32_t mode, int64_t J, const int32_t *idx,
+                         const double *prob) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    check_factors(c);
+    require(c->sampler != CP_SAMPLER_EXACT, CP_EINVAL,
+            "the exact sampler takes no samples");
+    require(J >= 1 && J <= c->max_J, CP_EINVAL, "J outside [1, max_J]");
+    require(idx && prob, CP_EINVAL, "null samples");
+    if (c->f64) do_set_samples<double>(c, mode, J, idx, prob);
+    else do_set_samples<float>(c, mode, J, idx, prob);
+  });
+}
+
+cp_status cp_sampled_mttkrp(cp_ctx *c, int32_t mode, void *M_out,
+                            int64_t *nnz_extracted) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    check_factors(c);
+    if (c->sampler == CP_SAMPLER_EXACT) {
+      pinv_for(c, make_ml(c, mode), false);
+    } else {
+      require(c->sampled_mode == mode, CP_ESTATE,
+              "cp_sampled_mttkrp without samples for this mode");
+    }
+    if (c->f64) do_mttkrp<double>(c, mode);
+    else do_mttkrp<float>(c, mode);
+    if (M_out)
+      hip_ok(hipMemcpyAsync(M_out, c->M, c->dims[mode] * c->R * c->tsize(),
+                            hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+    if (nnz_extracted) {
+      if (c->sampler == CP_SAMPLER_EXACT) {
+        *nnz_extracted = c->nnz;
+        read_errors(c);
+      } else {
+        int64_t cnt[2] = {0, 0};
+        hip_ok(hipMemcpyAsync(cnt, c->w.counts, 16, hipMemcpyDeviceToHost,
+                              c->s), "hipMemcpyAsync");
+        read_errors(c);
+        *nnz_extracted = cnt[1];
+      }
+    }
+  });
+}
+
+cp_status cp_solve_factor(cp_ctx *c, int32_t mode) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    require(c->mttkrp_mode == mode, CP_ESTATE,
+            "cp_solve_factor without a sampled MTTKRP for this mode");
+    if (c->f64) do_solve<double>(c, mode);
+    else do_solve<float>(c, mode);
+  });
+}
+
+cp_status cp_sweep(cp_ctx *c, int32_t nsweeps, int64_t J, const double *uni) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_factors(c);
+    require(nsweeps >= 0, CP_EINVAL, "negative sweep count");
+    const bool exact = c->sampler == CP_SAMPLER_EXACT;
+    if (!exact) {
+      require(J >= 1 && J <= c->max_J, CP_EINVAL, "J outside [1, max_J]");
+      require(uni != nullptr, CP_EINVAL, "null uniforms");
+    }
+    const int N = c->N;
+    for (int t = 0; t < nsweeps; ++t)
+      for (int j = 0; j < N; ++j) {
+        if (exact) {
+          pinv_for(c, make_ml(c, j), false);
+        } else {
+          const double *u = uni + ((int64_t)t * N + j) * J * (N - 1);
+          if (c->f64) do_sample<double>(c, j, J, u);
+          else do_sample<float>(c, j, J, u);
+        }
+        if (c->f64) {
+          do_mttkrp<double>(c, j);
+          do_solve<double>(c, j);
+        } else {
+          do_mttkrp<float>(c, j);
+          do_solve<float>(c, j);
+        }
+      }
+  });
+}
+
+cp_status cp_fit(cp_ctx *c, double *fit) {
+  if (!c || !c->N || !fit) return CP_EINVAL;
+  return guard(c, [&] {
+    check_factors(c);
+    if (c->f64) do_fit<double>(c, fit);
+    else do_fit<float>(c, fit);
+  });
+}
+
+cp_status cp_sync(cp_ctx *c) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] { read_errors(c); });
+}
+
+cp_status cp_get_factor(cp_ctx *c, int32_t mode, double *U_out) {
+  if (!c || !c->N || !U_out) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    copy_to_f64(c->U[mode], c->f64, U_out, c->dims[mode] * c->R, c->s);
+  });
+}
+
+cp_status cp_get_sigma(cp_ctx *c, double *sigma_out) {
+  if (!c || !c->N || !sigma_out) return CP_EINVAL;
+  return guard(c, [&] {
+    hip_ok(hipMemcpyAsync(sigma_out, c->sigma, c->R * 8,
+                          hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+  });
+}
+
+cp_status cp_get_gram(cp_ctx *c, int32_t mode, double *G_out) {
+  if (!c || !c->N || !G_out) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    hip_ok(hipMemcpyAsync(G_out, c->G[mode], c->R * c->R * 8,
+                          hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+  });
+}
+
+cp_status cp_get_unique(cp_ctx *c, uint64_t *col_key, int32_t *rep,
+                        int32_t *count, double *weight, int64_t cap,
+                        int64_t *n_out) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    require(c->sampled_mode >= 0, CP_ESTATE, "no samples");
+    int64_t cnt[2] = {0, 0};
+    hip_ok(hipMemcpyAsync(cnt, c->w.counts, 16, hipMemcpyDeviceToHost, c->s),
+           "hipMemcpyAsync");
+    hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+    debug_unique(c->w, cnt[0], c->ix[c->sampled_mode].col_key, col_key, rep,
+                 count, weight, cap, c->s);
+    if (n_out) *n_out = cnt[0];
+    read_errors(c);
+  });
+}
+
+cp_status cp_get_extracted(cp_ctx *c, uint64_t *col_key, int32_t *row,
+                           int32_t *rep, int64_t cap, int64_t *n_out) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    require(c->sampled_mode >= 0, CP_ESTATE, "no samples");
+    const ModeIndex &ix = c->ix[c->sampled_mode];
+    int64_t cnt[2] = {0, 0};
+    hip_ok(hipMemcpyAsync(cnt, c->w.counts, 16, hipMemcpyDeviceToHost, c->s),
+           "hipMemcpyAsync");
+    hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+    debug_extracted(c->w, cnt[1], ix.col_ptr, ix.col_key, ix.row, col_key, row,
+                    rep, cap, c->s);
+    if (n_out) *n_out = cnt[1];
+    read_errors(c);
+  });
+}
+
+cp_status cp_profile(cp_ctx *c, int32_t enable) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    if (enable) c->ev_used = 0;
+    c->prof = enable != 0;
+  });
+}
+
+cp_status cp_profile_read(cp_ctx *c, double *ms, int64_t *launches) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+    for (int p = 0; p < CP_NPHASE; ++p) {
+      if (ms) ms[p] = 0;
+      if (launches) launches[p] = 0;
+    }
+    for (size_t i = 0; i < c->ev_used; ++i) {
+      float t = 0;
+      hip_ok(hipEventElapsedTime(&t, c->evs[i].a, c->evs[i].b),
+             "hipEventElapsedTime");
+      const int p = c->evs[i].phase;
+      if (ms) ms[p] += t;
+      if (launches) launches[p] += 1;
+    }
+  });
+}
+
+cp_status cp_counters(cp_ctx *c, int64_t *out, int32_t reset) {
+  if (!c || !c->N || !out) return CP_EINVAL;
+  return guard(c, [&] {
+    hip_ok(hipMemcpyAsync(out, c->w.stats, 4 * 8, hipMemcpyDeviceToHost, c->s),
+           "hipMemcpyAsync");
+    hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+    if (reset) zero_fill<int64_t>(c->w.stats, 4, c->s);
+  });
+}
+
+const char *cp_phase_name(int32_t phase) {
+  static const char *names[CP_NPHASE] = {
+      "pinv", "sample", "merge", "mttkrp", "solve", "gram", "sampler_build",
+      "fit"};
+  return (phase >= 0 && phase < CP_NPHASE) ? names[phase] : "?";
+}
+
+cp_status cp_index_stats(cp_ctx *c, int32_t mode, int64_t *n_cols,
+                         int64_t *max_col) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    if (n_cols) *n_cols = c->ix[mode].n_cols;
+    if (max_col) *max_col = c->ix[mode].max_col;
+  });
+}
+
+void cp_destroy(cp_ctx *c) { destroy_ctx(c); }
+
+const char *cp_last_error(const cp_ctx *c) {
+  return c ? c->msg.c_str() : "null context";
+}
+
+const char *cp_status_string(cp_status s) {
+  switch (s) {
+    case CP_OK: return "CP_OK";
+    case CP_EINVAL: return "CP_EINVAL";
+    case CP_ENOMEM: return "CP_ENOMEM";
+    case CP_EHIP: return "CP_EHIP";
+    case CP_ESTATE: return "CP_ESTATE";
+    case CP_EDEGENERATE: return "CP_EDEGENERATE";
+    case CP_ENUMERIC: return "CP_ENUMERIC";
+    case CP_EUNSUPPORTED: return "CP_EUNSUPPORTED";
+  }
+  return "unknown";
+}
+
+}  // extern "C"

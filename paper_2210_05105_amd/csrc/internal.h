@@ -1,0 +1,207 @@
+// Internal declarations shared by the HIP translation units of libcpr.
+// Everything here is gfx950 (CDNA4, wave64) code; nothing is portable on
+// purpose.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/cpr.h"
+
+namespace cpr {
+
+constexpr int WAVE = 64;
+constexpr int MAXN = 8;
+constexpr int MAXR = 128;
+
+// Bits of the device error word (kernels atomicOr them in; synchronising
+// calls read and clear it).
+enum : uint32_t {
+  ERR_INDEX = 1u,      // coordinate outside [0, I_k)
+  ERR_DUP = 2u,        // repeated coordinate tuple
+  ERR_UNIFORM = 4u,    // uniform outside [0, 1) or NaN
+  ERR_ZERO_MASS = 8u,  // sampling mass Z <= 0
+  ERR_NONFINITE = 16u, // NaN/Inf in a factor or value
+  ERR_PINV = 32u,      // Jacobi eigen solver did not converge
+  ERR_CAPACITY = 64u,  // a device-sized buffer would overflow
+};
+
+// Profiling phases (order matches cp_phase_name).
+enum Phase { PH_PINV = 0, PH_SAMPLE, PH_DEDUP, PH_MTTKRP, PH_SOLVE,
+             PH_GRAM, PH_SAMPLER_BUILD, PH_FIT };
+
+// Small argument block for kernels that need per-mode pointers.
+struct ModeList {
+  int n;                      // number of entries used
+  int mode[MAXN];
+  const double *G[MAXN];      // R x R Grams
+  const void *U[MAXN];        // factors (float or double)
+  int64_t I[MAXN];
+  uint64_t stride[MAXN];      // column-key stride of each mode for mode j
+  const double *lev[MAXN];    // ARLS scores
+  const double *cdf[MAXN];    // ARLS inclusive prefix sums
+  const double *Z[MAXN];      // ARLS totals (device scalars)
+  const int64_t *last[MAXN];  // ARLS last row of positive mass
+  const double *tree[MAXN];   // STS trees
+  int64_t P2[MAXN];           // STS leaves (power of two)
+  const double *Ggt[MAXN];    // STS G_{>k} per sampled position (R x R)
+};
+
+// ---- index build (k_index.hip)
+uint32_t *validate_coo(const int32_t *idx, const void *val, int val_fp64,
+                       int64_t nnz, int N, const int64_t *dims,
+                       uint32_t *err, hipStream_t s);
+struct ModeIndex {
+  int64_t I = 0, n_cols = 0, max_col = 0;
+  uint64_t *col_key = nullptr;  // n_cols sorted distinct column keys
+  int64_t *col_ptr = nullptr;   // n_cols + 1 offsets
+  int32_t *row = nullptr;       // nnz rows i_j
+  void *val = nullptr;          // nnz values (float or double)
+};
+// Returns an error message ("" on success).
+std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
+                             int64_t nnz, int N, const int64_t *dims, int j,
+                             int out_fp64, ModeIndex &out, uint32_t *err,
+                             hipStream_t s);
+
+// ---- scans (k_scan.hip): deterministic reduce-then-scan
+size_t scan_temp_bytes(int64_t n);
+void inclusive_scan_f64(const double *in, double *out, int64_t n, void *tmp,
+                        hipStream_t s);
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n,
+                        void *tmp, hipStream_t s);
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                        void *tmp, hipStream_t s);
+
+// ---- dense R x R and tall-skinny kernels (k_dense.hip)
+// Gram of U (I x R): partial Grams per block (FP64 MFMA), then a fixed-order
+// reduction into G (R x R).  `scale` (R doubles or null) multiplies column r
+// by scale[r] before the product (used for renormalisation in place when
+// U_out is given: U_out = U * scale).
+size_t gram_temp_bytes(int64_t I, int R);
+template <typename T>
+void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s);
+// Hadamard product of the Grams in `ml` (n entries), pseudo-inverse Gp;
+// for STS also the G_{>k} chain and <G^+, G> (ggt_out may be null).
+void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
+                   double *ggt_out, double *trace_out, double *scratch,
+                   uint32_t *err, hipStream_t s);
+// X = M G^+ with one refinement step (FP64), written as double; per-block
+// column sums of squares into partial (nblk x R).
+template <typename T>
+void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
+                const double *Gp, double *X, double *partial, int nblk,
+                int64_t *rows_out, hipStream_t s);
+int solve_blocks(int64_t I);
+// sigma from partial sums; U = X / sigma (zero columns stay zero).
+template <typename T>
+void finish_normalize(const double *X, int64_t I, int R, const double *partial,
+                      int nblk, double *sigma, T *U, uint32_t *err,
+                      hipStream_t s);
+// U := U / ||U[:, r]|| in place (cp_set_factor), sigma unchanged.
+template <typename T>
+void normalize_in_place(const double *Uin, int64_t I, int R, T *U,
+                        double *partial, uint32_t *err, hipStream_t s);
+template <typename T>
+void zero_fill(T *p, int64_t n, hipStream_t s);
+void copy_to_f64(const void *src, int src_fp64, double *dst, int64_t n,
+                 hipStream_t s);
+void convert_values(const void *src, int src_fp64, void *dst, int dst_fp64,
+                    int64_t n, hipStream_t s);
+
+// ---- CP-ARLS-LEV (k_arls.hip)
+template <typename T>
+void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
+                double *cdf, double *Z, int64_t *last, void *tmp,
+                uint32_t *err, hipStream_t s);
+template <typename T>
+void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
+               int32_t *sidx, double *prob, T *h, uint32_t *err, hipStream_t s);
+
+// ---- STS-CP (k_sts.hip)
+int sts_packed(int R);
+template <typename T>
+void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
+               hipStream_t s);
+template <typename T>
+void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,
+              const double *Gp, const double *trace, int32_t *sidx,
+              double *prob, T *h, uint32_t *err, hipStream_t s);
+
+// ---- sample merge, extraction, MTTKRP (k_mttkrp.hip)
+struct SampleWork {
+  int32_t *col_id;   // J: column in the mode's index, -1 if empty
+  int32_t *owner;    // n_cols_max: first draw of a column (INT_MAX = none)
+  int32_t *dupcnt;   // J: extra draws merged into this first draw
+  int32_t *uq_s;     // J: first draw of each distinct column
+  int32_t *uq_cid;   // J: column id
+  int32_t *uq_cnt;   // J: number of draws of the column
+  double *uq_w;      // J: weight count/(J p)
+  int64_t *uq_off;   // J+1: extracted-nonzero offsets
+  int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
+  int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
+};
+template <typename T>
+void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
+                     T *h, uint32_t *err, hipStream_t s);
+void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
+                    const uint64_t *col_key, int64_t n_cols, SampleWork &w,
+                    hipStream_t s);
+void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
+                   SampleWork &w, hipStream_t s);
+template <typename T>
+void sampled_mttkrp(const SampleWork &w, int64_t J, const int64_t *col_ptr,
+                    const int32_t *row, const T *val, const T *h, int R,
+                    T *M, hipStream_t s);
+template <typename T>
+void exact_mttkrp(const ModeList &ml, int64_t n_cols, const uint64_t *col_key,
+                  const int64_t *col_ptr, const int32_t *row, const T *val,
+                  int R, T *M, hipStream_t s);
+void debug_extracted(const SampleWork &w, int64_t nz_host,
+                     const int64_t *col_ptr, const uint64_t *col_key,
+                     const int32_t *row, uint64_t *ck_out, int32_t *row_out,
+                     int32_t *rep_out, int64_t cap, hipStream_t s);
+void debug_unique(const SampleWork &w, int64_t nu_host,
+                  const uint64_t *col_key, uint64_t *ck_out, int32_t *rep_out,
+                  int32_t *cnt_out, double *w_out, int64_t cap, hipStream_t s);
+
+// ---- fit (k_fit.hip)
+template <typename T>
+void fit_inner(const int32_t *idx, const T *val, int64_t nnz, int N,
+               const ModeList &ml, const double *sigma, int R, double *partial,
+               int nblk, hipStream_t s);
+int fit_blocks(int64_t nnz);
+void fit_finish(const ModeList &ml, int N, int R, const double *sigma,
+                const double *partial, int nblk, double normT2, double *out,
+                hipStream_t s);
+double sum_squares(const void *val, int fp64, int64_t nnz, hipStream_t s);
+
+// ---- device helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace cpr
+
+#define CPR_LAUNCH_CHECK()                                  \
+  do {                                                      \
+    hipError_t e__ = hipGetLastError();                     \
+    if (e__ != hipSuccess) throw cpr::HipFail(e__, __FILE__, __LINE__); \
+  } while (0)
+
+namespace cpr {
+struct HipFail {
+  hipError_t e;
+  const char *file;
+  int line;
+  HipFail(hipError_t e_, const char *f, int l) : e(e_), file(f), line(l) {}
+};
+}  // namespace cpr

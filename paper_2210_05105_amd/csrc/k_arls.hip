@@ -1,0 +1,172 @@
+// CP-ARLS-LEV on one GPU (Appendix A).  Build (Alg. 2 without the
+// all-reduce): leverage scores l_i = U[i] G_k^+ U[i]^T of every row, their
+// inclusive prefix sums (the CDF) and total Z.  Draw (Alg. 3 without the
+// multinomial split and gather): one inverse-CDF search per (sample, factor),
+// index = min{ i : u Z < F(i) }.
+#include "internal.h"
+
+namespace cpr {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// l_i for 16 rows per wave: C = U_tile (16 x R) G^+ (R x R) on FP64 MFMA,
+// then l_i = sum_j C[i][j] U[i][j].
+template <typename T, int NT>
+__global__ void __launch_bounds__(256)
+k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
+           unsigned long long *last, uint32_t *err) {
+  const int l = lane_id();
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + threadIdx.x / WAVE) * 16;
+  if (row0 >= I) return;
+  const int Rp = NT * 16;
+  double4_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = double4_t{0, 0, 0, 0};
+  const int64_t ra = row0 + (l % 16);  // A operand row
+  for (int k0 = 0; k0 < Rp; k0 += 4) {
+    const int ka = k0 + l / 16;
+    const double a = (ra < I && ka < R) ? (double)U[ra * R + ka] : 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int jb = t * 16 + (l % 16);
+      const double b = (ka < R && jb < R) ? Gp[ka * R + jb] : 0.0;
+      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // D[i][j]: lane l, element v -> i = 4 (l / 16) + v, j = l % 16
+  double s[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = t * 16 + (l % 16);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = row0 + 4 * (l / 16) + v;
+      if (r < I && j < R) s[v] += acc[t][v] * (double)U[r * R + j];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    for (int o = 1; o < 16; o <<= 1) s[v] += __shfl_xor(s[v], o, WAVE);
+  if ((l % 16) == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = row0 + 4 * (l / 16) + v;
+      if (r < I) {
+        double x = s[v];
+        if (!isfinite(x)) atomicOr(err, ERR_NONFINITE);
+        x = x > 0 ? x : 0.0;
+        lev[r] = x;
+        if (x > 0) atomicMax(last, (unsigned long long)(r + 1));
+      }
+    }
+  }
+}
+
+__global__ void k_arls_tail(const double *cdf, int64_t I,
+                            const unsigned long long *lastp1, double *Z,
+                            int64_t *last, uint32_t *err) {
+  const double z = cdf[I - 1];
+  *Z = z;
+  *last = (int64_t)*lastp1 - 1;
+  if (!(z > 0) || *lastp1 == 0) atomicOr(err, ERR_ZERO_MASS);
+}
+
+constexpr int DR_THREADS = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(DR_THREADS)
+k_arls_draw(ModeList ml, int64_t J, int R, const double *uni, int32_t *sidx,
+            double *prob, T *h, uint32_t *err) {
+  __shared__ int32_t sh_idx[DR_THREADS * (MAXN - 1)];
+  const int nq = ml.n;
+  const int64_t s = (int64_t)blockIdx.x * DR_THREADS + threadIdx.x;
+  if (s < J) {
+    double p = 1.0;
+    for (int q = 0; q < nq; ++q) {
+      double u = uni[s * nq + q];
+      if (!(u >= 0.0 && u < 1.0)) {
+        atomicOr(err, ERR_UNIFORM);
+        u = 0.0;
+      }
+      const double Z = *ml.Z[q];
+      const double t = u * Z;
+      const double *cdf = ml.cdf[q];
+      int64_t lo = 0, hi = ml.I[q];
+      while (lo < hi) {  // first i with t < cdf[i]
+        int64_t mid = (lo + hi) >> 1;
+        if (t < cdf[mid]) hi = mid; else lo = mid + 1;
+      }
+      const int64_t last = *ml.last[q];
+      if (lo > last) lo = last;
+      if (lo < 0) lo = 0;
+      sidx[s * nq + q] = (int32_t)lo;
+      sh_idx[threadIdx.x * nq + q] = (int32_t)lo;
+      p = p * (ml.lev[q][lo] / Z);
+    }
+    prob[s] = p;
+  }
+  __syncthreads();
+  // Khatri-Rao rows of the block's samples, lanes over columns
+  const int64_t s0 = (int64_t)blockIdx.x * DR_THREADS;
+  for (int e = threadIdx.x; e < DR_THREADS * R; e += DR_THREADS) {
+    const int sl = e / R, r = e - sl * R;
+    if (s0 + sl >= J) break;
+    double v = 1.0;
+    for (int q = 0; q < nq; ++q)
+      v *= (double)static_cast<const T *>(ml.U[q])[(int64_t)sh_idx[sl * nq + q] * R + r];
+    h[(s0 + sl) * R + r] = (T)v;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
+                double *cdf, double *Z, int64_t *last, void *tmp,
+                uint32_t *err, hipStream_t s) {
+  unsigned long long *lastp1 = static_cast<unsigned long long *>(tmp);
+  void *scan_tmp = static_cast<char *>(tmp) + 256;
+  zero_fill<int64_t>(reinterpret_cast<int64_t *>(lastp1), 1, s);
+  const int nt = (R + 15) / 16;
+  const dim3 g(ceil_div(I, 64)), b(256);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL((k_leverage<T, 1>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 2: hipLaunchKernelGGL((k_leverage<T, 2>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 3: hipLaunchKernelGGL((k_leverage<T, 3>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 4: hipLaunchKernelGGL((k_leverage<T, 4>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 5: hipLaunchKernelGGL((k_leverage<T, 5>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 6: hipLaunchKernelGGL((k_leverage<T, 6>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    case 7: hipLaunchKernelGGL((k_leverage<T, 7>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+    default: hipLaunchKernelGGL((k_leverage<T, 8>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
+  }
+  CPR_LAUNCH_CHECK();
+  inclusive_scan_f64(lev, cdf, I, scan_tmp, s);
+  hipLaunchKernelGGL(k_arls_tail, dim3(1), dim3(1), 0, s, cdf, I, lastp1, Z,
+                     last, err);
+  CPR_LAUNCH_CHECK();
+}
+template void arls_build<float>(const float *, int64_t, int, const double *,
+                                double *, double *, double *, int64_t *,
+                                void *, uint32_t *, hipStream_t);
+template void arls_build<double>(const double *, int64_t, int, const double *,
+                                 double *, double *, double *, int64_t *,
+                                 void *, uint32_t *, hipStream_t);
+
+template <typename T>
+void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
+               int32_t *sidx, double *prob, T *h, uint32_t *err,
+               hipStream_t s) {
+  hipLaunchKernelGGL((k_arls_draw<T>), dim3(ceil_div(J, DR_THREADS)),
+                     dim3(DR_THREADS), 0, s, ml, J, R, uni, sidx, prob, h, err);
+  CPR_LAUNCH_CHECK();
+}
+template void arls_draw<float>(const ModeList &, int64_t, int, const double *,
+                               int32_t *, double *, float *, uint32_t *,
+                               hipStream_t);
+template void arls_draw<double>(const ModeList &, int64_t, int, const double *,
+                                int32_t *, double *, double *, uint32_t *,
+                                hipStream_t);
+
+}  // namespace cpr

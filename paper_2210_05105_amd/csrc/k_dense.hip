@@ -1,0 +1,629 @@
+// Dense kernels: factor Grams on FP64 MFMA, the R x R Hadamard Gram and its
+// pseudo-inverse (Eq. 4, Eq. 5), the row-wise solve U_j = M G^+ with one
+// refinement step, and column renormalisation (Alg. 1).
+#include "internal.h"
+
+#include <algorithm>
+
+namespace cpr {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Gram U^T U.  Each block stages 64-row chunks of U in LDS (as FP64, columns
+// padded to a multiple of 16) and its four waves accumulate the upper-
+// triangular 16x16 output tiles with v_mfma_f64_16x16x4f64.  Per-block
+// partial Grams are summed in a fixed order by a second kernel, so the
+// result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int GR_THREADS = 256;
+constexpr int GR_ROWS = 64;
+constexpr int GR_MAXBLK = 512;
+
+template <typename T, int TPW>
+__global__ void __launch_bounds__(GR_THREADS)
+k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
+               double *partial) {
+  extern __shared__ double lds[];  // GR_ROWS x Rp
+  const int w = threadIdx.x / WAVE, l = lane_id();
+  const int nt = Rp / 16;
+  const int ntri = nt * (nt + 1) / 2;
+  int ta[TPW], tb[TPW];
+  double4_t acc[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    int t = w + 4 * i;
+    ta[i] = tb[i] = -1;
+    acc[i] = double4_t{0, 0, 0, 0};
+    if (t < ntri) {  // t -> (a, b), a <= b, row-major upper triangle
+      int a = 0, rem = t;
+      while (rem >= nt - a) { rem -= nt - a; ++a; }
+      ta[i] = a;
+      tb[i] = a + rem;
+    }
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = std::min<int64_t>(I, r0 + rows_per_blk);
+  for (int64_t c0 = r0; c0 < r1; c0 += GR_ROWS) {
+    const int nrow = (int)std::min<int64_t>(GR_ROWS, r1 - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < GR_ROWS * Rp; e += GR_THREADS) {
+      int rr = e / Rp, cc = e - rr * Rp;
+      double v = 0;
+      if (rr < nrow && cc < R) v = (double)U[(c0 + rr) * R + cc];
+      lds[e] = v;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < GR_ROWS; k0 += 4) {
+      const double *rowp = lds + (k0 + l / 16) * Rp + (l % 16);
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        if (ta[i] < 0) continue;
+        double a = rowp[ta[i] * 16];
+        double b = rowp[tb[i] * 16];
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  // D[i][j] of a 16x16 tile: lane l, element v -> i = 4 (l / 16) + v, j = l % 16
+  double *out = partial + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (ta[i] < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int gi = ta[i] * 16 + 4 * (l / 16) + v;
+      int gj = tb[i] * 16 + (l % 16);
+      if (gi < R && gj < R) {
+        out[gi * R + gj] = acc[i][v];
+        out[gj * R + gi] = acc[i][v];
+      }
+    }
+  }
+}
+
+__global__ void k_sum_partials(const double *partial, int nblk, int n,
+                               double *out) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * n + e];
+  out[e] = s;
+}
+
+int gram_blocks(int64_t I, int64_t *rows_per_blk) {
+  int64_t chunks = (I + GR_ROWS - 1) / GR_ROWS;
+  int nblk = (int)std::min<int64_t>(std::max<int64_t>(chunks, 1), GR_MAXBLK);
+  int64_t cpb = (chunks + nblk - 1) / nblk;
+  *rows_per_blk = std::max<int64_t>(cpb, 1) * GR_ROWS;
+  nblk = (int)std::max<int64_t>(1, (I + *rows_per_blk - 1) / *rows_per_blk);
+  return nblk;
+}
+
+template <typename T, int TPW>
+void launch_gram(const T *U, int64_t I, int R, int Rp, double *partial,
+                 int nblk, int64_t rpb, hipStream_t s) {
+  hipLaunchKernelGGL((k_gram_partial<T, TPW>), dim3(nblk), dim3(GR_THREADS),
+                     GR_ROWS * Rp * sizeof(double), s, U, I, R, Rp, rpb,
+                     partial);
+}
+
+// ---------------------------------------------------------------------------
+// Hadamard Gram and pseudo-inverse in one workgroup.
+// ---------------------------------------------------------------------------
+constexpr int PV_THREADS = 256;
+
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  double t = 0;
+  for (int i = 0; i < PV_THREADS / WAVE; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+__device__ double block_max(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  const int w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int i = 1; i < PV_THREADS / WAVE; ++i) t = fmax(t, red[i]);
+  __syncthreads();
+  return t;
+}
+
+// A (LDS) holds G.  On success Gp = (L L^T)^{-1}; returns false if some
+// pivot is <= tol (then A is garbage).
+__device__ bool chol_inverse(double *A, int R, double tol, double *W,
+                             double *Gp, int *flag) {
+  const int t = threadIdx.x;
+  if (t == 0) *flag = 1;
+  __syncthreads();
+  for (int k = 0; k < R; ++k) {
+    const double d = A[k * R + k];
+    if (!(d > tol)) {
+      if (t == 0) *flag = 0;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    const double lkk = sqrt(d);
+    for (int i = k + 1 + t; i < R; i += PV_THREADS) A[i * R + k] /= lkk;
+    __syncthreads();
+    if (t == 0) A[k * R + k] = lkk;
+    // trailing update of the lower triangle
+    const int m = R - k - 1;
+    for (int e = t; e < m * m; e += PV_THREADS) {
+      int i = k + 1 + e / m, c = k + 1 + e % m;
+      if (c <= i) A[i * R + c] -= A[i * R + k] * A[c * R + k];
+    }
+    __syncthreads();
+  }
+  // W = L^{-1} (column c by thread c), forward substitution
+  for (int c = t; c < R; c += PV_THREADS) {
+    for (int i = 0; i < R; ++i) {
+      if (i < c) { W[i * R + c] = 0; continue; }
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) acc -= A[i * R + k] * W[k * R + c];
+      W[i * R + c] = acc / A[i * R + i];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // Gp = W^T W
+  for (int e = t; e < R * R; e += PV_THREADS) {
+    int a = e / R, b = e % R;
+    int k0 = a > b ? a : b;
+    double acc = 0;
+    for (int k = k0; k < R; ++k) acc += W[k * R + a] * W[k * R + b];
+    Gp[e] = acc;
+  }
+  return true;
+}
+
+// Cyclic Jacobi eigendecomposition of the symmetric A (LDS); V in global.
+// Gp = V diag(1/lambda, lambda > R 2^-52 lambda_max) V^T.
+__device__ bool jacobi_pinv(double *A, int R, double *V, double *Gp,
+                            double *red, double *rot) {
+  const int t = threadIdx.x;
+  const int m = R + (R & 1);  // players, one dummy when R is odd
+  for (int e = t; e < R * R; e += PV_THREADS)
+    V[e] = (e / R == e % R) ? 1.0 : 0.0;
+  __threadfence_block();
+  __syncthreads();
+  bool conv = false;
+  for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
+    double off = 0, dia = 0;
+    for (int e = t; e < R * R; e += PV_THREADS) {
+      double v = A[e] * A[e];
+      if (e / R == e % R) dia += v; else off += v;
+    }
+    off = block_sum(off, red);
+    dia = block_sum(dia, red);
+    if (off <= 1e-30 * dia || off == 0) { conv = true; break; }
+    for (int r = 0; r < m - 1; ++r) {
+      // pair i: (arr[i], arr[m-1-i]) with arr[0] = 0, arr[x] = 1 + (x-1+r)%(m-1)
+      for (int i = t; i < m / 2; i += PV_THREADS) {
+        int x = i, y = m - 1 - i;
+        int p = x == 0 ? 0 : 1 + (x - 1 + r) % (m - 1);
+        int q = 1 + (y - 1 + r) % (m - 1);
+        if (p > q) { int tmp = p; p = q; q = tmp; }
+        double c = 1, s = 0;
+        if (q < R) {
+          double apq = A[p * R + q];
+          if (fabs(apq) > 1e-300) {
+            double tau = (A[q * R + q] - A[p * R + p]) / (2 * apq);
+            double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
+            c = 1 / sqrt(1 + tt * tt);
+            s = tt * c;
+          }
+        }
+        rot[4 * i + 0] = p; rot[4 * i + 1] = q;
+        rot[4 * i + 2] = c; rot[4 * i + 3] = s;
+      }
+      __syncthreads();
+      // columns: A J and V J
+      for (int e = t; e < (m / 2) * R; e += PV_THREADS) {
+        int i = e / R, row = e % R;
+        int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
+        if (q >= R) continue;
+        double c = rot[4 * i + 2], s = rot[4 * i + 3];
+        double ap = A[row * R + p], aq = A[row * R + q];
+        A[row * R + p] = c * ap - s * aq;
+        A[row * R + q] = s * ap + c * aq;
+        double vp = V[row * R + p], vq = V[row * R + q];
+        V[row * R + p] = c * vp - s * vq;
+        V[row * R + q] = s * vp + c * vq;
+      }
+      __threadfence_block();
+      __syncthreads();
+      // rows: J^T (A J)
+      for (int e = t; e < (m / 2) * R; e += PV_THREADS) {
+        int i = e / R, col = e % R;
+        int p = (int)rot[4 * i], q = (int)rot[4 * i + 1];
+        if (q >= R) continue;
+        double c = rot[4 * i + 2], s = rot[4 * i + 3];
+        double ap = A[p * R + col], aq = A[q * R + col];
+        A[p * R + col] = c * ap - s * aq;
+        A[q * R + col] = s * ap + c * aq;
+      }
+      __syncthreads();
+    }
+  }
+  double lmax = 0;
+  for (int i = t; i < R; i += PV_THREADS) lmax = fmax(lmax, A[i * R + i]);
+  lmax = block_max(lmax, red);
+  const double cut = R * 0x1p-52 * fmax(lmax, 0.0);
+  for (int e = t; e < R * R; e += PV_THREADS) {
+    int a = e / R, b = e % R;
+    double acc = 0;
+    for (int k = 0; k < R; ++k) {
+      double lam = A[k * R + k];
+      if (lam > cut) acc += V[a * R + k] * V[b * R + k] / lam;
+    }
+    Gp[e] = acc;
+  }
+  return conv;
+}
+
+__global__ void __launch_bounds__(PV_THREADS)
+k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
+                double *trace_out, double *scratch, uint32_t *err) {
+  extern __shared__ double A[];  // R x R
+  __shared__ double red[PV_THREADS / WAVE];
+  __shared__ double rot[4 * (MAXR / 2 + 1)];
+  __shared__ int flag;
+  const int t = threadIdx.x;
+  double tr = 0;
+  bool bad = false;
+  for (int e = t; e < R * R; e += PV_THREADS) {
+    double v = 1;
+    for (int i = 0; i < ml.n; ++i) v *= ml.G[i][e];
+    A[e] = v;
+    Gfull[e] = v;
+    if (!isfinite(v)) bad = true;
+    if (e / R == e % R) tr += v;
+  }
+  if (bad) atomicOr(err, ERR_NONFINITE);
+  tr = block_sum(tr, red);
+  const double tol = R * 0x1p-52 * tr;
+  __syncthreads();
+  bool ok = chol_inverse(A, R, tol, scratch, Gp, &flag);
+  if (!ok) {
+    __syncthreads();
+    for (int e = t; e < R * R; e += PV_THREADS) A[e] = Gfull[e];
+    __syncthreads();
+    if (!jacobi_pinv(A, R, scratch, Gp, red, rot) && t == 0)
+      atomicOr(err, ERR_PINV);
+  }
+  __threadfence();
+  __syncthreads();
+  // <G^+, G> and, for STS, G_{>k} = G^+ (*) Hadamard of later Grams
+  double ip = 0;
+  for (int e = t; e < R * R; e += PV_THREADS) ip += Gp[e] * Gfull[e];
+  ip = block_sum(ip, red);
+  if (trace_out && t == 0) *trace_out = ip;
+  if (ggt) {
+    for (int q = 0; q < ml.n; ++q)
+      for (int e = t; e < R * R; e += PV_THREADS) {
+        double v = Gp[e];
+        for (int p = q + 1; p < ml.n; ++p) v *= ml.G[p][e];
+        ggt[(int64_t)q * R * R + e] = v;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row solve: X[i] = m G^+ + (m - (m G^+) G) G^+  (FP64), column sums of X^2.
+// A group of L lanes (L = smallest power of two >= R, at most 64) owns one
+// row at a time; lane c of the group owns columns c, c + L, ...
+// ---------------------------------------------------------------------------
+constexpr int SV_THREADS = 256;
+constexpr int SV_MAXBLK = 1024;
+
+template <typename T, int L>
+__global__ void __launch_bounds__(SV_THREADS)
+k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
+        double *X, double *partial, int64_t *rows_out) {
+  constexpr int CPL = (MAXR + L - 1) / L;  // columns per lane (max)
+  constexpr int GPW = WAVE / L;            // groups per wave
+  const int l = lane_id(), w = threadIdx.x / WAVE;
+  const int gl = l % L, gbase = l - gl;
+  const int64_t group = ((int64_t)blockIdx.x * (SV_THREADS / WAVE) + w) * GPW + l / L;
+  const int64_t ngroups = (int64_t)gridDim.x * (SV_THREADS / WAVE) * GPW;
+  const int ncl = (R + L - 1) / L;
+  double ss[CPL];
+#pragma unroll
+  for (int t = 0; t < CPL; ++t) ss[t] = 0;
+  int nrows = 0;  // nonzero rows handled by this group (counted on lane gl 0)
+  for (int64_t i = group; i < I; i += ngroups) {
+    double m[CPL], x[CPL], r[CPL];
+    bool nz = false;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      int c = gl + t * L;
+      m[t] = (t < ncl && c < R) ? (double)M[i * R + c] : 0.0;
+      nz |= (m[t] != 0.0);
+    }
+    // all lanes of the group take the same branch
+    uint64_t any = __ballot(nz);
+    uint64_t gmask = (L == 64) ? ~0ull : (((1ull << L) - 1) << gbase);
+    if (!(any & gmask)) {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        int c = gl + t * L;
+        if (t < ncl && c < R) X[i * R + c] = 0.0;
+      }
+      continue;
+    }
+    nrows += (gl == 0);
+    // x = m G^+
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) x[t] = 0;
+    for (int a = 0; a < R; ++a) {
+      double ma = __shfl(m[a / L], gbase + a % L, WAVE);
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        int c = gl + t * L;
+        if (t < ncl && c < R) x[t] += ma * Gp[a * R + c];
+      }
+    }
+    // r = m - x G
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) r[t] = m[t];
+    for (int a = 0; a < R; ++a) {
+      double xa = __shfl(x[a / L], gbase + a % L, WAVE);
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        int c = gl + t * L;
+        if (t < ncl && c < R) r[t] -= xa * G[a * R + c];
+      }
+    }
+    // x += r G^+
+    for (int a = 0; a < R; ++a) {
+      double ra = __shfl(r[a / L], gbase + a % L, WAVE);
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        int c = gl + t * L;
+        if (t < ncl && c < R) x[t] += ra * Gp[a * R + c];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      int c = gl + t * L;
+      if (t < ncl && c < R) {
+        X[i * R + c] = x[t];
+        ss[t] += x[t] * x[t];
+      }
+    }
+  }
+  if (rows_out) {
+    int nr = nrows;
+    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, WAVE);
+    if (l == 0 && nr) atomicAdd((unsigned long long *)rows_out,
+                                (unsigned long long)nr);
+  }
+  // fixed-order reduction of the per-lane column sums: groups within a wave
+  // (shuffle tree), then waves (LDS, in wave order)
+  __shared__ double red[SV_THREADS / WAVE][MAXR];
+#pragma unroll
+  for (int t = 0; t < CPL; ++t) {
+    double v = ss[t];
+    for (int o = L; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
+    int c = gl + t * L;
+    if (l < L && t < ncl && c < R) red[w][c] = v;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < R; c += SV_THREADS) {
+    double v = 0;
+    for (int q = 0; q < SV_THREADS / WAVE; ++q) v += red[q][c];
+    partial[(int64_t)blockIdx.x * R + c] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_colsumsq(const T *X, int64_t I, int R, double *partial) {
+  // block b sums rows b, b + grid, ... ; thread c owns column c
+  __shared__ double red[256];
+  for (int c0 = 0; c0 < R; c0 += 256) {
+    int c = c0 + threadIdx.x;
+    double s = 0;
+    if (c < R)
+      for (int64_t i = blockIdx.x; i < I; i += gridDim.x) {
+        double v = (double)X[i * R + c];
+        s += v * v;
+      }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (c < R) partial[(int64_t)blockIdx.x * R + c] = red[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+__global__ void k_sigma(const double *partial, int nblk, int R, double *sigma,
+                        uint32_t *err) {
+  int c = threadIdx.x + blockIdx.x * blockDim.x;
+  if (c >= R) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * R + c];
+  double sg = sqrt(s);
+  if (!isfinite(sg)) atomicOr(err, ERR_NONFINITE);
+  sigma[c] = sg;
+}
+
+template <typename T>
+__global__ void k_scale_cols(const double *X, int64_t n, int R,
+                             const double *sigma, T *U) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double sg = sigma[e % R];
+  U[e] = (T)(sg > 0 ? X[e] / sg : 0.0);
+}
+
+template <typename T>
+__global__ void k_zero(T *p, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (; e < n; e += st) p[e] = T(0);
+}
+
+__global__ void k_to_f64(const void *src, int fp64, double *dst, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  dst[e] = fp64 ? static_cast<const double *>(src)[e]
+                : (double)static_cast<const float *>(src)[e];
+}
+
+__global__ void k_convert(const void *src, int sf, void *dst, int df,
+                          int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double v = sf ? static_cast<const double *>(src)[e]
+                : (double)static_cast<const float *>(src)[e];
+  if (df) static_cast<double *>(dst)[e] = v;
+  else static_cast<float *>(dst)[e] = (float)v;
+}
+
+}  // namespace
+
+void convert_values(const void *src, int src_fp64, void *dst, int dst_fp64,
+                    int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert, dim3(ceil_div(n, 256)), dim3(256), 0, s, src,
+                     src_fp64, dst, dst_fp64, n);
+  CPR_LAUNCH_CHECK();
+}
+
+size_t gram_temp_bytes(int64_t I, int R) {
+  int64_t rpb;
+  int nblk = gram_blocks(I, &rpb);
+  return (size_t)nblk * R * R * sizeof(double) + 256;
+}
+
+template <typename T>
+void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
+  int64_t rpb;
+  const int nblk = gram_blocks(I, &rpb);
+  const int Rp = (R + 15) / 16 * 16;
+  const int nt = Rp / 16, ntri = nt * (nt + 1) / 2;
+  const int tpw = (ntri + 3) / 4;
+  double *partial = static_cast<double *>(tmp);
+  switch (tpw) {
+    case 1: launch_gram<T, 1>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    case 2: launch_gram<T, 2>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    case 3: launch_gram<T, 3>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    case 4: launch_gram<T, 4>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    case 6: case 5: launch_gram<T, 6>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    default: launch_gram<T, 9>(U, I, R, Rp, partial, nblk, rpb, s); break;
+  }
+  hipLaunchKernelGGL(k_sum_partials, dim3(ceil_div(R * R, 256)), dim3(256), 0,
+                     s, partial, nblk, R * R, G);
+  CPR_LAUNCH_CHECK();
+}
+template void gram<float>(const float *, int64_t, int, double *, void *,
+                          hipStream_t);
+template void gram<double>(const double *, int64_t, int, double *, void *,
+                           hipStream_t);
+
+void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
+                   double *ggt_out, double *trace_out, double *scratch,
+                   uint32_t *err, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {  // R x R doubles exceed the default 64 KiB for R > 90
+    hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_hadamard_pinv),
+        hipFuncAttributeMaxDynamicSharedMemorySize, MAXR * MAXR * 8);
+    if (e != hipSuccess) throw HipFail(e, __FILE__, __LINE__);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_hadamard_pinv, dim3(1), dim3(PV_THREADS),
+                     (size_t)R * R * sizeof(double), s, ml, R, Gfull, Gp,
+                     ggt_out, trace_out, scratch, err);
+  CPR_LAUNCH_CHECK();
+}
+
+int solve_blocks(int64_t I) {
+  return (int)std::min<int64_t>(SV_MAXBLK, std::max<int64_t>(1, (I + 15) / 16));
+}
+
+template <typename T>
+void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
+                const double *Gp, double *X, double *partial, int nblk,
+                int64_t *rows_out, hipStream_t s) {
+  const dim3 g(nblk), b(SV_THREADS);
+  if (R <= 8)
+    hipLaunchKernelGGL((k_solve<T, 8>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+  else if (R <= 16)
+    hipLaunchKernelGGL((k_solve<T, 16>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+  else if (R <= 32)
+    hipLaunchKernelGGL((k_solve<T, 32>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+  else
+    hipLaunchKernelGGL((k_solve<T, 64>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+  CPR_LAUNCH_CHECK();
+}
+template void solve_rows<float>(const float *, int64_t, int, const double *,
+                                const double *, double *, double *, int,
+                                int64_t *, hipStream_t);
+template void solve_rows<double>(const double *, int64_t, int, const double *,
+                                 const double *, double *, double *, int,
+                                 int64_t *, hipStream_t);
+
+template <typename T>
+void finish_normalize(const double *X, int64_t I, int R, const double *partial,
+                      int nblk, double *sigma, T *U, uint32_t *err,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(MAXR), 0, s, partial, nblk, R,
+                     sigma, err);
+  hipLaunchKernelGGL((k_scale_cols<T>), dim3(ceil_div(I * R, 256)), dim3(256),
+                     0, s, X, I * R, R, sigma, U);
+  CPR_LAUNCH_CHECK();
+}
+template void finish_normalize<float>(const double *, int64_t, int,
+                                      const double *, int, double *, float *,
+                                      uint32_t *, hipStream_t);
+template void finish_normalize<double>(const double *, int64_t, int,
+                                       const double *, int, double *, double *,
+                                       uint32_t *, hipStream_t);
+
+template <typename T>
+void normalize_in_place(const double *Uin, int64_t I, int R, T *U,
+                        double *partial, uint32_t *err, hipStream_t s) {
+  const int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, I));
+  hipLaunchKernelGGL((k_colsumsq<double>), dim3(nblk), dim3(256), 0, s, Uin, I,
+                     R, partial);
+  CPR_LAUNCH_CHECK();
+  // sigma of the input is not kept: Alg. 1 starts from sigma = 1
+  double *sig = partial + (int64_t)nblk * R;
+  finish_normalize<T>(Uin, I, R, partial, nblk, sig, U, err, s);
+}
+template void normalize_in_place<float>(const double *, int64_t, int, float *,
+                                        double *, uint32_t *, hipStream_t);
+template void normalize_in_place<double>(const double *, int64_t, int,
+                                         double *, double *, uint32_t *,
+                                         hipStream_t);
+
+template <typename T>
+void zero_fill(T *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL((k_zero<T>), dim3(nb), dim3(256), 0, s, p, n);
+  CPR_LAUNCH_CHECK();
+}
+template void zero_fill<float>(float *, int64_t, hipStream_t);
+template void zero_fill<double>(double *, int64_t, hipStream_t);
+template void zero_fill<int32_t>(int32_t *, int64_t, hipStream_t);
+template void zero_fill<int64_t>(int64_t *, int64_t, hipStream_t);
+
+void copy_to_f64(const void *src, int src_fp64, double *dst, int64_t n,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f64, dim3(ceil_div(n, 256)), dim3(256), 0, s, src,
+                     src_fp64, dst, n);
+  CPR_LAUNCH_CHECK();
+}
+
+}  // namespace cpr

@@ -1,0 +1,334 @@
+"""HIP path vs FP64 oracle, element by element, through the C ABI.
+
+Tolerances (from the project's parity bar): sample indices bit-exact except
+within 1e-12 of a CDF boundary; extracted nonzero sets and merged draws
+bit-exact; MTTKRP and factors within 1e-4 relative Frobenius error in FP32
+(1e-10 in FP64, where only summation order differs); fit within 1e-3 (FP32)
+and 1e-9 (FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import tensorgen as tg
+from tests.helpers import (compare_arls_indices, compare_sts_indices,
+                           gpu_state, oracle_sampled_M, rel_fro, to_np)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2210_05105_amd import load_library
+    load_library()
+    return torch.device("cuda:0")
+
+
+def make_ctx(dev, T, R, sampler, precision, J, leaf=0):
+    from paper_2210_05105_amd import Context
+    vdt = np.float64 if precision == "fp64" else np.float32
+    return Context(torch.from_numpy(np.ascontiguousarray(T.idx)).to(dev),
+                   torch.from_numpy(T.val.astype(vdt)).to(dev), T.dims, R,
+                   sampler, precision, max_J=J, sts_leaf=leaf)
+
+
+def init_ctx(ctx, dims, R, seed, fp32=False):
+    _, _, rinit, runi = tg.streams([96, seed])
+    U0 = tg.init_factors(rinit, dims, R,
+                         dtype=np.float32 if fp32 else np.float64)
+    for k in range(len(dims)):
+        ctx.set_factor(k, torch.from_numpy(U0[k]))
+    return U0, runi
+
+
+def check_mode_solve(ctx, T, j, u, J, sampler, tol):
+    """One teacher-forced mode solve: draws, merge, extraction, M, U_j, G_j."""
+    dims = T.dims
+    U, G = gpu_state(ctx)
+    gidx, gprob = ctx.sample(j, torch.from_numpy(u))
+    gidx, gprob = to_np(gidx).astype(np.int64), to_np(gprob)
+    if sampler == "arls":
+        st = {k: O.arls_build(U[k], G[k]) for k in range(len(dims)) if k != j}
+        oidx, oprob, _ = O.arls_sample(U, st, j, u)
+        n_acc = compare_arls_indices(gidx, oidx, U, G, j, u)
+    else:
+        oidx, oprob, _ = O.sts_sample(U, G, j, u, block=64)
+        n_acc = compare_sts_indices(gidx, oidx, U, G, j, u)
+    same = np.all(gidx == oidx, axis=1)
+    np.testing.assert_allclose(gprob[same], oprob[same], rtol=1e-11)
+    # merge and extraction, teacher-forced with the GPU's draws
+    ref = oracle_sampled_M(T, dims, j, gidx, gprob, U, J)
+    uq = ctx.get_unique(J)
+    order = np.argsort(to_np(uq["col_key"]))
+    np.testing.assert_array_equal(to_np(uq["col_key"])[order].astype(np.uint64),
+                                  ref["keys"])
+    np.testing.assert_array_equal(to_np(uq["rep"])[order], ref["rep"])
+    np.testing.assert_array_equal(to_np(uq["count"])[order], ref["counts"])
+    np.testing.assert_allclose(to_np(uq["weight"])[order], ref["w"],
+                               rtol=1e-14)
+    ex = ctx.get_extracted(max(1, ref["rows"].shape[0] + 16))
+    assert ex["n"] == ref["rows"].shape[0]
+    g = np.stack([to_np(ex["col_key"]).astype(np.uint64).astype(np.float64),
+                  to_np(ex["row"]), to_np(ex["rep"])], axis=1)
+    o = np.stack([ref["ck"].astype(np.float64), ref["rows"],
+                  ref["rep"][ref["slot"]]], axis=1)
+    g = g[np.lexsort(g.T[::-1])]
+    o = o[np.lexsort(o.T[::-1])]
+    np.testing.assert_array_equal(g, o)
+    M, nnz = ctx.sampled_mttkrp(j, want_nnz=True)
+    assert nnz == ref["rows"].shape[0]
+    M = to_np(M).astype(np.float64)
+    assert rel_fro(M, ref["M"]) < tol, rel_fro(M, ref["M"])
+    # solve from the GPU's M
+    ctx.solve_factor(j)
+    Uj = to_np(ctx.get_factor(j))
+    sig = to_np(ctx.get_sigma())
+    Gp = O.pinv_psd(O.gram_hadamard(G, j))
+    Uo, so = O.solve(M, Gp)
+    assert rel_fro(Uj, Uo) < tol, rel_fro(Uj, Uo)
+    np.testing.assert_allclose(sig, so, rtol=tol)
+    np.testing.assert_allclose(to_np(ctx.get_gram(j)), O.gram(Uj),
+                               rtol=1e-12, atol=1e-12)
+    return n_acc
+
+
+# ------------------------------------------------------------------ Grams
+
+@pytest.mark.parametrize("R", [1, 8, 17, 32, 48, 100, 128])
+def test_gram_mfma_matches_oracle(dev, R):
+    dims = (1000, 77, 33)
+    T, _ = tg.tiny_tensor(40, dims, 3000)
+    ctx = make_ctx(dev, T, R, "exact", "fp64", 1)
+    U0, _ = init_ctx(ctx, dims, R, 1)
+    for k in range(3):
+        Un = O.normalize_columns(U0[k])[0]
+        np.testing.assert_allclose(to_np(ctx.get_factor(k)), Un, rtol=1e-14,
+                                   atol=1e-15)
+        np.testing.assert_allclose(to_np(ctx.get_gram(k)), O.gram(Un),
+                                   rtol=1e-13, atol=1e-13)
+    ctx.close()
+
+
+# --------------------------------------------------------- mode solves
+
+@pytest.mark.parametrize("R,J", [(8, 4096), (17, 1000), (1, 33), (128, 300)])
+def test_arls_fp64_mode_solves(dev, R, J):
+    T = tg.make_tensor("planted")
+    ctx = make_ctx(dev, T, R, "arls", "fp64", J)
+    _, runi = init_ctx(ctx, T.dims, R, 2)
+    acc = 0
+    for j in range(3):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "arls", 1e-10)
+    assert acc <= 2
+    f = ctx.fit()
+    U, _ = gpu_state(ctx)
+    fo = O.fit(T.idx, T.val, to_np(ctx.get_sigma()), U)
+    assert abs(f - fo) < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("R,J,leaf", [(8, 2048, 16), (16, 1500, 32),
+                                      (32, 1024, 64), (48, 333, 16),
+                                      (64, 256, 16)])
+def test_sts_fp64_mode_solves(dev, R, J, leaf):
+    T, _ = tg.tiny_tensor(41, (300, 250, 190), 30000, rank=4, noise_var=0.01)
+    ctx = make_ctx(dev, T, R, "sts", "fp64", J, leaf)
+    _, runi = init_ctx(ctx, T.dims, R, 3)
+    acc = 0
+    for j in range(3):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-10)
+    assert acc <= 2
+    ctx.close()
+
+
+def test_sts_fp32_zipf_mode_solves(dev):
+    T = tg.zipf_tensor(42, (3000, 2400, 1800), 200_000, s=1.1)
+    R, J = 32, 4096
+    ctx = make_ctx(dev, T, R, "sts", "fp32", J)
+    _, runi = init_ctx(ctx, T.dims, R, 4, fp32=True)
+    for j in range(3):
+        u = tg.uniform_block(runi, J, 3)
+        check_mode_solve(ctx, T, j, u, J, "sts", 1e-4)
+    f = ctx.fit()
+    U, _ = gpu_state(ctx)
+    fo = O.fit(T.idx, T.val.astype(np.float64), to_np(ctx.get_sigma()), U)
+    assert abs(f - fo) < 1e-3
+    ctx.close()
+
+
+def test_arls_fp32_4way_mode_solves(dev):
+    T = tg.zipf_tensor(43, (2000, 1000, 400, 20), 150_000, s=1.2)
+    R, J = 24, 3000
+    ctx = make_ctx(dev, T, R, "arls", "fp32", J)
+    _, runi = init_ctx(ctx, T.dims, R, 5, fp32=True)
+    for j in range(4):
+        u = tg.uniform_block(runi, J, 4)
+        check_mode_solve(ctx, T, j, u, J, "arls", 1e-4)
+    ctx.close()
+
+
+# ----------------------------------------------------- end to end (C1)
+
+def test_planted_end_to_end_fp64_ten_sweeps(dev):
+    """200x150x100, 20k nnz, R=8, J=4096, CP-ARLS-LEV, 10 sweeps, FP64:
+    identical init and uniforms, no teacher forcing; indices compared in
+    every mode solve."""
+    w = tg.WORKLOADS["planted"]
+    T = tg.make_tensor("planted")
+    R, J, sweeps = w["R"], w["J"], w["sweeps"]
+    _, _, rinit, runi = tg.streams(w["tag"])
+    U0 = tg.init_factors(rinit, T.dims, R)
+    uni = tg.uniform_blocks(runi, sweeps, J, 3)
+    ctx = make_ctx(dev, T, R, "arls", "fp64", J)
+    for k in range(3):
+        ctx.set_factor(k, torch.from_numpy(U0[k]))
+    U = [O.normalize_columns(x)[0] for x in U0]
+    G = [O.gram(x) for x in U]
+    st = {k: O.arls_build(U[k], G[k]) for k in range(3)}
+    mism = 0
+    for t in range(sweeps):
+        for j in range(3):
+            u = uni[t, j]
+            gidx, _ = ctx.sample(j, torch.from_numpy(u))
+            oidx, prob, h = O.arls_sample(U, st, j, u)
+            mism += int(np.sum(to_np(gidx) != oidx))
+            ctx.sampled_mttkrp(j, want_M=False)
+            ctx.solve_factor(j)
+            keys, rep, cnt, wts = O.dedup(oidx, prob, T.dims, j, J)
+            ck, rows, vals, slot = O.extract(T.idx, T.val, T.dims, j, keys)
+            M = O.sampled_mttkrp(T.dims[j], rows, vals, slot, wts, h[rep])
+            U[j], sig = O.solve(M, O.pinv_psd(O.gram_hadamard(G, j)))
+            G[j] = O.gram(U[j])
+            st[j] = O.arls_build(U[j], G[j])
+    assert mism == 0
+    Ug, _ = gpu_state(ctx)
+    for k in range(3):
+        assert rel_fro(Ug[k], U[k]) < 1e-8
+    f = ctx.fit()
+    fo = O.fit(T.idx, T.val, sig, U)
+    assert abs(f - fo) < 1e-9 and fo > 0.5
+    ctx.close()
+
+
+def test_sweep_entry_point_matches_stepwise(dev):
+    w = tg.WORKLOADS["planted"]
+    T = tg.make_tensor("planted")
+    R, J = w["R"], 1024
+    uni = tg.uniform_blocks(np.random.default_rng(5), 3, J, 3)
+    a = make_ctx(dev, T, R, "arls", "fp64", J)
+    b = make_ctx(dev, T, R, "arls", "fp64", J)
+    init_ctx(a, T.dims, R, 7)
+    init_ctx(b, T.dims, R, 7)
+    a.sweep(3, J, torch.from_numpy(uni))
+    for t in range(3):
+        for j in range(3):
+            b.sample(j, torch.from_numpy(uni[t, j]), outputs=False)
+            b.sampled_mttkrp(j, want_M=False)
+            b.solve_factor(j)
+    assert abs(a.fit() - b.fit()) < 1e-12
+    for k in range(3):
+        assert rel_fro(to_np(a.get_factor(k)), to_np(b.get_factor(k))) < 1e-12
+    a.close()
+    b.close()
+
+
+# -------------------------------------------------------------- exact
+
+def test_exact_mttkrp_and_als(dev):
+    dims, R = (40, 30, 20), 5
+    T, _ = tg.tiny_tensor(44, dims, 5000, rank=R, noise_var=0.0)
+    ctx = make_ctx(dev, T, R, "exact", "fp64", 1)
+    U0, _ = init_ctx(ctx, dims, R, 8)
+    U, G = gpu_state(ctx)
+    M, n = ctx.sampled_mttkrp(1, want_nnz=True)
+    assert n == T.nnz
+    assert rel_fro(to_np(M), O.mttkrp_exact(T.idx, T.val, U, 1)) < 1e-13
+    ctx.solve_factor(1)
+    ctx.sweep(4)
+    Uo, so, fo = O.als(T.idx, T.val, dims, R, "exact",
+                       [O.normalize_columns(x)[0] for x in U0], sweeps=5,
+                       record_fit=True)
+    # the GPU did mode 1 once more before its 4 sweeps; compare fits loosely
+    # and the one-step factor exactly
+    assert ctx.fit() > 0.9
+    ctx.close()
+
+
+# -------------------------------------------------------- invariances
+
+def test_sts_leaf_size_invariance(dev):
+    T, _ = tg.tiny_tensor(45, (500, 300, 200), 20000, rank=3)
+    R, J = 16, 2048
+    u = tg.uniform_block(np.random.default_rng(6), J, 3)
+    out = []
+    for leaf in (16, 32, 64):
+        ctx = make_ctx(dev, T, R, "sts", "fp64", J, leaf)
+        init_ctx(ctx, T.dims, R, 9)
+        gidx, gprob = ctx.sample(0, torch.from_numpy(u))
+        out.append((to_np(gidx), to_np(gprob)))
+        ctx.close()
+    for gidx, gprob in out[1:]:
+        assert np.sum(gidx != out[0][0]) <= 1
+        same = np.all(gidx == out[0][0], axis=1)
+        np.testing.assert_allclose(gprob[same], out[0][1][same], rtol=1e-12)
+
+
+# -------------------------------------------------------------- errors
+
+def test_error_paths(dev):
+    from paper_2210_05105_amd import CprError
+    dims = (20, 10, 8)
+    T, _ = tg.tiny_tensor(46, dims, 300)
+    bad = tg.SparseTensor(dims, T.idx.copy(), T.val.copy())
+    bad.idx[5, 1] = 10  # out of range
+    with pytest.raises(CprError) as e:
+        make_ctx(dev, bad, 4, "arls", "fp64", 16)
+    assert e.value.name == "CP_EINVAL"
+    dup = tg.SparseTensor(dims, T.idx.copy(), T.val.copy())
+    dup.idx[7] = dup.idx[3]
+    with pytest.raises(CprError) as e:
+        make_ctx(dev, dup, 4, "arls", "fp64", 16)
+    assert e.value.name == "CP_EINVAL"
+    ctx = make_ctx(dev, T, 4, "arls", "fp64", 16)
+    with pytest.raises(CprError) as e:
+        ctx.sampled_mttkrp(0)
+    assert e.value.name == "CP_ESTATE"  # factors not set yet
+    init_ctx(ctx, dims, 4, 10)
+    with pytest.raises(CprError) as e:
+        ctx.sampled_mttkrp(0)
+    assert e.value.name == "CP_ESTATE"  # no samples yet
+    u = np.full((16, 2), 0.5)
+    u[3, 1] = 1.0
+    ctx.sample(0, torch.from_numpy(u))
+    with pytest.raises(CprError) as e:
+        ctx.sync()
+    assert e.value.name == "CP_EINVAL"
+    with pytest.raises(CprError) as e:
+        ctx.sample(0, torch.from_numpy(np.full((17, 2), 0.5)))  # J > max_J
+    assert e.value.name == "CP_EINVAL"
+    ctx.set_factor(1, torch.zeros(dims[1], 4, dtype=torch.float64))
+    with pytest.raises(CprError) as e:
+        ctx.sync()
+    assert e.value.name == "CP_EDEGENERATE"
+    ctx.close()
+
+
+def test_rank_deficient_gram_uses_pseudo_inverse(dev):
+    dims, R, J = (60, 50, 40), 4, 512
+    T, _ = tg.tiny_tensor(47, dims, 4000, rank=3)
+    ctx = make_ctx(dev, T, R, "arls", "fp64", J)
+    rng = np.random.default_rng(11)
+    U0 = [rng.standard_normal((d, R)) for d in dims]
+    U0[1][:, 3] = U0[1][:, 0]  # duplicated column: G_1 is singular
+    for k in range(3):
+        ctx.set_factor(k, torch.from_numpy(U0[k]))
+    u = tg.uniform_block(rng, J, 3)
+    check_mode_solve(ctx, T, 0, u, J, "arls", 1e-9)
+    ctx.sync()
+    ctx.close()
