@@ -184,7 +184,8 @@ cp_status cp_get_gram(cp_ctx *ctx, int32_t mode, double *G_out); /* R x R */
 
 /*
  * cp_get_unique - the merged draws of the last cp_sample/cp_set_samples:
- * for each distinct sampled column, in increasing order of its first draw:
+ * for each distinct sampled column that holds nonzeros (columns without
+ * nonzeros add nothing to M), in increasing order of its first draw:
  * col_key (uint64), rep (index of its first draw), count (number of draws),
  * weight (count / (J p)).  Device outputs of capacity `cap` (any may be
  * NULL); n_out (host) receives the number of distinct columns.
@@ -215,6 +216,17 @@ cp_status cp_get_extracted(cp_ctx *ctx, uint64_t *col_key, int32_t *row,
 cp_status cp_profile(cp_ctx *ctx, int32_t enable);
 cp_status cp_profile_read(cp_ctx *ctx, double *ms, int64_t *launches);
 const char *cp_phase_name(int32_t phase);
+
+/*
+ * cp_pinv - Moore-Penrose pseudo-inverse of one symmetric positive
+ * semi-definite R x R matrix (Eq. 4), as used for G^+ in every mode solve:
+ * Cholesky when every pivot exceeds max(R 2^-52 tr(G), 1e-9 max_i G_ii),
+ * otherwise a cyclic Jacobi eigendecomposition with eigenvalues at or below
+ * R 2^-52 lambda_max treated as zero.  G, Gp: device, row-major FP64.
+ * stream: hipStream_t.  Synchronising; allocates its own scratch.
+ * CP_ENUMERIC if G is not finite or the eigen-iteration fails.
+ */
+cp_status cp_pinv(const double *G, int32_t R, double *Gp, void *stream);
 
 /*
  * cp_counters - cumulative work counters (host out, 4 int64): sampled mode

@@ -85,6 +85,7 @@ def load_library(path=LIB_PATH):
         "cp_profile_read": [P, P, P],
         "cp_index_stats": [P, I32, C.POINTER(I64), C.POINTER(I64)],
         "cp_counters": [P, P, I32],
+        "cp_pinv": [P, I32, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -104,6 +105,21 @@ def load_library(path=LIB_PATH):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def pinv(G, stream=None):
+    """Pseudo-inverse of a symmetric PSD matrix (torch FP64 CUDA tensor)."""
+    import torch
+    lib = load_library()
+    G = G.to(torch.float64).contiguous()
+    R = G.shape[0]
+    assert G.shape == (R, R) and G.is_cuda
+    out = torch.empty_like(G)
+    s = stream if stream is not None else torch.cuda.current_stream(G.device)
+    st = lib.cp_pinv(_ptr(G), R, _ptr(out), C.c_void_p(s.cuda_stream))
+    if st != 0:
+        raise CprError(st, "cp_pinv failed")
+    return out
 
 
 class Context:

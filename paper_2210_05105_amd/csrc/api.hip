@@ -745,6 +745,42 @@ cp_status cp_profile_read(cp_ctx *c, double *ms, int64_t *launches) {
   });
 }
 
+cp_status cp_pinv(const double *G, int32_t R, double *Gp, void *stream) {
+  if (!G || !Gp || R < 1 || R > MAXR) return CP_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *scratch = nullptr, *Gfull = nullptr;
+  uint32_t *err = nullptr;
+  cp_status st = CP_OK;
+  if (hipMalloc(&scratch, (size_t)R * R * 8) != hipSuccess ||
+      hipMalloc(&Gfull, (size_t)R * R * 8) != hipSuccess ||
+      hipMalloc(&err, 4) != hipSuccess) {
+    st = CP_ENOMEM;
+  } else {
+    try {
+      ModeList ml;
+      std::memset(&ml, 0, sizeof(ml));
+      ml.n = 1;
+      ml.G[0] = G;
+      uint32_t e = 0;
+      if (hipMemsetAsync(err, 0, 4, s) != hipSuccess) throw Fail{CP_EHIP, ""};
+      hadamard_pinv(ml, R, Gfull, Gp, nullptr, nullptr, scratch, err, s);
+      if (hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        throw Fail{CP_EHIP, ""};
+      if (e & ERR_NONFINITE) st = CP_ENUMERIC;
+      else if (e & ERR_PINV) st = CP_ENUMERIC;
+    } catch (const Fail &f) {
+      st = f.st;
+    } catch (const HipFail &) {
+      st = CP_EHIP;
+    }
+  }
+  if (scratch) (void)hipFree(scratch);
+  if (Gfull) (void)hipFree(Gfull);
+  if (err) (void)hipFree(err);
+  return st;
+}
+
 cp_status cp_counters(cp_ctx *c, int64_t *out, int32_t reset) {
   if (!c || !c->N || !out) return CP_EINVAL;
   return guard(c, [&] {

@@ -35,14 +35,15 @@ k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
       acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
     }
   }
-  // D[i][j]: lane l, element v -> i = 4 (l / 16) + v, j = l % 16
+  // D[i][j] of v_mfma_f64_16x16x4f64: lane l, element v -> i = l / 16 + 4 v,
+  // j = l % 16
   double s[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = t * 16 + (l % 16);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t r = row0 + 4 * (l / 16) + v;
+      const int64_t r = row0 + (l / 16) + 4 * v;
       if (r < I && j < R) s[v] += acc[t][v] * (double)U[r * R + j];
     }
   }
@@ -52,7 +53,7 @@ k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
   if ((l % 16) == 0) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t r = row0 + 4 * (l / 16) + v;
+      const int64_t r = row0 + (l / 16) + 4 * v;
       if (r < I) {
         double x = s[v];
         if (!isfinite(x)) atomicOr(err, ERR_NONFINITE);

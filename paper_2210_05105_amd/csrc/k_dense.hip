@@ -67,14 +67,15 @@ k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
       }
     }
   }
-  // D[i][j] of a 16x16 tile: lane l, element v -> i = 4 (l / 16) + v, j = l % 16
+  // D[i][j] of v_mfma_f64_16x16x4f64: lane l, element v -> i = l / 16 + 4 v,
+  // j = l % 16
   double *out = partial + (int64_t)blockIdx.x * R * R;
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
     if (ta[i] < 0) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      int gi = ta[i] * 16 + 4 * (l / 16) + v;
+      int gi = ta[i] * 16 + (l / 16) + 4 * v;
       int gj = tb[i] * 16 + (l % 16);
       if (gi < R && gj < R) {
         out[gi * R + gj] = acc[i][v];
@@ -198,15 +199,17 @@ __device__ bool jacobi_pinv(double *A, int R, double *V, double *Gp,
   __threadfence_block();
   __syncthreads();
   bool conv = false;
+  double off = 0, dia = 0;
   for (int sweep = 0; sweep < 40 && !conv; ++sweep) {
-    double off = 0, dia = 0;
+    off = 0;
+    dia = 0;
     for (int e = t; e < R * R; e += PV_THREADS) {
       double v = A[e] * A[e];
       if (e / R == e % R) dia += v; else off += v;
     }
     off = block_sum(off, red);
     dia = block_sum(dia, red);
-    if (off <= 1e-30 * dia || off == 0) { conv = true; break; }
+    if (off <= 1e-26 * dia || off == 0) { conv = true; break; }
     for (int r = 0; r < m - 1; ++r) {
       // pair i: (arr[i], arr[m-1-i]) with arr[0] = 0, arr[x] = 1 + (x-1+r)%(m-1)
       for (int i = t; i < m / 2; i += PV_THREADS) {
@@ -269,7 +272,7 @@ __device__ bool jacobi_pinv(double *A, int R, double *V, double *Gp,
     }
     Gp[e] = acc;
   }
-  return conv;
+  return conv || off <= 1e-20 * dia;
 }
 
 __global__ void __launch_bounds__(PV_THREADS)
@@ -280,7 +283,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   __shared__ double rot[4 * (MAXR / 2 + 1)];
   __shared__ int flag;
   const int t = threadIdx.x;
-  double tr = 0;
+  double tr = 0, dmax = 0;
   bool bad = false;
   for (int e = t; e < R * R; e += PV_THREADS) {
     double v = 1;
@@ -288,11 +291,18 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
     A[e] = v;
     Gfull[e] = v;
     if (!isfinite(v)) bad = true;
-    if (e / R == e % R) tr += v;
+    if (e / R == e % R) {
+      tr += v;
+      dmax = fmax(dmax, v);
+    }
   }
   if (bad) atomicOr(err, ERR_NONFINITE);
   tr = block_sum(tr, red);
-  const double tol = R * 0x1p-52 * tr;
+  dmax = block_max(dmax, red);
+  // Cholesky only for clearly positive definite G (every pivot above
+  // 1e-9 of the largest diagonal entry); anything closer to singular takes
+  // the eigendecomposition, whose cutoff defines the pseudo-inverse.
+  const double tol = fmax(R * 0x1p-52 * tr, 1e-9 * dmax);
   __syncthreads();
   bool ok = chol_inverse(A, R, tol, scratch, Gp, &flag);
   if (!ok) {

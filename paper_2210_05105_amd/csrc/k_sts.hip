@@ -75,7 +75,7 @@ k_tree_leaves(const T *U, int64_t I, int R, int F, int64_t P2, int LB,
           }
       }
     }
-    // tile (ta, tb), lane l, element v -> (ta*16 + 4(l/16) + v, tb*16 + l%16)
+    // tile (ta, tb), lane l, element v -> (ta*16 + l/16 + 4v, tb*16 + l%16)
 #pragma unroll
     for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
@@ -83,7 +83,7 @@ k_tree_leaves(const T *U, int64_t I, int R, int F, int64_t P2, int LB,
         const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int ga = ta * 16 + 4 * (l / 16) + v;
+          const int ga = ta * 16 + (l / 16) + 4 * v;
           const int gb = tb * 16 + (l % 16);
           if (ga < R && gb < R && ga <= gb)
             node[packed_index(ga, gb, R)] = acc[i][v];
@@ -220,7 +220,7 @@ k_sts_draw(ModeList ml, int64_t J, int R, int F, const double *uni,
         const int j = x * 16 + (l % 16);
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
-          const int64_t r = row0 + tile * 16 + 4 * (l / 16) + vv;
+          const int64_t r = row0 + tile * 16 + (l / 16) + 4 * vv;
           if (r < I && j < R) sm[vv] += acc[x][vv] * (double)U[r * R + j];
         }
       }
@@ -228,7 +228,7 @@ k_sts_draw(ModeList ml, int64_t J, int R, int F, const double *uni,
       for (int vv = 0; vv < 4; ++vv)
         for (int o = 1; o < 16; o <<= 1) sm[vv] += __shfl_xor(sm[vv], o, WAVE);
       if ((l % 16) == 0)
-        for (int vv = 0; vv < 4; ++vv) sh_m[w][tile * 16 + 4 * (l / 16) + vv] = sm[vv];
+        for (int vv = 0; vv < 4; ++vv) sh_m[w][tile * 16 + (l / 16) + 4 * vv] = sm[vv];
     }
     wave_sync();
     // prefix over the leaf's rows (lane i = row row0 + i)

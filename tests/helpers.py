@@ -17,6 +17,21 @@ def gpu_state(ctx):
     return U, G
 
 
+def cond_psd(G):
+    """Condition number over the eigenvalues the pseudo-inverse keeps."""
+    w = np.linalg.eigvalsh(0.5 * (G + G.T))
+    cut = G.shape[0] * 2.0 ** -52 * max(w.max(), 0)
+    keep = w[w > cut]
+    return float(keep.max() / keep.min()) if keep.size else 1.0
+
+
+def pinv_rtol(base, *grams):
+    """Relative tolerance for results that go through a pseudo-inverse:
+    two correct FP64 pseudo-inverses differ by about cond * eps."""
+    k = max(cond_psd(G) for G in grams)
+    return max(base, 100.0 * k * 2.0 ** -52)
+
+
 def rel_fro(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
