@@ -42,6 +42,8 @@ struct cp_ctx {
   int64_t *last[MAXN] = {};
   double *tree[MAXN] = {};
   int64_t P2[MAXN] = {};
+  double *sts_lev = nullptr, *sts_cdf = nullptr, *sts_Z = nullptr;
+  int64_t *sts_last = nullptr;
   double *Gfull = nullptr, *Gp = nullptr, *ggt = nullptr, *trace = nullptr;
   double *pv_scratch = nullptr, *Gp1 = nullptr, *Gfull1 = nullptr;
   int32_t *sidx = nullptr;
@@ -100,7 +102,7 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 
 class PhaseScope {
  public:
-  PhaseScope(cp_ctx *c, int ph) : c_(c), ph_(ph) {
+  PhaseScope(cp_ctx *c, int ph) : c_(c) {
     if (!c_->prof) return;
     if (c_->ev_used == c_->evs.size()) {
       ProfEv e{ph, nullptr, nullptr};
@@ -118,7 +120,7 @@ class PhaseScope {
 
  private:
   cp_ctx *c_;
-  int ph_;
+
   size_t idx_ = (size_t)-1;
 };
 
@@ -254,17 +256,26 @@ void pinv_for(cp_ctx *c, const ModeList &ml, bool sts) {
 
 template <typename T>
 void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
-  const ModeList ml = make_ml(c, mode);
+  ModeList ml = make_ml(c, mode);
   const bool sts = c->sampler == CP_SAMPLER_STS;
   pinv_for(c, ml, sts);
   {
     PhaseScope ps(c, PH_SAMPLE);
-    if (sts)
+    if (sts) {
+      // first factor: CDF of the row masses U[i] G_{>k} U[i]^T (h = 1)
+      arls_build<T>(static_cast<const T *>(ml.U[0]), ml.I[0], c->R, c->ggt,
+                    c->sts_lev, c->sts_cdf, c->sts_Z, c->sts_last, c->tmp,
+                    c->d_err, c->s);
+      ml.lev[0] = c->sts_lev;
+      ml.cdf[0] = c->sts_cdf;
+      ml.Z[0] = c->sts_Z;
+      ml.last[0] = c->sts_last;
       sts_draw<T>(ml, J, c->R, c->F, uni, c->Gp, c->trace, c->sidx, c->prob,
                   static_cast<T *>(c->h), c->d_err, c->s);
-    else
+    } else {
       arls_draw<T>(ml, J, c->R, uni, c->sidx, c->prob, static_cast<T *>(c->h),
                    c->d_err, c->s);
+    }
   }
   {
     PhaseScope ps(c, PH_DEDUP);
@@ -419,6 +430,14 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
       dalloc(c, &c->tree[k], (size_t)2 * c->P2[k] * sts_packed(R) * 8);
     }
   }
+  if (c->sampler == CP_SAMPLER_STS) {
+    int64_t mI = 0;
+    for (int k = 0; k < N; ++k) mI = std::max(mI, c->dims[k]);
+    dalloc(c, &c->sts_lev, mI * 8);
+    dalloc(c, &c->sts_cdf, mI * 8);
+    dalloc(c, &c->sts_Z, 8);
+    dalloc(c, &c->sts_last, 8);
+  }
   dalloc(c, &c->sigma, R * 8);
   dalloc(c, &c->Gfull, R * R * 8);
   dalloc(c, &c->Gp, R * R * 8);
@@ -441,6 +460,8 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.uq_off, (J + 1) * 8);
   dalloc(c, &c->w.counts, 16);
   dalloc(c, &c->w.stats, 4 * 8);
+  dalloc(c, &c->w.scratch, (size_t)4 * J * 8);
+  dalloc(c, &c->w.scan_tmp, scan_temp_bytes(J));
   zero_fill<int64_t>(c->w.stats, 4, c->s);
   dalloc(c, &c->M, (size_t)c->max_I * R * ts);
   dalloc(c, &c->X, (size_t)c->max_I * R * 8);

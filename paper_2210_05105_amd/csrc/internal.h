@@ -142,6 +142,8 @@ struct SampleWork {
   int64_t *uq_off;   // J+1: extracted-nonzero offsets
   int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
+  int64_t *scratch;  // 4 J: first-draw flags, lengths and their prefix sums
+  void *scan_tmp;    // scan_temp_bytes(J)
 };
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,

@@ -85,13 +85,29 @@ k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
   }
 }
 
-__global__ void k_sum_partials(const double *partial, int nblk, int n,
-                               double *out) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// out[c] = sum over b of P[b][c] (P is nrows x n), in a fixed order: 16
+// columns per block, 16 lanes per column stride over the rows, then the 16
+// lane sums are added in lane order.  Optionally out[c] = sqrt(sum).
+__global__ void __launch_bounds__(256)
+k_colsum(const double *P, int nrows, int n, double *out, int take_sqrt,
+         uint32_t *err) {
+  __shared__ double red[16][17];
+  const int cl = threadIdx.x % 16, rl = threadIdx.x / 16;
+  const int c = blockIdx.x * 16 + cl;
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * n + e];
-  out[e] = s;
+  if (c < n)
+    for (int b = rl; b < nrows; b += 16) s += P[(int64_t)b * n + c];
+  red[rl][cl] = s;
+  __syncthreads();
+  if (rl == 0 && c < n) {
+    double t = 0;
+    for (int i = 0; i < 16; ++i) t += red[i][cl];
+    if (take_sqrt) {
+      t = sqrt(t);
+      if (!isfinite(t)) atomicOr(err, ERR_NONFINITE);
+    }
+    out[c] = t;
+  }
 }
 
 int gram_blocks(int64_t I, int64_t *rows_per_blk) {
@@ -339,8 +355,20 @@ constexpr int SV_MAXBLK = 1024;
 
 template <typename T, int L>
 __global__ void __launch_bounds__(SV_THREADS)
-k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
+k_solve(const T *M, int64_t I, int R, const double *Gg, const double *Gpg,
         double *X, double *partial, int64_t *rows_out) {
+  // G and G^+ are read R times per row: stage them in LDS when they fit
+  extern __shared__ double gl_lds[];
+  const double *G = Gg, *Gp = Gpg;
+  if (R <= 48) {
+    for (int e = threadIdx.x; e < R * R; e += SV_THREADS) {
+      gl_lds[e] = Gg[e];
+      gl_lds[R * R + e] = Gpg[e];
+    }
+    __syncthreads();
+    G = gl_lds;
+    Gp = gl_lds + R * R;
+  }
   constexpr int CPL = (MAXR + L - 1) / L;  // columns per lane (max)
   constexpr int GPW = WAVE / L;            // groups per wave
   const int l = lane_id(), w = threadIdx.x / WAVE;
@@ -456,17 +484,6 @@ __global__ void k_colsumsq(const T *X, int64_t I, int R, double *partial) {
   }
 }
 
-__global__ void k_sigma(const double *partial, int nblk, int R, double *sigma,
-                        uint32_t *err) {
-  int c = threadIdx.x + blockIdx.x * blockDim.x;
-  if (c >= R) return;
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * R + c];
-  double sg = sqrt(s);
-  if (!isfinite(sg)) atomicOr(err, ERR_NONFINITE);
-  sigma[c] = sg;
-}
-
 template <typename T>
 __global__ void k_scale_cols(const double *X, int64_t n, int R,
                              const double *sigma, T *U) {
@@ -531,8 +548,8 @@ void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
     case 6: case 5: launch_gram<T, 6>(U, I, R, Rp, partial, nblk, rpb, s); break;
     default: launch_gram<T, 9>(U, I, R, Rp, partial, nblk, rpb, s); break;
   }
-  hipLaunchKernelGGL(k_sum_partials, dim3(ceil_div(R * R, 256)), dim3(256), 0,
-                     s, partial, nblk, R * R, G);
+  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(R * R, 16)), dim3(256), 0, s,
+                     partial, nblk, R * R, G, 0, nullptr);
   CPR_LAUNCH_CHECK();
 }
 template void gram<float>(const float *, int64_t, int, double *, void *,
@@ -566,14 +583,15 @@ void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
                 const double *Gp, double *X, double *partial, int nblk,
                 int64_t *rows_out, hipStream_t s) {
   const dim3 g(nblk), b(SV_THREADS);
+  const size_t lds = R <= 48 ? (size_t)2 * R * R * sizeof(double) : 0;
   if (R <= 8)
-    hipLaunchKernelGGL((k_solve<T, 8>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+    hipLaunchKernelGGL((k_solve<T, 8>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
   else if (R <= 16)
-    hipLaunchKernelGGL((k_solve<T, 16>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+    hipLaunchKernelGGL((k_solve<T, 16>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
   else if (R <= 32)
-    hipLaunchKernelGGL((k_solve<T, 32>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+    hipLaunchKernelGGL((k_solve<T, 32>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
   else
-    hipLaunchKernelGGL((k_solve<T, 64>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+    hipLaunchKernelGGL((k_solve<T, 64>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
   CPR_LAUNCH_CHECK();
 }
 template void solve_rows<float>(const float *, int64_t, int, const double *,
@@ -587,8 +605,8 @@ template <typename T>
 void finish_normalize(const double *X, int64_t I, int R, const double *partial,
                       int nblk, double *sigma, T *U, uint32_t *err,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_sigma, dim3(1), dim3(MAXR), 0, s, partial, nblk, R,
-                     sigma, err);
+  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(R, 16)), dim3(256), 0, s,
+                     partial, nblk, R, sigma, 1, err);
   hipLaunchKernelGGL((k_scale_cols<T>), dim3(ceil_div(I * R, 256)), dim3(256),
                      0, s, X, I * R, R, sigma, U);
   CPR_LAUNCH_CHECK();

@@ -72,71 +72,43 @@ __global__ void k_dup(int64_t J, const int32_t *col_id, const int32_t *owner,
   if (o != (int32_t)s) atomicAdd(&dupcnt[o], 1);
 }
 
-constexpr int MG_THREADS = 1024;
-constexpr int MG_WAVES = MG_THREADS / WAVE;
-
-__device__ int64_t block_excl_scan_i64(int64_t x, int64_t *total,
-                                       int64_t *wsum) {
-  const int w = threadIdx.x / WAVE, l = lane_id();
-  int64_t inc = x;
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int64_t y = __shfl_up(inc, o, WAVE);
-    if (l >= o) inc += y;
-  }
-  if (l == WAVE - 1) wsum[w] = inc;
-  __syncthreads();
-  int64_t off = 0, tot = 0;
-  for (int i = 0; i < MG_WAVES; ++i) {
-    if (i < w) off += wsum[i];
-    tot += wsum[i];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + inc - x;
+// First draw of each column: flag and nonzero-range length (prefix-summed
+// next, to number the distinct columns in draw order and place their
+// nonzero ranges).
+__global__ void k_first(int64_t J, const int32_t *col_id, const int32_t *owner,
+                        const int64_t *col_ptr, int64_t *flag, int64_t *len) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J) return;
+  const int32_t cid = col_id[s];
+  const bool first = cid >= 0 && owner[cid] == (int32_t)s;
+  flag[s] = first ? 1 : 0;
+  len[s] = first ? col_ptr[cid + 1] - col_ptr[cid] : 0;
 }
 
-// One workgroup: compaction of first draws in draw order, weights and
-// extracted-nonzero offsets; restores owner/dupcnt for the next call.
-__global__ void __launch_bounds__(MG_THREADS)
-k_merge(int64_t J, const double *prob, const int64_t *col_ptr,
-        const int32_t *col_id, int32_t *owner, int32_t *dupcnt, int32_t *uq_s,
-        int32_t *uq_cid, int32_t *uq_cnt, double *uq_w, int64_t *uq_off,
-        int64_t *counts, int64_t *stats) {
-  __shared__ int64_t wsum[MG_WAVES];
-  int64_t nu = 0, nz = 0;
-  for (int64_t c0 = 0; c0 < J; c0 += MG_THREADS) {
-    const int64_t s = c0 + threadIdx.x;
-    int32_t cid = -1;
-    bool first = false;
-    if (s < J) {
-      cid = col_id[s];
-      first = cid >= 0 && owner[cid] == (int32_t)s;
-    }
-    int64_t len = first ? col_ptr[cid + 1] - col_ptr[cid] : 0;
-    int64_t tu, tz;
-    const int64_t pu = block_excl_scan_i64(first ? 1 : 0, &tu, wsum);
-    const int64_t pz = block_excl_scan_i64(len, &tz, wsum);
-    if (first) {
-      const int64_t u = nu + pu;
-      const int32_t cnt = 1 + dupcnt[s];
-      uq_s[u] = (int32_t)s;
-      uq_cid[u] = cid;
-      uq_cnt[u] = cnt;
-      uq_w[u] = (double)cnt / ((double)J * prob[s]);
-      uq_off[u] = nz + pz;
-    }
-    nu += tu;
-    nz += tz;
-  }
-  __syncthreads();
-  // all reads of owner/dupcnt are done: restore them
-  for (int64_t s = threadIdx.x; s < J; s += MG_THREADS) {
+// Compaction of the first draws (weights count / (J p)); restores owner and
+// dupcnt for the next call (owner is not read after k_first).
+__global__ void k_compact(int64_t J, const double *prob, const int32_t *col_id,
+                          const int64_t *flag, const int64_t *len,
+                          const int64_t *uidx, const int64_t *off,
+                          int32_t *owner, int32_t *dupcnt, int32_t *uq_s,
+                          int32_t *uq_cid, int32_t *uq_cnt, double *uq_w,
+                          int64_t *uq_off, int64_t *counts, int64_t *stats) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= J) return;
+  if (flag[s]) {
+    const int64_t u = uidx[s];
     const int32_t cid = col_id[s];
-    if (cid >= 0) owner[cid] = INT_MAX;
-    dupcnt[s] = 0;
+    const int32_t cnt = 1 + dupcnt[s];
+    uq_s[u] = (int32_t)s;
+    uq_cid[u] = cid;
+    uq_cnt[u] = cnt;
+    uq_w[u] = (double)cnt / ((double)J * prob[s]);
+    uq_off[u] = off[s];
+    owner[cid] = INT_MAX;
   }
-  if (threadIdx.x == 0) {
+  dupcnt[s] = 0;
+  if (s == J - 1) {
+    const int64_t nu = uidx[s] + flag[s], nz = off[s] + len[s];
     uq_off[nu] = nz;
     counts[0] = nu;
     counts[1] = nz;
@@ -148,9 +120,14 @@ k_merge(int64_t J, const double *prob, const int64_t *col_ptr,
   }
 }
 
-// Sampled MTTKRP.  A group of L lanes (L = smallest power of two >= R, at
-// most 64) handles one nonzero at a time; chunks of CH consecutive extracted
-// nonzeros are dealt to waves round-robin.
+// Sampled MTTKRP.  Waves take chunks of MT_CHUNK consecutive extracted
+// nonzeros round-robin (balance by nonzeros).  In each 64-nonzero batch,
+// lane i first resolves nonzero i of the batch on its own (distinct column
+// by a short binary search, position in the mode's index, row, w v, sampled
+// row id), so the dependent loads of 64 nonzeros are in flight together;
+// then groups of L lanes (L = smallest power of two >= R, at most 64) take
+// the resolved nonzeros from their owners by shuffle and add w v h into
+// M[i, :] with hardware float atomics.
 constexpr int MT_THREADS = 256;
 constexpr int MT_CHUNK = 256;
 
@@ -169,22 +146,42 @@ k_mttkrp(const int64_t *counts, const int32_t *uq_s, const int32_t *uq_cid,
   for (int64_t c = wave; c < nchunk; c += nwave) {
     const int64_t e0 = c * MT_CHUNK;
     const int64_t e1 = e0 + MT_CHUNK < nz ? e0 + MT_CHUNK : nz;
-    // u = last distinct column with uq_off[u] <= e0
+    // first distinct column of the chunk: last u with uq_off[u] <= e0
     int64_t lo = 0, hi = nu;
     while (hi - lo > 1) {
       int64_t mid = (lo + hi) >> 1;
       if (uq_off[mid] <= e0) lo = mid; else hi = mid;
     }
-    int64_t u = lo;
-    for (int64_t e = e0 + g; e < e1; e += GPW) {
-      while (uq_off[u + 1] <= e) ++u;
-      const int32_t cid = uq_cid[u];
-      const int64_t p = col_ptr[cid] + (e - uq_off[u]);
-      const int32_t i = row[p];
-      const T coef = (T)(uq_w[u] * (double)val[p]);
-      const T *hr = h + (int64_t)uq_s[u] * R;
-      T *mr = M + (int64_t)i * R;
-      for (int r = gl; r < R; r += L) unsafeAtomicAdd(mr + r, coef * hr[r]);
+    const int64_t ub = lo;
+    // a chunk touches at most MT_CHUNK + 1 distinct columns
+    const int64_t ue = ub + MT_CHUNK + 1 < nu ? ub + MT_CHUNK + 1 : nu;
+    for (int64_t b0 = e0; b0 < e1; b0 += WAVE) {
+      const int64_t e = b0 + l;
+      int32_t my_row = 0, my_s = 0;
+      T my_coef = 0;
+      if (e < e1) {
+        int64_t a = ub, z = ue;  // last u in [ub, ue) with uq_off[u] <= e
+        while (z - a > 1) {
+          int64_t m = (a + z) >> 1;
+          if (uq_off[m] <= e) a = m; else z = m;
+        }
+        const int64_t p = col_ptr[uq_cid[a]] + (e - uq_off[a]);
+        my_row = row[p];
+        my_coef = (T)(uq_w[a] * (double)val[p]);
+        my_s = uq_s[a];
+      }
+      const int nb = (int)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
+      for (int i = 0; i < nb; i += GPW) {
+        const int k = i + g;
+        const int32_t rr = __shfl(my_row, k, WAVE);
+        const T cf = __shfl(my_coef, k, WAVE);
+        const int32_t ss = __shfl(my_s, k, WAVE);
+        if (k < nb) {
+          const T *hr = h + (int64_t)ss * R;
+          T *mr = M + (int64_t)rr * R;
+          for (int r = gl; r < R; r += L) unsafeAtomicAdd(mr + r, cf * hr[r]);
+        }
+      }
     }
   }
 }
@@ -284,11 +281,18 @@ void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
 
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    SampleWork &w, hipStream_t s) {
-  hipLaunchKernelGGL(k_dup, dim3(ceil_div(J, 256)), dim3(256), 0, s, J,
-                     w.col_id, w.owner, w.dupcnt);
-  hipLaunchKernelGGL(k_merge, dim3(1), dim3(MG_THREADS), 0, s, J, prob,
-                     col_ptr, w.col_id, w.owner, w.dupcnt, w.uq_s, w.uq_cid,
-                     w.uq_cnt, w.uq_w, w.uq_off, w.counts, w.stats);
+  const dim3 g(ceil_div(J, 256)), b(256);
+  int64_t *flag = w.scratch, *len = w.scratch + J, *uidx = w.scratch + 2 * J,
+          *off = w.scratch + 3 * J;
+  hipLaunchKernelGGL(k_dup, g, b, 0, s, J, w.col_id, w.owner, w.dupcnt);
+  hipLaunchKernelGGL(k_first, g, b, 0, s, J, w.col_id, w.owner, col_ptr, flag,
+                     len);
+  CPR_LAUNCH_CHECK();
+  exclusive_scan_i64(flag, uidx, J, w.scan_tmp, s);
+  exclusive_scan_i64(len, off, J, w.scan_tmp, s);
+  hipLaunchKernelGGL(k_compact, g, b, 0, s, J, prob, w.col_id, flag, len, uidx,
+                     off, w.owner, w.dupcnt, w.uq_s, w.uq_cid, w.uq_cnt,
+                     w.uq_w, w.uq_off, w.counts, w.stats);
   CPR_LAUNCH_CHECK();
 }
 

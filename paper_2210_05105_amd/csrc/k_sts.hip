@@ -6,6 +6,8 @@
 // P2 .. 2 P2 - 1 with P2 a power of two) as packed upper triangles in FP64.
 //
 // Draw (Alg. 5 without routing): for the factors != j in ascending order,
+// the first factor (h = 1, a law shared by all samples) is drawn from a flat
+// CDF of row masses; every later factor walks its tree.
 // with h the Hadamard product of the rows drawn so far and
 // G_{>k} = G^+ (*) (Grams of the factors drawn later), the mass of a node is
 // <(h h^T) (*) G_{>k}, G^node>.  A wave carries the absolute target
@@ -158,6 +160,25 @@ k_sts_draw(ModeList ml, int64_t J, int R, int F, const double *uni,
     if (!(u >= 0.0 && u < 1.0)) {
       if (l == 0) atomicOr(err, ERR_UNIFORM);
       u = 0.0;
+    }
+    if (q == 0) {
+      // h = 1: every sample shares this conditional law, held as a flat
+      // CDF of the row masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)}
+      const double Z0 = *ml.Z[0];
+      const double t0 = u * Z0;
+      const double *cdf = ml.cdf[0];
+      int64_t lo = 0, hi = I;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (t0 < cdf[mid]) hi = mid; else lo = mid + 1;
+      }
+      const int64_t last = *ml.last[0];
+      if (lo > last) lo = last;
+      if (lo < 0) lo = 0;
+      if (l == 0) sidx[s * nq + q] = (int32_t)lo;
+      for (int r = l; r < R; r += WAVE) h[r] = (double)U[lo * R + r];
+      wave_sync();
+      continue;
     }
     // W entries (packed, off-diagonal doubled)
     double W[E];
