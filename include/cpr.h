@@ -83,7 +83,8 @@ typedef struct {
   int32_t sampler;    /* cp_sampler                                            */
   int32_t precision;  /* cp_precision                                          */
   int32_t sts_leaf;   /* STS-CP tree leaf size in rows (16, 32 or 64); 0: 16  */
-  int64_t max_J;      /* largest J any cp_sample will use (sizes workspaces)   */
+  int64_t max_J;      /* largest J any cp_sample will use, <= 2^24 (sizes    
+                         workspaces); ignored by CP_SAMPLER_EXACT             */
 } cp_config;
 
 /*

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <functional>
 #include <cstring>
 #include <new>
 
@@ -321,7 +322,7 @@ void do_mttkrp(cp_ctx *c, int mode) {
     exact_mttkrp<T>(ml, ix.n_cols, ix.col_key, ix.col_ptr, ix.row,
                     static_cast<const T *>(ix.val), c->R, M, c->s);
   } else {
-    sampled_mttkrp<T>(c->w, c->cur_J, ix.col_ptr, ix.row,
+    sampled_mttkrp<T>(c->w, c->dims[mode], ix.col_ptr, ix.row,
                       static_cast<const T *>(ix.val),
                       static_cast<const T *>(c->h), c->R, M, c->s);
   }
@@ -461,7 +462,38 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.counts, 16);
   dalloc(c, &c->w.stats, 4 * 8);
   dalloc(c, &c->w.scratch, (size_t)4 * J * 8);
-  dalloc(c, &c->w.scan_tmp, scan_temp_bytes(J));
+  // output-row buckets of the sampled MTTKRP and the record capacity: at
+  // most J distinct columns are extracted, so the J longest columns of a
+  // mode bound the extracted nonzeros of any of its solves
+  const int bb = bucket_shift(R, (int)ts);
+  const int64_t nbk = (c->max_I + (1 << bb) - 1) >> bb;
+  dalloc(c, &c->w.scan_tmp, std::max(scan_temp_bytes(J),
+                                     scan_temp_bytes(nbk + 1)));
+  dalloc(c, &c->w.bk, (size_t)5 * (nbk + 1) * 8);
+  int64_t cap = 1;
+  if (c->sampler != CP_SAMPLER_EXACT) {
+    for (int k = 0; k < N; ++k) {
+      const int64_t nc = c->ix[k].n_cols;
+      std::vector<int64_t> ptr(nc + 1);
+      hip_ok(hipMemcpyAsync(ptr.data(), c->ix[k].col_ptr, (nc + 1) * 8,
+                            hipMemcpyDeviceToHost, c->s), "hipMemcpyAsync");
+      hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
+      std::vector<int64_t> len(nc);
+      for (int64_t i = 0; i < nc; ++i) len[i] = ptr[i + 1] - ptr[i];
+      int64_t top = 0;
+      if (J >= nc) {
+        top = c->nnz;
+      } else {
+        std::nth_element(len.begin(), len.begin() + J, len.end(),
+                         std::greater<int64_t>());
+        for (int64_t i = 0; i < J; ++i) top += len[i];
+      }
+      cap = std::max(cap, std::min(top, c->nnz));
+    }
+  }
+  c->w.rec_cap = cap;
+  dalloc(c, &c->w.rec, (size_t)cap * bucket_record_bytes((int)ts));
+  dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);
   zero_fill<int64_t>(c->w.stats, 4, c->s);
   dalloc(c, &c->M, (size_t)c->max_I * R * ts);
   dalloc(c, &c->X, (size_t)c->max_I * R * 8);
@@ -507,7 +539,7 @@ cp_status cp_init(const cp_tensor *t, const cp_config *cfg, void *stream,
   if (cfg->sampler < 0 || cfg->sampler > 2) return CP_EINVAL;
   if (cfg->precision < 0 || cfg->precision > 2) return CP_EINVAL;
   if (cfg->sampler != CP_SAMPLER_EXACT &&
-      (cfg->max_J < 1 || cfg->max_J > INT_MAX))
+      (cfg->max_J < 1 || cfg->max_J > (int64_t(1) << 24)))
     return CP_EINVAL;
   if (cfg->sts_leaf != 0 && cfg->sts_leaf != 16 && cfg->sts_leaf != 32 &&
       cfg->sts_leaf != 64)

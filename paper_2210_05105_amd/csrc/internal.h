@@ -143,8 +143,15 @@ struct SampleWork {
   int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
   int64_t *scratch;  // 4 J: first-draw flags, lengths and their prefix sums
-  void *scan_tmp;    // scan_temp_bytes(J)
+  void *scan_tmp;    // scan_temp_bytes(max(J, buckets + 1))
+  int64_t *bk;       // 5 (buckets + 1): per output-row bucket counts/offsets
+  void *rec;         // cap records: extracted nonzeros grouped by bucket
+  int64_t rec_cap;
+  void *part;        // per-slice blocks of split buckets (B x R each)
 };
+int bucket_shift(int R, int tsize);
+int64_t bucket_max_items(int64_t rec_cap, int64_t nbk);
+size_t bucket_record_bytes(int tsize);
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
                      T *h, uint32_t *err, hipStream_t s);
@@ -154,7 +161,7 @@ void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    SampleWork &w, hipStream_t s);
 template <typename T>
-void sampled_mttkrp(const SampleWork &w, int64_t J, const int64_t *col_ptr,
+void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                     const int32_t *row, const T *val, const T *h, int R,
                     T *M, hipStream_t s);
 template <typename T>

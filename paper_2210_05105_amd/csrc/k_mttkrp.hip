@@ -120,69 +120,285 @@ __global__ void k_compact(int64_t J, const double *prob, const int32_t *col_id,
   }
 }
 
-// Sampled MTTKRP.  Waves take chunks of MT_CHUNK consecutive extracted
-// nonzeros round-robin (balance by nonzeros).  In each 64-nonzero batch,
-// lane i first resolves nonzero i of the batch on its own (distinct column
-// by a short binary search, position in the mode's index, row, w v, sampled
-// row id), so the dependent loads of 64 nonzeros are in flight together;
-// then groups of L lanes (L = smallest power of two >= R, at most 64) take
-// the resolved nonzeros from their owners by shuffle and add w v h into
-// M[i, :] with hardware float atomics.
+// Sampled MTTKRP, output-row-block form (the paper's transposition of the
+// extracted nonzeros to row order, Section 4.3, done as one counting-sort
+// pass by blocks of B output rows):
+//   count   : bucket (= row / B) histogram of the extracted nonzeros;
+//   scatter : compact records (row % B, draw id, w v) grouped by bucket;
+//   accum   : one workgroup per (bucket, slice of <= BK_SLICE records)
+//             adds w v h into an LDS copy of the bucket's B rows of M with
+//             LDS atomics, then writes the rows once (plain stores when
+//             the bucket is one slice, float atomics when it is split).
+// Extracted nonzeros are never materialised: position e of the
+// concatenated sampled-column ranges is resolved to (distinct column,
+// position in the mode's index) by a binary search over uq_off.
 constexpr int MT_THREADS = 256;
-constexpr int MT_CHUNK = 256;
+constexpr int BK_TILE = 4096;     // positions per count/scatter tile
+constexpr int BK_ITEMS = BK_TILE / MT_THREADS;
+constexpr int BK_LDS_MAX = 4096;  // buckets histogrammed in LDS
+constexpr int BK_SLICE = 4096;    // records per accumulation workgroup
 
+// last u in [lo, hi) with uq_off[u] <= e (uq_off[lo] <= e < uq_off[hi])
+__device__ __forceinline__ int64_t find_col(const int64_t *uq_off, int64_t lo,
+                                            int64_t hi, int64_t e) {
+  while (hi - lo > 1) {
+    int64_t m = (lo + hi) >> 1;
+    if (uq_off[m] <= e) lo = m; else hi = m;
+  }
+  return lo;
+}
+
+// distinct-column range [ub, ue) covering positions [e0, e1)
+__device__ void tile_cols(const int64_t *uq_off, int64_t nu, int64_t e0,
+                          int64_t e1, int64_t *ub, int64_t *ue) {
+  *ub = find_col(uq_off, 0, nu, e0);
+  *ue = find_col(uq_off, *ub, nu, e1 - 1) + 1;
+}
+
+__global__ void __launch_bounds__(MT_THREADS)
+k_bk_count(const int64_t *counts, const int64_t *uq_off, const int32_t *uq_cid,
+           const int64_t *col_ptr, const int32_t *row, int nbk, int bb,
+           int64_t *bk_total) {
+  __shared__ uint32_t hist[BK_LDS_MAX];
+  __shared__ int64_t sh_ub, sh_ue;
+  const int64_t nu = counts[0], nz = counts[1];
+  const bool use_lds = nbk <= BK_LDS_MAX;
+  const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t e0 = tile * BK_TILE;
+    const int64_t e1 = e0 + BK_TILE < nz ? e0 + BK_TILE : nz;
+    if (use_lds)
+      for (int b = threadIdx.x; b < nbk; b += MT_THREADS) hist[b] = 0;
+    if (threadIdx.x == 0) tile_cols(uq_off, nu, e0, e1, &sh_ub, &sh_ue);
+    __syncthreads();
+    const int64_t ub = sh_ub, ue = sh_ue;
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      const int64_t e = e0 + (int64_t)i * MT_THREADS + threadIdx.x;
+      if (e >= e1) break;
+      const int64_t u = find_col(uq_off, ub, ue, e);
+      const int32_t rr = row[col_ptr[uq_cid[u]] + (e - uq_off[u])];
+      const int bk = rr >> bb;
+      if (use_lds) atomicAdd(&hist[bk], 1u);
+      else atomicAdd((unsigned long long *)&bk_total[bk], 1ull);
+    }
+    __syncthreads();
+    if (use_lds)
+      for (int b = threadIdx.x; b < nbk; b += MT_THREADS)
+        if (hist[b])
+          atomicAdd((unsigned long long *)&bk_total[b],
+                    (unsigned long long)hist[b]);
+    __syncthreads();
+  }
+}
+
+__global__ void k_bk_items(const int64_t *bk_total, int nbk, int64_t *items) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > nbk) return;
+  items[b] = b < nbk ? (bk_total[b] + BK_SLICE - 1) / BK_SLICE : 0;
+}
+
+// One extracted nonzero in bucket order: key = (draw id << 8) | row % B.
+template <typename T>
+struct BkRec {
+  uint32_t key;
+  T coef;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(MT_THREADS)
+k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const int32_t *uq_cid,
+             const double *uq_w, const int64_t *uq_off, const int64_t *col_ptr,
+             const int32_t *row, const T *val, int nbk, int bb,
+             const int64_t *bk_start, int64_t *bk_fill, BkRec<T> *rec) {
+  __shared__ uint32_t cnt[BK_LDS_MAX];
+  __shared__ uint32_t base[BK_LDS_MAX];
+  __shared__ int64_t sh_ub, sh_ue;
+  const int64_t nu = counts[0], nz = counts[1];
+  const bool use_lds = nbk <= BK_LDS_MAX;
+  const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
+  const uint32_t bmask = (1u << bb) - 1;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t e0 = tile * BK_TILE;
+    const int64_t e1 = e0 + BK_TILE < nz ? e0 + BK_TILE : nz;
+    if (use_lds)
+      for (int b = threadIdx.x; b < nbk; b += MT_THREADS) cnt[b] = 0;
+    if (threadIdx.x == 0) tile_cols(uq_off, nu, e0, e1, &sh_ub, &sh_ue);
+    __syncthreads();
+    const int64_t ub = sh_ub, ue = sh_ue;
+    int32_t my_row[BK_ITEMS];
+    uint32_t my_key[BK_ITEMS];
+    T my_cf[BK_ITEMS];
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      const int64_t e = e0 + (int64_t)i * MT_THREADS + threadIdx.x;
+      my_row[i] = -1;
+      if (e < e1) {
+        const int64_t u = find_col(uq_off, ub, ue, e);
+        const int64_t p = col_ptr[uq_cid[u]] + (e - uq_off[u]);
+        my_row[i] = row[p];
+        my_key[i] = ((uint32_t)uq_s[u] << 8) | ((uint32_t)my_row[i] & bmask);
+        my_cf[i] = (T)(uq_w[u] * (double)val[p]);
+        if (use_lds) atomicAdd(&cnt[my_row[i] >> bb], 1u);
+      }
+    }
+    __syncthreads();
+    if (use_lds)
+      for (int b = threadIdx.x; b < nbk; b += MT_THREADS) {
+        const uint32_t c = cnt[b];
+        if (c)
+          base[b] = (uint32_t)(bk_start[b] +
+                               (int64_t)atomicAdd((unsigned long long *)&bk_fill[b],
+                                                  (unsigned long long)c));
+        cnt[b] = 0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      if (my_row[i] < 0) continue;
+      const int bk = my_row[i] >> bb;
+      const uint64_t dst =
+          use_lds ? (uint64_t)base[bk] + atomicAdd(&cnt[bk], 1u)
+                  : (uint64_t)bk_start[bk] +
+                        atomicAdd((unsigned long long *)&bk_fill[bk], 1ull);
+      rec[dst] = BkRec<T>{my_key[i], my_cf[i]};
+    }
+    __syncthreads();
+  }
+}
+
+// Accumulation without floating-point LDS atomics (they run at a small
+// fraction of LDS speed): the slice's records are counting-sorted by row of
+// the bucket in LDS (integer atomics only); each group of L lanes (lanes
+// over columns) then walks a contiguous chunk of the sorted records,
+// accumulating runs of one row in registers and adding each run to the LDS
+// copy of the bucket's rows once.  Only runs cut by a chunk boundary meet
+// another group on the same row, so the remaining float atomics are few.
 template <typename T, int L>
 __global__ void __launch_bounds__(MT_THREADS)
-k_mttkrp(const int64_t *counts, const int32_t *uq_s, const int32_t *uq_cid,
-         const double *uq_w, const int64_t *uq_off, const int64_t *col_ptr,
-         const int32_t *row, const T *val, const T *h, int R, T *M) {
-  constexpr int GPW = WAVE / L;
-  const int l = lane_id();
-  const int gl = l % L, g = l / L;
-  const int64_t nu = counts[0], nz = counts[1];
-  const int64_t wave = (int64_t)blockIdx.x * (MT_THREADS / WAVE) + threadIdx.x / WAVE;
-  const int64_t nwave = (int64_t)gridDim.x * (MT_THREADS / WAVE);
-  const int64_t nchunk = (nz + MT_CHUNK - 1) / MT_CHUNK;
-  for (int64_t c = wave; c < nchunk; c += nwave) {
-    const int64_t e0 = c * MT_CHUNK;
-    const int64_t e1 = e0 + MT_CHUNK < nz ? e0 + MT_CHUNK : nz;
-    // first distinct column of the chunk: last u with uq_off[u] <= e0
-    int64_t lo = 0, hi = nu;
+k_bk_accum(const int64_t *item_start, const int64_t *bk_start, int nbk, int bb,
+           const BkRec<T> *rec, const T *h, int R, int64_t I, T *M, T *part) {
+  constexpr int G = MT_THREADS / L;         // lane groups per block
+  constexpr int CPL = (MAXR + L - 1) / L;   // columns per lane (max)
+  extern __shared__ unsigned char bk_lds_raw[];
+  T *blk = reinterpret_cast<T *>(bk_lds_raw);          // B x R
+  const int B = 1 << bb;
+  T *lc = blk + B * R;                                 // BK_SLICE coefs
+  int32_t *ls = reinterpret_cast<int32_t *>(lc + BK_SLICE);  // draw ids
+  uint8_t *lr = reinterpret_cast<uint8_t *>(ls + BK_SLICE);  // rows
+  __shared__ int32_t cnt[256 + 1];
+  __shared__ int32_t wsum[MT_THREADS / WAVE];
+  const int t = threadIdx.x, l = lane_id();
+  const int gl = l % L, g = t / L;
+  const int ncl = (R + L - 1) / L;
+  const int64_t nitems = item_start[nbk];
+  for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    int64_t lo = 0, hi = nbk;  // bucket: last b with item_start[b] <= item
     while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (uq_off[mid] <= e0) lo = mid; else hi = mid;
+      int64_t m = (lo + hi) >> 1;
+      if (item_start[m] <= item) lo = m; else hi = m;
     }
-    const int64_t ub = lo;
-    // a chunk touches at most MT_CHUNK + 1 distinct columns
-    const int64_t ue = ub + MT_CHUNK + 1 < nu ? ub + MT_CHUNK + 1 : nu;
-    for (int64_t b0 = e0; b0 < e1; b0 += WAVE) {
-      const int64_t e = b0 + l;
-      int32_t my_row = 0, my_s = 0;
-      T my_coef = 0;
-      if (e < e1) {
-        int64_t a = ub, z = ue;  // last u in [ub, ue) with uq_off[u] <= e
-        while (z - a > 1) {
-          int64_t m = (a + z) >> 1;
-          if (uq_off[m] <= e) a = m; else z = m;
-        }
-        const int64_t p = col_ptr[uq_cid[a]] + (e - uq_off[a]);
-        my_row = row[p];
-        my_coef = (T)(uq_w[a] * (double)val[p]);
-        my_s = uq_s[a];
+    const int bk = (int)lo;
+    const int64_t k = item - item_start[bk];
+    const int64_t r0 = bk_start[bk] + k * BK_SLICE;
+    const int64_t r1 = r0 + BK_SLICE < bk_start[bk + 1] ? r0 + BK_SLICE
+                                                          : bk_start[bk + 1];
+    const int n = (int)(r1 - r0);
+    const bool single = item_start[bk + 1] - item_start[bk] == 1;
+    for (int e = t; e < B * R; e += MT_THREADS) blk[e] = T(0);
+    for (int e = t; e <= 256; e += MT_THREADS) cnt[e] = 0;
+    __syncthreads();
+    for (int e = t; e < n; e += MT_THREADS)
+      atomicAdd(&cnt[rec[r0 + e].key & 255u], 1);
+    __syncthreads();
+    {  // exclusive scan of the 256 row counts (thread t owns row t)
+      const int w = t / WAVE;
+      const int v = t < 256 ? cnt[t] : 0;
+      int inc = v;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(inc, o, WAVE);
+        if (l >= o) inc += y;
       }
-      const int nb = (int)(e1 - b0 < WAVE ? e1 - b0 : WAVE);
-      for (int i = 0; i < nb; i += GPW) {
-        const int k = i + g;
-        const int32_t rr = __shfl(my_row, k, WAVE);
-        const T cf = __shfl(my_coef, k, WAVE);
-        const int32_t ss = __shfl(my_s, k, WAVE);
-        if (k < nb) {
-          const T *hr = h + (int64_t)ss * R;
-          T *mr = M + (int64_t)rr * R;
-          for (int r = gl; r < R; r += L) unsafeAtomicAdd(mr + r, cf * hr[r]);
+      if (l == WAVE - 1) wsum[w] = inc;
+      __syncthreads();
+      int off = 0;
+      for (int i = 0; i < w; ++i) off += wsum[i];
+      if (t < 256) cnt[t] = off + inc - v;  // becomes the fill cursor
+      __syncthreads();
+    }
+    for (int e = t; e < n; e += MT_THREADS) {
+      const BkRec<T> rc = rec[r0 + e];
+      const int rr = (int)(rc.key & 255u);
+      const int pos = atomicAdd(&cnt[rr], 1);
+      ls[pos] = (int32_t)(rc.key >> 8);
+      lc[pos] = rc.coef;
+      lr[pos] = (uint8_t)rr;
+    }
+    __syncthreads();
+    // group g: sorted records [c0, c1)
+    const int per = (n + G - 1) / G;
+    const int c0 = g * per < n ? g * per : n;
+    const int c1 = c0 + per < n ? c0 + per : n;
+    T acc[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) acc[q] = T(0);
+    int cur = c0 < c1 ? lr[c0] : -1;
+    auto flush = [&](int row) {
+      T *br = blk + row * R;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = gl + q * L;
+        if (q < ncl && c < R) atomicAdd(br + c, acc[q]);
+        acc[q] = T(0);
+      }
+    };
+    int kk = c0;
+    for (; kk + 4 <= c1; kk += 4) {
+      T hv[4][CPL];
+      int rw[4];
+      T cf[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rw[u] = lr[kk + u];
+        cf[u] = lc[kk + u];
+        const T *hr = h + (int64_t)ls[kk + u] * R;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = gl + q * L;
+          hv[u][q] = hr[c < R ? c : 0];
         }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (rw[u] != cur) {
+          flush(cur);
+          cur = rw[u];
+        }
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) acc[q] += cf[u] * hv[u][q];
       }
     }
+    for (; kk < c1; ++kk) {
+      const int rw = lr[kk];
+      if (rw != cur) {
+        flush(cur);
+        cur = rw;
+      }
+      const T *hr = h + (int64_t)ls[kk] * R;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int c = gl + q * L;
+        acc[q] += lc[kk] * hr[c < R ? c : 0];
+      }
+    }
+    if (cur >= 0) flush(cur);
+    __syncthreads();
+    // a bucket held by one slice goes straight to M; the slices of a split
+    // bucket store their block in their own scratch slot for k_bk_combine
+    const int64_t row0 = (int64_t)bk * B;
+    const int nrows = (int)(I - row0 < B ? I - row0 : B);
+    T *mo = single ? M + row0 * R : part + item * (int64_t)B * R;
+    for (int e = t; e < nrows * R; e += MT_THREADS) mo[e] = blk[e];
+    __syncthreads();
   }
 }
 
@@ -253,7 +469,28 @@ __global__ void k_debug_unique(const int64_t *counts, const int32_t *uq_s,
   if (w_out) w_out[u] = uq_w[u];
 }
 
+// Rows of a split bucket: sum of its slices' blocks, in slice order.
+template <typename T>
+__global__ void k_bk_combine(const int64_t *item_start, int nbk, int bb, int R,
+                             int64_t I, const T *part, T *M) {
+  const int B = 1 << bb;
+  const int64_t per = (int64_t)B * R;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       g < (int64_t)nbk * per; g += (int64_t)gridDim.x * blockDim.x) {
+    const int bk = (int)(g / per);
+    const int e = (int)(g - (int64_t)bk * per);
+    const int64_t k0 = item_start[bk], k1 = item_start[bk + 1];
+    if (k1 - k0 < 2) continue;
+    const int64_t row0 = (int64_t)bk * B;
+    if (row0 + e / R >= I) continue;
+    T acc = 0;
+    for (int64_t k = k0; k < k1; ++k) acc += part[k * per + e];
+    M[row0 * R + e] = acc;
+  }
+}
+
 int mttkrp_grid() { return 256 * 8; }
+
 
 }  // namespace
 
@@ -296,21 +533,70 @@ void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
   CPR_LAUNCH_CHECK();
 }
 
+int bucket_shift(int R, int tsize) {
+  // B rows of M per bucket: 256, or fewer so that the B x R block fits
+  // 32 KiB of LDS beside the sorted slice
+  int bb = 8;
+  while (bb > 0 && ((1 << bb) * R * tsize) > 32768) --bb;
+  return bb;
+}
+
+size_t lds_cap() { return 160 * 1024 - 8 * 1024; }
+
 template <typename T>
-void sampled_mttkrp(const SampleWork &w, int64_t J, const int64_t *col_ptr,
+void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                     const int32_t *row, const T *val, const T *h, int R, T *M,
                     hipStream_t s) {
-  const dim3 g(mttkrp_grid()), b(MT_THREADS);
-  if (R <= 8)
-    hipLaunchKernelGGL((k_mttkrp<T, 8>), g, b, 0, s, w.counts, w.uq_s, w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, h, R, M);
-  else if (R <= 16)
-    hipLaunchKernelGGL((k_mttkrp<T, 16>), g, b, 0, s, w.counts, w.uq_s, w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, h, R, M);
-  else if (R <= 32)
-    hipLaunchKernelGGL((k_mttkrp<T, 32>), g, b, 0, s, w.counts, w.uq_s, w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, h, R, M);
-  else
-    hipLaunchKernelGGL((k_mttkrp<T, 64>), g, b, 0, s, w.counts, w.uq_s, w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, h, R, M);
+  const int bb = bucket_shift(R, (int)sizeof(T));
+  const int nbk = (int)((I + (1 << bb) - 1) >> bb);
+  int64_t *bk_total = w.bk, *bk_fill = w.bk + (nbk + 1),
+          *bk_start = w.bk + 2 * (nbk + 1), *items = w.bk + 3 * (nbk + 1),
+          *item_start = w.bk + 4 * (nbk + 1);
+  const dim3 b(MT_THREADS), gt(mttkrp_grid());
+  zero_fill<int64_t>(bk_total, 2 * (nbk + 1), s);  // totals and fill cursors
+  hipLaunchKernelGGL(k_bk_count, gt, b, 0, s, w.counts, w.uq_off, w.uq_cid,
+                     col_ptr, row, nbk, bb, bk_total);
   CPR_LAUNCH_CHECK();
-  (void)J;
+  exclusive_scan_i64(bk_total, bk_start, nbk + 1, w.scan_tmp, s);
+  hipLaunchKernelGGL(k_bk_items, dim3(ceil_div(nbk + 1, 256)), b, 0, s,
+                     bk_total, nbk, items);
+  CPR_LAUNCH_CHECK();
+  exclusive_scan_i64(items, item_start, nbk + 1, w.scan_tmp, s);
+  BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
+  T *part = static_cast<T *>(w.part);
+  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 0, s, w.counts, w.uq_s,
+                     w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, nbk, bb,
+                     bk_start, bk_fill, rec);
+  CPR_LAUNCH_CHECK();
+  const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
+                     (size_t)BK_SLICE * (sizeof(T) + 4 + 1);
+  static bool attr_set[2][4] = {};
+  auto launch = [&](auto kern, int li) {
+    if (!attr_set[sizeof(T) == 8][li]) {
+      hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void *>(kern),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap());
+      if (e != hipSuccess) throw HipFail(e, __FILE__, __LINE__);
+      attr_set[sizeof(T) == 8][li] = true;
+    }
+    hipLaunchKernelGGL(kern, gt, b, lds, s, item_start, bk_start, nbk, bb, rec,
+                       h, R, I, M, part);
+  };
+  if (R <= 8) launch(k_bk_accum<T, 8>, 0);
+  else if (R <= 16) launch(k_bk_accum<T, 16>, 1);
+  else if (R <= 32) launch(k_bk_accum<T, 32>, 2);
+  else launch(k_bk_accum<T, 64>, 3);
+  CPR_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_bk_combine<T>), gt, b, 0, s, item_start, nbk, bb, R, I,
+                     part, M);
+  CPR_LAUNCH_CHECK();
+}
+int64_t bucket_max_items(int64_t rec_cap, int64_t nbk) {
+  return rec_cap / BK_SLICE + nbk + 1;
+}
+
+size_t bucket_record_bytes(int tsize) {
+  return tsize == 4 ? sizeof(BkRec<float>) : sizeof(BkRec<double>);
 }
 template void sampled_mttkrp<float>(const SampleWork &, int64_t,
                                     const int64_t *, const int32_t *,
