@@ -45,6 +45,7 @@ struct cp_ctx {
   int64_t P2[MAXN] = {};
   double *sts_lev = nullptr, *sts_cdf = nullptr, *sts_Z = nullptr;
   int64_t *sts_last = nullptr;
+  StsWork sw{};
   double *Gfull = nullptr, *Gp = nullptr, *ggt = nullptr, *trace = nullptr;
   double *pv_scratch = nullptr, *Gp1 = nullptr, *Gfull1 = nullptr;
   int32_t *sidx = nullptr;
@@ -272,7 +273,7 @@ void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
       ml.Z[0] = c->sts_Z;
       ml.last[0] = c->sts_last;
       sts_draw<T>(ml, J, c->R, c->F, uni, c->Gp, c->trace, c->sidx, c->prob,
-                  static_cast<T *>(c->h), c->d_err, c->s);
+                  static_cast<T *>(c->h), c->sw, c->d_err, c->s);
     } else {
       arls_draw<T>(ml, J, c->R, uni, c->sidx, c->prob, static_cast<T *>(c->h),
                    c->d_err, c->s);
@@ -438,6 +439,19 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     dalloc(c, &c->sts_cdf, mI * 8);
     dalloc(c, &c->sts_Z, 8);
     dalloc(c, &c->sts_last, 8);
+    int64_t mP2 = 1;
+    for (int k = 0; k < N; ++k) mP2 = std::max(mP2, c->P2[k]);
+    const int64_t Js = std::max<int64_t>(c->max_J, 1);
+    dalloc(c, &c->sw.h, (size_t)Js * sts_pad(R) * 8);
+    dalloc(c, &c->sw.tgt, Js * 8);
+    dalloc(c, &c->sw.mv, Js * 8);
+    dalloc(c, &c->sw.node, Js * 4);
+    dalloc(c, &c->sw.perm[0], Js * 4);
+    dalloc(c, &c->sw.perm[1], Js * 4);
+    dalloc(c, &c->sw.lc, 2 * mP2 * 4);
+    dalloc(c, &c->sw.rc, 2 * mP2 * 4);
+    dalloc(c, &c->sw.sbeg, 2 * mP2 * 4);
+    dalloc(c, &c->sw.send, 2 * mP2 * 4);
   }
   dalloc(c, &c->sigma, R * 8);
   dalloc(c, &c->Gfull, R * R * 8);

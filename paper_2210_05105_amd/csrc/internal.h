@@ -121,14 +121,26 @@ void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
                int32_t *sidx, double *prob, T *h, uint32_t *err, hipStream_t s);
 
 // ---- STS-CP (k_sts.hip)
-int sts_packed(int R);
+int sts_pad(int R);     // rank padded to the draw width (row stride of StsWork::h)
+int sts_packed(int R);  // doubles per tree node: packed upper triangle of sts_pad(R)
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
                hipStream_t s);
+// per-sample state of the level-by-level tree descent
+struct StsWork {
+  double *h;             // J x sts_pad(R): product of the rows drawn so far
+  double *tgt;           // J: target inside the current node
+  double *mv;            // J: mass of the current node
+  int32_t *node;         // J: current node (heap index)
+  int32_t *perm[2];      // J: slot -> sample, grouped by node
+  int32_t *lc, *rc;      // 2 P2: samples sent left / right from a node
+  int32_t *sbeg, *send;  // 2 P2: slot range of a node
+};
 template <typename T>
 void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,
               const double *Gp, const double *trace, int32_t *sidx,
-              double *prob, T *h, uint32_t *err, hipStream_t s);
+              double *prob, T *h, const StsWork &w, uint32_t *err,
+              hipStream_t s);
 
 // ---- sample merge, extraction, MTTKRP (k_mttkrp.hip)
 struct SampleWork {

@@ -3,6 +3,8 @@
 // inclusive prefix sums (the CDF) and total Z.  Draw (Alg. 3 without the
 // multinomial split and gather): one inverse-CDF search per (sample, factor),
 // index = min{ i : u Z < F(i) }.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace cpr {
@@ -11,57 +13,85 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 namespace {
 
-// l_i for 16 rows per wave: C = U_tile (16 x R) G^+ (R x R) on FP64 MFMA,
-// then l_i = sum_j C[i][j] U[i][j].
+// l_i for 16 rows per wave and tile: C = U_tile (16 x R) G^+ (R x R) on
+// FP64 MFMA, then l_i = sum_j C[i][j] U[i][j].  Waves stride over the row
+// tiles; the last row of positive mass is reduced per block and published
+// with one atomicMax.
 template <typename T, int NT>
 __global__ void __launch_bounds__(256)
 k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
            unsigned long long *last, uint32_t *err) {
-  const int l = lane_id();
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + threadIdx.x / WAVE) * 16;
-  if (row0 >= I) return;
-  const int Rp = NT * 16;
-  double4_t acc[NT];
+  __shared__ unsigned long long smax[4];
+  const int l = lane_id(), w = threadIdx.x / WAVE;
+  constexpr int Rp = NT * 16;
+  const int64_t ntiles = (I + 15) / 16;
+  unsigned long long mx = 0;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntiles;
+       tile += (int64_t)gridDim.x * 4) {
+    const int64_t row0 = tile * 16;
+    double4_t acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = double4_t{0, 0, 0, 0};
-  const int64_t ra = row0 + (l % 16);  // A operand row
-  for (int k0 = 0; k0 < Rp; k0 += 4) {
-    const int ka = k0 + l / 16;
-    const double a = (ra < I && ka < R) ? (double)U[ra * R + ka] : 0.0;
+    for (int t = 0; t < NT; ++t) acc[t] = double4_t{0, 0, 0, 0};
+    const int64_t ra = row0 + (l % 16);  // A operand row
+    const int64_t rac = ra < I ? ra : I - 1;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int jb = t * 16 + (l % 16);
-      const double b = (ka < R && jb < R) ? Gp[ka * R + jb] : 0.0;
-      acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-    }
-  }
-  // D[i][j] of v_mfma_f64_16x16x4f64: lane l, element v -> i = l / 16 + 4 v,
-  // j = l % 16
-  double s[4] = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < Rp; k0 += 4) {
+      const int ka = k0 + l / 16;
+      const int kac = ka < R ? ka : R - 1;
+      const double av = (double)U[rac * R + kac];
+      const double a = (ra < I && ka < R) ? av : 0.0;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int j = t * 16 + (l % 16);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = row0 + (l / 16) + 4 * v;
-      if (r < I && j < R) s[v] += acc[t][v] * (double)U[r * R + j];
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    for (int o = 1; o < 16; o <<= 1) s[v] += __shfl_xor(s[v], o, WAVE);
-  if ((l % 16) == 0) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = row0 + (l / 16) + 4 * v;
-      if (r < I) {
-        double x = s[v];
-        if (!isfinite(x)) atomicOr(err, ERR_NONFINITE);
-        x = x > 0 ? x : 0.0;
-        lev[r] = x;
-        if (x > 0) atomicMax(last, (unsigned long long)(r + 1));
+      for (int t = 0; t < NT; ++t) {
+        const int jb = t * 16 + (l % 16);
+        const int jbc = jb < R ? jb : R - 1;
+        const double bv = Gp[kac * R + jbc];
+        const double b = (ka < R && jb < R) ? bv : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
+    // D[i][j] of v_mfma_f64_16x16x4f64: lane l, element v -> i = l / 16 + 4 v,
+    // j = l % 16
+    double s[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int j = t * 16 + (l % 16);
+      const int jc = j < R ? j : R - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + (l / 16) + 4 * v;
+        const int64_t rc = r < I ? r : I - 1;
+        const double u = (double)U[rc * R + jc];
+        s[v] += (r < I && j < R) ? acc[t][v] * u : 0.0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int o = 1; o < 16; o <<= 1) s[v] += __shfl_xor(s[v], o, WAVE);
+    if ((l % 16) == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = row0 + (l / 16) + 4 * v;
+        if (r < I) {
+          double x = s[v];
+          if (!isfinite(x)) atomicOr(err, ERR_NONFINITE);
+          x = x > 0 ? x : 0.0;
+          lev[r] = x;
+          if (x > 0 && (unsigned long long)(r + 1) > mx)
+            mx = (unsigned long long)(r + 1);
+        }
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(mx, o, WAVE);
+    mx = y > mx ? y : mx;
+  }
+  if (l == 0) smax[w] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = smax[0];
+    for (int q = 1; q < 4; ++q) m = smax[q] > m ? smax[q] : m;
+    if (m) atomicMax(last, m);
   }
 }
 
@@ -131,7 +161,8 @@ void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
   void *scan_tmp = static_cast<char *>(tmp) + 256;
   zero_fill<int64_t>(reinterpret_cast<int64_t *>(lastp1), 1, s);
   const int nt = (R + 15) / 16;
-  const dim3 g(ceil_div(I, 64)), b(256);
+  const int64_t ntiles = (I + 15) / 16;
+  const dim3 g((unsigned)std::min<int64_t>(ceil_div(ntiles, 4), 512)), b(256);
   switch (nt) {
     case 1: hipLaunchKernelGGL((k_leverage<T, 1>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
     case 2: hipLaunchKernelGGL((k_leverage<T, 2>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;

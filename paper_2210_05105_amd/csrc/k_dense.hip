@@ -347,116 +347,137 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
 
 // ---------------------------------------------------------------------------
 // Row solve: X[i] = m G^+ + (m - (m G^+) G) G^+  (FP64), column sums of X^2.
-// A group of L lanes (L = smallest power of two >= R, at most 64) owns one
-// row at a time; lane c of the group owns columns c, c + L, ...
+// One wave per 16-row tile of M, on FP64 MFMA in transposed form:
+// X^T = (G^+)^T M^T.  With A = (G^+)^T (or G^T) and B = M^T, the accumulator
+// of tile t holds X[row0 + l % 16][16 t + l / 16 + 4 v] in lane l, element v,
+// which is also the B-operand layout of k-step 4 t + v of the next product,
+// so the residual R^T = M^T - G^T X^T and the correction
+// X^T += (G^+)^T R^T chain in registers.  A zero row of M gives an exactly
+// zero row of X.
 // ---------------------------------------------------------------------------
 constexpr int SV_THREADS = 256;
 constexpr int SV_MAXBLK = 1024;
 
-template <typename T, int L>
+template <int NT>
+__device__ __forceinline__ double afrag(const double *A, int R, int t, int ks,
+                                        int l) {
+  // (A^T)[i][k] of tile t, k-step ks: i = 16 t + l % 16, k = 4 ks + l / 16
+  const int i = 16 * t + (l % 16), k = 4 * ks + l / 16;
+  const int ic = i < R ? i : R - 1, kc = k < R ? k : R - 1;
+  const double v = A[kc * R + ic];
+  return (i < R && k < R) ? v : 0.0;
+}
+
+template <typename T, int NT>
 __global__ void __launch_bounds__(SV_THREADS)
-k_solve(const T *M, int64_t I, int R, const double *Gg, const double *Gpg,
+k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         double *X, double *partial, int64_t *rows_out) {
-  // G and G^+ are read R times per row: stage them in LDS when they fit
-  extern __shared__ double gl_lds[];
-  const double *G = Gg, *Gp = Gpg;
-  if (R <= 48) {
-    for (int e = threadIdx.x; e < R * R; e += SV_THREADS) {
-      gl_lds[e] = Gg[e];
-      gl_lds[R * R + e] = Gpg[e];
-    }
-    __syncthreads();
-    G = gl_lds;
-    Gp = gl_lds + R * R;
-  }
-  constexpr int CPL = (MAXR + L - 1) / L;  // columns per lane (max)
-  constexpr int GPW = WAVE / L;            // groups per wave
+  constexpr int KS = 4 * NT;          // k-steps
+  constexpr bool REG = NT <= 2;       // G, G^+ fragments held in registers
   const int l = lane_id(), w = threadIdx.x / WAVE;
-  const int gl = l % L, gbase = l - gl;
-  const int64_t group = ((int64_t)blockIdx.x * (SV_THREADS / WAVE) + w) * GPW + l / L;
-  const int64_t ngroups = (int64_t)gridDim.x * (SV_THREADS / WAVE) * GPW;
-  const int ncl = (R + L - 1) / L;
-  double ss[CPL];
+  double gpf[REG ? NT * KS : 1], gf[REG ? NT * KS : 1];
+  if (REG) {
 #pragma unroll
-  for (int t = 0; t < CPL; ++t) ss[t] = 0;
-  int nrows = 0;  // nonzero rows handled by this group (counted on lane gl 0)
-  for (int64_t i = group; i < I; i += ngroups) {
-    double m[CPL], x[CPL], r[CPL];
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        gpf[t * KS + ks] = afrag<NT>(Gp, R, t, ks, l);
+        gf[t * KS + ks] = afrag<NT>(G, R, t, ks, l);
+      }
+  }
+  double ss[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ss[t][v] = 0.0;
+  int nrows = 0;
+  const int64_t ntiles = (I + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
+       tile < ntiles; tile += (int64_t)gridDim.x * (SV_THREADS / WAVE)) {
+    const int64_t row = tile * 16 + (l % 16);
+    const int64_t rc = row < I ? row : I - 1;
+    // B fragments of M^T: M[row][4 ks + l / 16]
+    double mf[KS];
     bool nz = false;
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-      int c = gl + t * L;
-      m[t] = (t < ncl && c < R) ? (double)M[i * R + c] : 0.0;
-      nz |= (m[t] != 0.0);
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + l / 16;
+      const int kc = k < R ? k : R - 1;
+      const double v = (double)M[rc * R + kc];
+      mf[ks] = (row < I && k < R) ? v : 0.0;
+      nz |= (mf[ks] != 0.0);
     }
-    // all lanes of the group take the same branch
-    uint64_t any = __ballot(nz);
-    uint64_t gmask = (L == 64) ? ~0ull : (((1ull << L) - 1) << gbase);
-    if (!(any & gmask)) {
+    const uint64_t b = __ballot(nz);
+    nrows += __popcll((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xffffull);
+    // X^T = G^+ M^T
+    double4_t ax[NT];
 #pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        int c = gl + t * L;
-        if (t < ncl && c < R) X[i * R + c] = 0.0;
-      }
-      continue;
-    }
-    nrows += (gl == 0);
-    // x = m G^+
+    for (int t = 0; t < NT; ++t) {
+      ax[t] = double4_t{0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) x[t] = 0;
-    for (int a = 0; a < R; ++a) {
-      double ma = __shfl(m[a / L], gbase + a % L, WAVE);
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        int c = gl + t * L;
-        if (t < ncl && c < R) x[t] += ma * Gp[a * R + c];
+      for (int ks = 0; ks < KS; ++ks) {
+        const double a = REG ? gpf[t * KS + ks] : afrag<NT>(Gp, R, t, ks, l);
+        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, mf[ks], ax[t], 0, 0, 0);
       }
     }
-    // r = m - x G
+    // R^T = M^T - G X^T
+    double rf[KS];
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) r[t] = m[t];
-    for (int a = 0; a < R; ++a) {
-      double xa = __shfl(x[a / L], gbase + a % L, WAVE);
+    for (int t = 0; t < NT; ++t) {
+      double4_t ar = double4_t{0, 0, 0, 0};
 #pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        int c = gl + t * L;
-        if (t < ncl && c < R) r[t] -= xa * G[a * R + c];
+      for (int ks = 0; ks < KS; ++ks) {
+        const double a = REG ? gf[t * KS + ks] : afrag<NT>(G, R, t, ks, l);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ax[ks / 4][ks % 4], ar,
+                                                  0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rf[4 * t + v] = mf[4 * t + v] - ar[v];
+    }
+    // X^T += G^+ R^T
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const double a = REG ? gpf[t * KS + ks] : afrag<NT>(Gp, R, t, ks, l);
+        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rf[ks], ax[t], 0, 0, 0);
       }
     }
-    // x += r G^+
-    for (int a = 0; a < R; ++a) {
-      double ra = __shfl(r[a / L], gbase + a % L, WAVE);
+    if (row < I) {
 #pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        int c = gl + t * L;
-        if (t < ncl && c < R) x[t] += ra * Gp[a * R + c];
-      }
-    }
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-      int c = gl + t * L;
-      if (t < ncl && c < R) {
-        X[i * R + c] = x[t];
-        ss[t] += x[t] * x[t];
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * t + l / 16 + 4 * v;
+          if (c < R) {
+            X[row * R + c] = ax[t][v];
+            ss[t][v] += ax[t][v] * ax[t][v];
+          }
+        }
     }
   }
   if (rows_out) {
-    int nr = nrows;
-    for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o, WAVE);
-    if (l == 0 && nr) atomicAdd((unsigned long long *)rows_out,
-                                (unsigned long long)nr);
+    __shared__ int cnt[SV_THREADS / WAVE];
+    if (l == 0) cnt[w] = nrows;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int n = 0;
+      for (int q = 0; q < SV_THREADS / WAVE; ++q) n += cnt[q];
+      if (n) atomicAdd((unsigned long long *)rows_out, (unsigned long long)n);
+    }
   }
-  // fixed-order reduction of the per-lane column sums: groups within a wave
+  // fixed-order reduction of the column sums: the 16 row lanes of a column
   // (shuffle tree), then waves (LDS, in wave order)
   __shared__ double red[SV_THREADS / WAVE][MAXR];
 #pragma unroll
-  for (int t = 0; t < CPL; ++t) {
-    double v = ss[t];
-    for (int o = L; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
-    int c = gl + t * L;
-    if (l < L && t < ncl && c < R) red[w][c] = v;
-  }
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double s = ss[t][v];
+      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, WAVE);
+      const int c = 16 * t + l / 16 + 4 * v;
+      if ((l % 16) == 0 && c < R) red[w][c] = s;
+    }
   __syncthreads();
   for (int c = threadIdx.x; c < R; c += SV_THREADS) {
     double v = 0;
@@ -575,7 +596,8 @@ void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
 }
 
 int solve_blocks(int64_t I) {
-  return (int)std::min<int64_t>(SV_MAXBLK, std::max<int64_t>(1, (I + 15) / 16));
+  // about four 16-row tiles per block (one per wave) or more
+  return (int)std::min<int64_t>(SV_MAXBLK, std::max<int64_t>(1, (I + 63) / 64));
 }
 
 template <typename T>
@@ -583,15 +605,16 @@ void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
                 const double *Gp, double *X, double *partial, int nblk,
                 int64_t *rows_out, hipStream_t s) {
   const dim3 g(nblk), b(SV_THREADS);
-  const size_t lds = R <= 48 ? (size_t)2 * R * R * sizeof(double) : 0;
-  if (R <= 8)
-    hipLaunchKernelGGL((k_solve<T, 8>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
-  else if (R <= 16)
-    hipLaunchKernelGGL((k_solve<T, 16>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
-  else if (R <= 32)
-    hipLaunchKernelGGL((k_solve<T, 32>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
-  else
-    hipLaunchKernelGGL((k_solve<T, 64>), g, b, lds, s, M, I, R, Gfull, Gp, X, partial, rows_out);
+  switch ((R + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_solve<T, 1>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 2: hipLaunchKernelGGL((k_solve<T, 2>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 3: hipLaunchKernelGGL((k_solve<T, 3>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 4: hipLaunchKernelGGL((k_solve<T, 4>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 5: hipLaunchKernelGGL((k_solve<T, 5>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 6: hipLaunchKernelGGL((k_solve<T, 6>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    case 7: hipLaunchKernelGGL((k_solve<T, 7>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+    default: hipLaunchKernelGGL((k_solve<T, 8>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
+  }
   CPR_LAUNCH_CHECK();
 }
 template void solve_rows<float>(const float *, int64_t, int, const double *,

@@ -165,11 +165,29 @@ __global__ void k_cols(const uint64_t *hi, int64_t n, int lo_bits,
   col_ptr[cid[p]] = p;
 }
 
-__global__ void k_max_col(const int64_t *col_ptr, int64_t n_cols,
-                          unsigned long long *mx) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cols) return;
-  atomicMax(mx, (unsigned long long)(col_ptr[c + 1] - col_ptr[c]));
+// longest column: grid-stride per thread, then wave and block maxima and
+// one atomicMax per block (same-address atomics serialise)
+__global__ void __launch_bounds__(256)
+k_max_col(const int64_t *col_ptr, int64_t n_cols, unsigned long long *mx) {
+  __shared__ unsigned long long sm[4];
+  unsigned long long m = 0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n_cols;
+       c += (int64_t)gridDim.x * 256) {
+    const unsigned long long len =
+        (unsigned long long)(col_ptr[c + 1] - col_ptr[c]);
+    m = len > m ? len : m;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(m, o, WAVE);
+    m = y > m ? y : m;
+  }
+  if (lane_id() == 0) sm[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q) m = sm[q] > m ? sm[q] : m;
+    m = sm[0] > m ? sm[0] : m;
+    if (m) atomicMax(mx, m);
+  }
 }
 
 struct DevBuf {
@@ -302,7 +320,9 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemsetAsync(mx.p, 0, 8, s) != hipSuccess)
     return "hip error while building the mode index";
-  hipLaunchKernelGGL(k_max_col, dim3(ceil_div(out.n_cols, 256)), b1, 0, s,
+  hipLaunchKernelGGL(k_max_col,
+                     dim3((unsigned)std::min<int64_t>(ceil_div(out.n_cols, 256), 512)),
+                     dim3(256), 0, s,
                      out.col_ptr, out.n_cols,
                      mx.get<unsigned long long>());
   CPR_LAUNCH_CHECK();
