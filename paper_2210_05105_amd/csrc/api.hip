@@ -443,13 +443,14 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     for (int k = 0; k < N; ++k) mP2 = std::max(mP2, c->P2[k]);
     const int64_t Js = std::max<int64_t>(c->max_J, 1);
     dalloc(c, &c->sw.h, (size_t)Js * sts_pad(R) * 8);
-    dalloc(c, &c->sw.tgt, Js * 8);
-    dalloc(c, &c->sw.mv, Js * 8);
-    dalloc(c, &c->sw.node, Js * 4);
-    dalloc(c, &c->sw.perm[0], Js * 4);
-    dalloc(c, &c->sw.perm[1], Js * 4);
-    dalloc(c, &c->sw.lc, 2 * mP2 * 4);
-    dalloc(c, &c->sw.rc, 2 * mP2 * 4);
+    for (int b = 0; b < 2; ++b) {
+      dalloc(c, &c->sw.slot[b].s, Js * 4);
+      dalloc(c, &c->sw.slot[b].v, Js * 4);
+      dalloc(c, &c->sw.slot[b].t, Js * 8);
+      dalloc(c, &c->sw.slot[b].m, Js * 8);
+    }
+    dalloc(c, &c->sw.lc, sts_counters(mP2) * 4);
+    dalloc(c, &c->sw.rc, sts_counters(mP2) * 4);
     dalloc(c, &c->sw.sbeg, 2 * mP2 * 4);
     dalloc(c, &c->sw.send, 2 * mP2 * 4);
   }

@@ -122,18 +122,22 @@ void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
 
 // ---- STS-CP (k_sts.hip)
 int sts_pad(int R);     // rank padded to the draw width (row stride of StsWork::h)
+int64_t sts_counters(int64_t P2);  // entries of StsWork::lc and ::rc
 int sts_packed(int R);  // doubles per tree node: packed upper triangle of sts_pad(R)
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
                hipStream_t s);
-// per-sample state of the level-by-level tree descent
+// per-slot record of the level-by-level tree descent (slots grouped by node)
+struct SlotBuf {
+  int32_t *s;  // sample
+  int32_t *v;  // current node (heap index)
+  double *t;   // target inside the node
+  double *m;   // mass of the node
+};
 struct StsWork {
   double *h;             // J x sts_pad(R): product of the rows drawn so far
-  double *tgt;           // J: target inside the current node
-  double *mv;            // J: mass of the current node
-  int32_t *node;         // J: current node (heap index)
-  int32_t *perm[2];      // J: slot -> sample, grouped by node
-  int32_t *lc, *rc;      // 2 P2: samples sent left / right from a node
+  SlotBuf slot[2];       // J records, double-buffered across levels
+  int32_t *lc, *rc;      // sts_counters(P2): samples sent left / right
   int32_t *sbeg, *send;  // 2 P2: slot range of a node
 };
 template <typename T>

@@ -25,6 +25,15 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // it with exact zeros beyond R.
 int sts_pad(int R) { return 16 * ((R + 15) / 16); }
 
+// Placement counter of node v.  Every block updates the counters of the top
+// nodes, so those get a 128-byte line each; deeper nodes are packed.
+constexpr int64_t CTOP = 1024, CLINE = 32;
+__host__ __device__ __forceinline__ int64_t cslot(int64_t v) {
+  return v < CTOP ? v * CLINE : CTOP * CLINE + (v - CTOP);
+}
+
+int64_t sts_counters(int64_t P2) { return CTOP * CLINE + 2 * P2; }
+
 int sts_packed(int R) {
   const int RP = sts_pad(R);
   return RP * (RP + 1) / 2;
@@ -36,6 +45,7 @@ __device__ __forceinline__ int packed_index(int a, int b, int R) {
   // a <= b; row-major upper triangle
   return a * (2 * R - a + 1) / 2 + (b - a);
 }
+
 
 // ---------------------------------------------------------------------------
 // Build: leaf Grams on FP64 MFMA (one wave per leaf), then the subtree of
@@ -131,34 +141,29 @@ __global__ void k_tree_level(double *tree, int64_t first, int64_t cnt, int P) {
 // ---------------------------------------------------------------------------
 constexpr int ST = 256;
 
-// B fragments of an R x R row-major matrix, zeros beyond R
-template <int NT>
-__device__ __forceinline__ void load_bfrag(const double *A, int R,
-                                           double (&f)[NT][4 * NT]) {
-  const int l = lane_id();
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int ks = 0; ks < 4 * NT; ++ks) {
-      const int k = 4 * ks + l / 16, j = 16 * t + (l % 16);
-      const int kc = k < R ? k : R - 1, jc = j < R ? j : R - 1;
-      const double v = A[kc * R + jc];
-      f[t][ks] = (k < R && j < R) ? v : 0.0;
-    }
+// R x R row-major matrix into LDS as RP x RP with zeros beyond R (block-wide;
+// a barrier must follow)
+template <int RP>
+__device__ __forceinline__ void stage_pad(double *dst, const double *A, int R) {
+  for (int e = threadIdx.x; e < RP * RP; e += ST) {
+    const int a = e / RP, b = e % RP;
+    const int ac = a < R ? a : R - 1, bc = b < R ? b : R - 1;
+    const double x = A[ac * R + bc];  // unconditional load, then mask
+    dst[e] = (a < R && b < R) ? x : 0.0;
+  }
 }
 
-// packed-node offsets of the B fragments (node symmetric, upper triangle)
+// B fragments of a zero-padded RP x RP matrix held in LDS
 template <int NT>
-__device__ __forceinline__ void node_offsets(int (&off)[NT][4 * NT]) {
+__device__ __forceinline__ void lds_bfrag(const double *sA,
+                                          double (&f)[NT][4 * NT]) {
   constexpr int RP = 16 * NT;
   const int l = lane_id();
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int ks = 0; ks < 4 * NT; ++ks) {
-      const int k = 4 * ks + l / 16, j = 16 * t + (l % 16);
-      off[t][ks] = k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP);
-    }
+    for (int ks = 0; ks < 4 * NT; ++ks)
+      f[t][ks] = sA[(4 * ks + l / 16) * RP + 16 * t + (l % 16)];
 }
 
 // masses of the 16 rows: lanes of group l / 16 get row l / 16 + 4 v in ms[v]
@@ -215,11 +220,12 @@ __device__ __forceinline__ double lane_mass(const double (&ms)[4]) {
 
 // First factor (h = 1): every sample shares one conditional law, held as a
 // flat CDF of the row masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)}.
-template <typename T>
+template <typename T, int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
             const int64_t *lastp, const double *uni, int nq, int64_t J,
-            int32_t *sidx, double *hbuf, int HS, uint32_t *err) {
+            int32_t *sidx, double *hbuf, uint32_t *err) {
+  constexpr int RP = 16 * NT;
   const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
   if (s >= J) return;
   double u = uni[s * nq];
@@ -237,46 +243,53 @@ k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
   if (lo > last) lo = last;
   if (lo < 0) lo = 0;
   sidx[s * nq] = (int32_t)lo;
-  for (int a = 0; a < HS; ++a)
-    hbuf[s * HS + a] = (a < R) ? (double)U[lo * R + a] : 0.0;
+  const T *ur = U + lo * R;
+  double2 *h2 = reinterpret_cast<double2 *>(hbuf + s * RP);
+#pragma unroll
+  for (int a = 0; a < RP; a += 2) {
+    const int a0 = a < R ? a : R - 1, a1 = a + 1 < R ? a + 1 : R - 1;
+    const double x0 = (double)ur[a0], x1 = (double)ur[a1];
+    h2[a / 2] = double2{a < R ? x0 : 0.0, a + 1 < R ? x1 : 0.0};
+  }
 }
 
-// Root of a tree factor: node mass Z(h) and target t = u Z; clears the
-// per-node placement counters of this factor's tree.
+// Root of a tree factor: node mass Z(h) and target t = u Z; slot s holds
+// sample s; clears the per-node placement counters of this factor's tree.
+// 16 samples per wave (lanes 0..15), one MFMA tile.
 template <int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
            const double *uni, int q, int nq, int64_t J, StsWork w,
-           uint32_t *err) {
+           SlotBuf out, uint32_t *err) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
-  const int64_t g = (int64_t)blockIdx.x * ST + threadIdx.x;
-  for (int64_t i = g; i < 2 * P2; i += (int64_t)gridDim.x * ST) {
+  __shared__ double sQ[RP * RP];  // G_{>k} (*) G^root, zeros beyond R
+  const int64_t g0 = (int64_t)blockIdx.x * ST + threadIdx.x;
+  for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * ST) {
     w.lc[i] = 0;
     w.rc[i] = 0;
   }
-  if (g == 0) {
+  if (g0 == 0) {
     w.sbeg[1] = 0;
     w.send[1] = (int32_t)J;
   }
-  if ((int64_t)blockIdx.x * ST + (threadIdx.x & ~(WAVE - 1)) >= J) return;
-  const bool act = g < J;
-  const int32_t s = act ? (int32_t)g : 0;
-  double qB[NT][4 * NT];
-  int off[NT][4 * NT];
-  load_bfrag<NT>(Gg, R, qB);
-  node_offsets<NT>(off);
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int ks = 0; ks < 4 * NT; ++ks) qB[t][ks] *= tree[P + off[t][ks]];
-  double Z = 0.0;
-  for (int tau = 0; tau < 4; ++tau) {
-    double xA[4 * NT], xD[NT][4], ms[4];
-    load_hfrag<NT>(w.h, s, tau, xA, xD);
-    tile_mass<NT>(xA, xD, qB, ms);
-    const double m = lane_mass(ms);
-    if ((lane_id() >> 4) == tau) Z = m;
+  stage_pad<RP>(sQ, Gg, R);
+  __syncthreads();
+  for (int e = threadIdx.x; e < RP * RP; e += ST) {
+    const int a = e / RP, b = e % RP;
+    sQ[e] *= tree[P + (a <= b ? packed_index(a, b, RP) : packed_index(b, a, RP))];
   }
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
+  if (p0 >= J) return;
+  const int64_t g = p0 + l;
+  const bool act = l < 16 && g < J;
+  const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
+  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
+  lds_bfrag<NT>(sQ, qB);
+  load_hfrag<NT>(w.h, s, 0, xA, xD);
+  tile_mass<NT>(xA, xD, qB, ms);
+  const double Z = lane_mass(ms);
   if (!act) return;
   double u = uni[g * nq + q];
   if (!(u >= 0.0 && u < 1.0)) {
@@ -284,74 +297,88 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
     u = 0.0;
   }
   if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
-  w.tgt[g] = u * Z;
-  w.mv[g] = Z;
-  w.node[g] = 1;
-  w.perm[0][g] = (int32_t)g;
+  out.s[g] = (int32_t)g;
+  out.v[g] = 1;
+  out.t[g] = u * Z;
+  out.m[g] = Z;
 }
 
-// One level: lane p takes the sample in slot p; per 16-slot tile and per
-// distinct node v among its slots, the masses of the left child 2v.  Go
-// right iff that mass is not positive, or the target is at or past it and
-// the right child has mass; then place the sample in its child's range.
+// One level.  A block owns 64 consecutive slots; wave i takes slots
+// 16 i .. 16 i + 15 in lanes 0..15 and, per distinct node v among them, the
+// masses of the left child 2v on MFMA.  Go right iff that mass is not
+// positive, or the target is at or past it and the right child has mass.
+// Wave 0 then places the block's 64 samples in their children's slot
+// ranges with one atomic per (node, side).
 template <int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
-            StsWork w, const int32_t *pin, int32_t *pout, int level) {
+            StsWork w, SlotBuf in, SlotBuf out) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
-  const int64_t p = (int64_t)blockIdx.x * ST + threadIdx.x;
-  if ((int64_t)blockIdx.x * ST + (threadIdx.x & ~(WAVE - 1)) >= J) return;
-  const int l = lane_id();
-  const bool act = p < J;
-  const int32_t s = act ? pin[p] : 0;
-  const int32_t v = act ? w.node[s] : (int32_t)(1 << level);
-  int32_t beg, end;  // slot range of node v
-  if (v == 1) {
-    beg = w.sbeg[1];
-    end = w.send[1];
-  } else {
-    const int32_t par = v >> 1, pb = w.sbeg[par], nl = w.lc[par];
-    if (v & 1) {
-      beg = pb + nl;
-      end = w.send[par];
-    } else {
-      beg = pb;
-      end = pb + nl;
-    }
-  }
+  __shared__ int32_t sh_s[64], sh_v[64], sh_beg[64], sh_end[64];
+  __shared__ double sh_t[64], sh_m[64];
+  __shared__ int32_t sh_r[64];
+  __shared__ double sG[RP * RP];  // G_{>k}, zeros beyond R
+  const int64_t pb = (int64_t)blockIdx.x * 64;
+  if (pb >= J) return;
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  const int64_t p = pb + 16 * wv + l;
+  const bool act = l < 16 && p < J;
+  // slot record (clamped slot; inactive lanes are ignored), issued before
+  // the staging barrier
+  const int64_t pc = p < J ? p : J - 1;
+  const int32_t s = in.s[pc];
+  const int32_t v = in.v[pc];
+  double t = in.t[pc], m = in.m[pc];
+  stage_pad<RP>(sG, Gg, R);
+  // slot range of node v: the root's, or the parent's split at its left count
+  const int32_t par = v > 1 ? v >> 1 : 1;
+  const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
+  // h fragments of the 16 slots and the node of slot 0, loaded together
+  double xA[4 * NT], xD[NT][4];
+  load_hfrag<NT>(w.h, s, 0, xA, xD);
+  const uint64_t actm = __ballot(act);
+  const int ld0 = actm ? __ffsll((long long)actm) - 1 : 0;
+  int32_t v0 = __shfl(v, ld0, WAVE);
+  double nv[NT][4 * NT];
+  auto load_node = [&](int32_t vn) {
+    const double *nd = tree + (int64_t)(2 * vn) * P;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int ks = 0; ks < 4 * NT; ++ks) {
+        const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
+        nv[tt][ks] = nd[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
+      }
+  };
+  load_node(v0);
+  __syncthreads();
+  const int32_t beg = v == 1 ? pbg : (v & 1) ? pbg + nl : pbg;
+  const int32_t end = v == 1 ? pen : (v & 1) ? pen : pbg + nl;
   if (act && p == beg) {
     w.sbeg[v] = beg;
     w.send[v] = end;
   }
-  double gB[NT][4 * NT];
-  int off[NT][4 * NT];
-  load_bfrag<NT>(Gg, R, gB);
-  node_offsets<NT>(off);
-  const uint64_t actm = __ballot(act);
   double mL = 0.0;
-  for (int tau = 0; tau < 4; ++tau) {
-    uint64_t rem = actm & (0xffffull << (16 * tau));
-    if (!rem) continue;
-    double xA[4 * NT], xD[NT][4];
-    load_hfrag<NT>(w.h, s, tau, xA, xD);
-    while (rem) {
-      const int ld = __ffsll((long long)rem) - 1;
-      const int32_t v0 = __shfl(v, ld, WAVE);
-      const uint64_t grp = __ballot(v == v0) & rem;
-      const double *nd = tree + (int64_t)(2 * v0) * P;
-      double qB[NT][4 * NT], ms[4];
+  uint64_t rem = actm;
+  while (rem) {
+    const uint64_t grp = __ballot(v == v0) & rem;
+    double qB[NT][4 * NT], ms[4];
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int ks = 0; ks < 4 * NT; ++ks)
-          qB[t][ks] = gB[t][ks] * nd[off[t][ks]];
-      tile_mass<NT>(xA, xD, qB, ms);
-      const double m = lane_mass(ms);
-      if ((grp >> l) & 1ull) mL = m;
-      rem &= ~grp;
+      for (int ks = 0; ks < 4 * NT; ++ks) {
+        const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
+        qB[tt][ks] = sG[k * RP + j] * nv[tt][ks];
+      }
+    tile_mass<NT>(xA, xD, qB, ms);
+    const double x = lane_mass(ms);
+    if ((grp >> l) & 1ull) mL = x;
+    rem &= ~grp;
+    if (rem) {
+      v0 = __shfl(v, __ffsll((long long)rem) - 1, WAVE);
+      load_node(v0);
     }
   }
-  double t = act ? w.tgt[s] : 0.0, m = act ? w.mv[s] : 0.0;
   const bool right = mL <= 0 || (t >= mL && m - mL > 0);
   if (right) {
     t -= (mL > 0 ? mL : 0.0);
@@ -359,143 +386,197 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   } else {
     m = mL;
   }
-  if (act) {
-    w.tgt[s] = t;
-    w.mv[s] = m;
-    w.node[s] = 2 * v + (right ? 1 : 0);
+  if (l < 16) {
+    const int i = 16 * wv + l;
+    sh_s[i] = s;
+    sh_v[i] = v;
+    sh_beg[i] = beg;
+    sh_end[i] = end;
+    sh_t[i] = t;
+    sh_m[i] = m;
+    sh_r[i] = right ? 1 : 0;
   }
-  // one atomic per (wave, node, side)
-  uint64_t todo = actm;
-  const uint64_t rm = __ballot(act && right);
+  __syncthreads();
+  if (wv != 0) return;
+  // placement of the block's 64 slots (lane i = slot pb + i): left children
+  // fill a node's range from the front, right children from the back
+  const bool a2 = pb + l < J;
+  const int32_t v2 = sh_v[l], b2 = sh_beg[l], e2 = sh_end[l];
+  const bool r2 = sh_r[l] != 0;
+  uint64_t todo = __ballot(a2);
+  const uint64_t rm = __ballot(a2 && r2);
   const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
   int32_t pos = 0;
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
-    const int32_t v0 = __shfl(v, leader, WAVE);
-    const uint64_t grp = __ballot(act && v == v0) & todo;
+    const int32_t v0 = __shfl(v2, leader, WAVE);
+    const uint64_t grp = __ballot(a2 && v2 == v0) & todo;
     const uint64_t gl = grp & ~rm, gr = grp & rm;
     int32_t bl = 0, br = 0;
     if (l == leader) {
-      if (gl) bl = atomicAdd(&w.lc[v0], (int32_t)__popcll(gl));
-      if (gr) br = atomicAdd(&w.rc[v0], (int32_t)__popcll(gr));
+      if (gl) bl = atomicAdd(&w.lc[cslot(v0)], (int32_t)__popcll(gl));
+      if (gr) br = atomicAdd(&w.rc[cslot(v0)], (int32_t)__popcll(gr));
     }
     bl = __shfl(bl, leader, WAVE);
     br = __shfl(br, leader, WAVE);
     if ((grp >> l) & 1ull)
-      pos = right ? end - 1 - (br + (int32_t)__popcll(gr & below))
-                  : beg + bl + (int32_t)__popcll(gl & below);
+      pos = r2 ? e2 - 1 - (br + (int32_t)__popcll(gr & below))
+               : b2 + bl + (int32_t)__popcll(gl & below);
     todo &= ~grp;
   }
-  if (act) pout[pos] = s;
+  if (a2) {
+    out.s[pos] = sh_s[l];
+    out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
+    out.t[pos] = sh_t[l];
+    out.m[pos] = sh_m[l];
+  }
 }
 
-// Leaf: one wave per 16 slots, one sample at a time.  Row masses
-// (U[i] (*) h)^T G_{>k} (U[i] (*) h) for 16 rows per MFMA tile, accumulated
-// in row order; index = min{i : t < F(i)} over rows of positive mass, then
-// h *= U[index].
+// Leaf: one wave per 16 slots, the 16 samples side by side (lane i and the
+// rows i of the MFMA tiles belong to slot i).  Pass r computes the masses
+// (U[row0 + r] (*) h)^T G_{>k} (U[row0 + r] (*) h) of row r of every
+// sample's leaf; each sample accumulates its rows in order and takes
+// index = min{i : t < F(i)} over rows of positive mass.  Then h *= U[index].
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
-           int64_t J, StsWork w, const int32_t *pin, int q, int nq,
-           int32_t *sidx, uint32_t *err) {
+           int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
+           uint32_t *err) {
   constexpr int RP = 16 * NT, KS = 4 * NT;
+  __shared__ double sG[RP * RP];
+  stage_pad<RP>(sG, Gg, R);
+  __syncthreads();
   const int l = lane_id();
   const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
   if (p0 >= J) return;
-  double gB[NT][KS];
-  load_bfrag<NT>(Gg, R, gB);
-  const int64_t pend = p0 + 16 < J ? p0 + 16 : J;
-  for (int64_t p = p0; p < pend; ++p) {
-    const int32_t s = pin[p];
-    const int64_t row0 = (int64_t)(w.node[s] - P2) * F;
-    const double *hrow = w.h + (int64_t)s * RP;
-    const double t = w.tgt[s];
-    double hk[KS], hj[NT];
+  const int n = J - p0 < 16 ? (int)(J - p0) : 16;
+  // lane l holds slot l % 16 (slot 0 stands in beyond n)
+  const int64_t ps = p0 + ((l % 16) < n ? (l % 16) : 0);
+  const int32_t s = in.s[ps];
+  const int64_t row0 = (int64_t)(in.v[ps] - P2) * F;
+  const double t = in.t[ps];
+  double gB[NT][KS], hA[KS], hD[NT][4];
+  lds_bfrag<NT>(sG, gB);
+  load_hfrag<NT>(w.h, s, 0, hA, hD);
+  int64_t r0D[4];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) hk[ks] = hrow[4 * ks + l / 16];
+  for (int v = 0; v < 4; ++v) r0D[v] = __shfl(row0, l / 16 + 4 * v, WAVE);
+  // raw U fragments of row r of every slot's leaf, four rows in flight
+  struct RowBuf {
+    T a[KS];      // U[row0 + r][4 ks + l / 16]
+    T d[NT][4];   // U[row0(slot l / 16 + 4 v) + r][16 t + l % 16]
+  };
+  auto load_row = [&](int r, RowBuf &b) {
+    r = r < F ? r : F - 1;
+    const int64_t row = row0 + r;
+    const T *ur = U + (row < I ? row : I - 1) * R;
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) hj[tt] = hrow[16 * tt + (l % 16)];
-    double pre = 0.0;
-    int pick = -1, lastpos = -1;
-    for (int sub = 0; sub < F && pick < 0; sub += 16) {
-      const int64_t rb = row0 + sub;
-      if (rb >= I) break;
-      double xA[KS], xD[NT][4], ms[4];
-      {
-        const int64_t r = rb + (l % 16);
-        const int64_t rc = r < I ? r : I - 1;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + l / 16;
+      b.a[ks] = ur[k < R ? k : R - 1];
+    }
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const int k = 4 * ks + l / 16, kc = k < R ? k : R - 1;
-          const double x = (double)U[rc * R + kc] * hk[ks];
-          xA[ks] = r < I ? x : 0.0;
-        }
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int64_t rw = r0D[v] + r;
+      const T *uw = U + (rw < I ? rw : I - 1) * R;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = rb + l / 16 + 4 * v;
-        const int64_t rc = r < I ? r : I - 1;
-#pragma unroll
-        for (int tt = 0; tt < NT; ++tt) {
-          const int j = 16 * tt + (l % 16), jc = j < R ? j : R - 1;
-          const double x = (double)U[rc * R + jc] * hj[tt];
-          xD[tt][v] = r < I ? x : 0.0;
-        }
-      }
-      tile_mass<NT>(xA, xD, gB, ms);
-      // row order over the 16 rows (every lane runs the same scan)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const double mi = __shfl(ms[i / 4], (i % 4) * 16, WAVE);
-        if (pick < 0 && rb + i < I && mi > 0) {
-          pre += mi;
-          lastpos = sub + i;
-          if (t < pre) pick = sub + i;
-        }
+      for (int tt = 0; tt < NT; ++tt) {
+        const int j = 16 * tt + (l % 16);
+        b.d[tt][v] = uw[j < R ? j : R - 1];
       }
     }
+  };
+  double pre = 0.0;
+  int pick = -1, lastpos = -1;
+  // masses of row r from b, then b refilled with row r + 4
+  auto pass = [&](int r, RowBuf &b) {
+    double xA[KS], xD[NT][4], ms[4];
+    {
+      const double mask = row0 + r < I ? 1.0 : 0.0;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) xA[ks] = (double)b.a[ks] * hA[ks] * mask;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double mask = r0D[v] + r < I ? 1.0 : 0.0;
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+        xD[tt][v] = (double)b.d[tt][v] * hD[tt][v] * mask;  // h zero beyond R
+    }
+    load_row(r + 4, b);
+    tile_mass<NT>(xA, xD, gB, ms);
+    const double m = lane_mass(ms);  // lanes 0..15: row r of slot l
+    if (pick < 0 && row0 + r < I && m > 0) {
+      pre += m;
+      lastpos = r;
+      if (t < pre) pick = r;
+    }
+  };
+  RowBuf b0, b1, b2, b3;
+  load_row(0, b0);
+  load_row(1, b1);
+  load_row(2, b2);
+  load_row(3, b3);
+  for (int r = 0; r < F; r += 4) {  // F is a multiple of 16
+    pass(r, b0);
+    pass(r + 1, b1);
+    pass(r + 2, b2);
+    pass(r + 3, b3);
+  }
+  const bool act = l < n;
+  if (pick < 0) {
+    pick = lastpos;
     if (pick < 0) {
-      pick = lastpos;
-      if (pick < 0) {
-        pick = 0;
-        if (l == 0) atomicOr(err, ERR_ZERO_MASS);
-      }
+      pick = 0;
+      if (act) atomicOr(err, ERR_ZERO_MASS);
     }
-    int64_t idx = row0 + pick;
-    if (idx >= I) idx = I - 1;
-    if (l == 0) sidx[(int64_t)s * nq + q] = (int32_t)idx;
-    if (l < RP) {
-      const int lc = l < R ? l : R - 1;
-      const double x = hrow[l] * (double)U[idx * R + lc];
-      w.h[(int64_t)s * RP + l] = l < R ? x : 0.0;
+  }
+  int64_t idx = row0 + pick;
+  if (idx >= I) idx = I - 1;
+  if (act) sidx[(int64_t)s * nq + q] = (int32_t)idx;
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {  // 16 RP entries, 64 per pass
+    const int e = it * WAVE + l, k = e / RP, a = e % RP;
+    const int64_t sk = __shfl(s, k, WAVE), ik = __shfl(idx, k, WAVE);
+    if (k < n) {
+      const int ac = a < R ? a : R - 1;
+      const double x = w.h[sk * RP + a] * (double)U[ik * R + ac];
+      w.h[sk * RP + a] = a < R ? x : 0.0;
     }
   }
 }
 
 // Probability of the drawn Khatri-Rao row, (h^T G^+ h) / <G^+, G>, and the
-// row itself in the path precision.
+// row itself in the path precision.  16 samples per wave (lanes 0..15).
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
             const double *trace, double *prob, T *h_out) {
   constexpr int RP = 16 * NT;
-  const int64_t g = (int64_t)blockIdx.x * ST + threadIdx.x;
-  if ((int64_t)blockIdx.x * ST + (threadIdx.x & ~(WAVE - 1)) >= J) return;
-  const bool act = g < J;
-  const int32_t s = act ? (int32_t)g : 0;
-  double qB[NT][4 * NT];
-  load_bfrag<NT>(Gp, R, qB);
-  double mass = 0.0;
-  for (int tau = 0; tau < 4; ++tau) {
-    double xA[4 * NT], xD[NT][4], ms[4];
-    load_hfrag<NT>(hbuf, s, tau, xA, xD);
-    tile_mass<NT>(xA, xD, qB, ms);
-    const double m = lane_mass(ms);
-    if ((lane_id() >> 4) == tau) mass = m;
+  __shared__ double sP[RP * RP];
+  stage_pad<RP>(sP, Gp, R);
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
+  if (p0 >= J) return;
+  const int n = J - p0 < 16 ? (int)(J - p0) : 16;
+  const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
+  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
+  lds_bfrag<NT>(sP, qB);
+  load_hfrag<NT>(hbuf, s, 0, xA, xD);
+  tile_mass<NT>(xA, xD, qB, ms);
+  const double mass = lane_mass(ms);
+  if (l < n) prob[p0 + l] = mass / *trace;
+  // the 16 rows of h in the path precision, coalesced
+  const int ne = n * R;
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {  // ne <= 16 R <= 64 (RP / 4)
+    const int e = it * WAVE + l;
+    if (e < ne) {
+      const int r = e / R, c = e % R;
+      h_out[(p0 + r) * R + c] = (T)hbuf[(p0 + r) * RP + c];
+    }
   }
-  if (!act) return;
-  prob[g] = mass / *trace;
-  for (int a = 0; a < R; ++a) h_out[g * R + a] = (T)hbuf[g * RP + a];
 }
 
 template <typename T, int NT>
@@ -505,29 +586,29 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
              hipStream_t st) {
   const int nq = ml.n;
   const dim3 g(ceil_div(J, ST)), b(ST), gl(ceil_div(J, 16 * (ST / WAVE)));
-  hipLaunchKernelGGL((k_sts_first<T>), g, b, 0, st,
+  hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
                      static_cast<const T *>(ml.U[0]), ml.I[0], R, ml.cdf[0],
-                     ml.Z[0], ml.last[0], uni, nq, J, sidx, w.h, 16 * NT, err);
+                     ml.Z[0], ml.last[0], uni, nq, J, sidx, w.h, err);
   CPR_LAUNCH_CHECK();
   for (int q = 1; q < nq; ++q) {
     const double *tree = ml.tree[q], *Gg = ml.Ggt[q];
     const int64_t P2 = ml.P2[q];
-    hipLaunchKernelGGL((k_sts_root<NT>), g, b, 0, st, tree, Gg, P2, R, uni,
-                       q, nq, J, w, err);
+    hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R, uni,
+                       q, nq, J, w, w.slot[0], err);
     CPR_LAUNCH_CHECK();
-    int cur = 0, level = 0;
-    for (int64_t n = 1; n < P2; n <<= 1, ++level) {
-      hipLaunchKernelGGL((k_sts_level<NT>), g, b, 0, st, tree, Gg, R, J, w,
-                         w.perm[cur], w.perm[cur ^ 1], level);
+    int cur = 0;
+    for (int64_t n = 1; n < P2; n <<= 1) {
+      hipLaunchKernelGGL((k_sts_level<NT>), gl, b, 0, st, tree, Gg, R, J, w,
+                         w.slot[cur], w.slot[cur ^ 1]);
       CPR_LAUNCH_CHECK();
       cur ^= 1;
     }
     hipLaunchKernelGGL((k_sts_leaf<T, NT>), gl, b, 0, st,
                        static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2, Gg,
-                       J, w, w.perm[cur], q, nq, sidx, err);
+                       J, w, w.slot[cur], q, nq, sidx, err);
     CPR_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL((k_sts_final<T, NT>), g, b, 0, st, R, J, w.h, Gp, trace,
+  hipLaunchKernelGGL((k_sts_final<T, NT>), gl, b, 0, st, R, J, w.h, Gp, trace,
                      prob, h);
   CPR_LAUNCH_CHECK();
 }
