@@ -40,6 +40,9 @@ def parse():
     p.add_argument("--leaf", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="also copy MIB MiB device to device (a plain copy "
+                        "kernel of known size, to scale HBM counters)")
     return p.parse_args()
 
 
@@ -47,15 +50,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sts_flops_per_draw(R, depth, F):
-    """FP64 FLOPs of one STS-CP factor draw (one sample, one factor).
+def sts_flops_per_solve(dims, j, R, J, F):
+    """Algorithmic FP64 FLOPs of the STS-CP draws of one mode-j solve.
 
-    W = (h h^T) (*) G_{>k} packed: 3P multiplies; root and one left-child
-    mass per level: 2P each; leaf: F rows of U_row W' (2R^2) and the dot
-    with U_row (2R); h update: R.
+    First factor (h = 1): row masses U[i] G_{>k} U[i]^T, 2R^2 + 2R per row.
+    Each later factor, per draw: the root and one left-child mass per level,
+    <(h h^T) (*) G_{>k}, G^node> at 3 FLOPs per packed entry (P = R(R+1)/2),
+    then F leaf rows at R + 2R^2 each.  Per draw: h^T G^+ h, 2R^2 + R.
     """
     P = R * (R + 1) // 2
-    return 3 * P + 2 * P * (depth + 1) + F * (2 * R * R + 2 * R) + R
+    modes = [k for k in range(len(dims)) if k != j]
+    fl = dims[modes[0]] * (2 * R * R + 2 * R)
+    for k in modes[1:]:
+        depth = math.ceil(math.log2(max(1, -(-dims[k] // F))))
+        fl += J * ((depth + 1) * 3 * P + F * (2 * R * R + R))
+    return fl + J * (2 * R * R + R)
 
 
 def cpu_baseline(T, w, ctx, J, N, R, sampler):
@@ -196,25 +205,32 @@ def main():
         ms_dom = ph[dom][0] / max(ph[dom][1], 1)
         if dom == "sample" and sampler == "sts":
             F = a.leaf or 16
-            depth = [math.ceil(math.log2(max(1, -(-d // F)))) for d in T.dims]
-            # every mode solve draws from the N-1 other factors; average
-            # over the N solves of a sweep
-            mean_depth = np.mean([depth[k] for j in range(N)
-                                  for k in range(N) if k != j])
-            fl = J * (N - 1) * sts_flops_per_draw(R, mean_depth, F)
+            fl = np.mean([sts_flops_per_solve(T.dims, j, R, J, F)
+                          for j in range(N)])
             ach = fl / (ms_dom * 1e-3) / 1e12
-            roof = dict(kernel="sts_draw", bound="alu", achieved=ach,
+            roof = dict(kernel="sts_draw", bound="mfma", achieved=ach,
                         peak=FP64_PEAK_TFS, unit="TFLOP/s",
-                        frac=ach / FP64_PEAK_TFS, traffic=None)
+                        frac=ach / FP64_PEAK_TFS, traffic=None,
+                        flops_per_launch=fl, ms_per_launch=ms_dom)
         elif dom == "mttkrp":
             roof = dict(kernel="sampled_mttkrp", bound="hbm",
                         achieved=mttkrp["achieved_GBs"], peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=mttkrp["frac_of_peak"],
-                        traffic=None)
+                        traffic=None, bytes_per_launch=mtt_bytes,
+                        ms_per_launch=ms_mtt)
         else:
             roof = dict(kernel=dom, bound="latency", achieved=None,
                         peak=None, unit=None, frac=None, traffic=None,
                         ms_per_launch=ms_dom)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {a.copy_calibration} MiB")
+        del src_t, dst_t
     cpu = None
     if not a.no_cpu_baseline:
         log("timing the oracle on the host ...")

@@ -281,8 +281,7 @@ void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
   }
   {
     PhaseScope ps(c, PH_DEDUP);
-    lookup_columns(ml, J, c->sidx, c->ix[mode].col_key, c->ix[mode].n_cols,
-                   c->w, c->s);
+    lookup_columns(ml, J, c->sidx, c->ix[mode], c->w, c->s);
     merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
   }
   c->sampled_mode = mode;
@@ -303,8 +302,7 @@ void do_set_samples(cp_ctx *c, int mode, int64_t J, const int32_t *idx,
                      c->s);
   {
     PhaseScope ps(c, PH_DEDUP);
-    lookup_columns(ml, J, c->sidx, c->ix[mode].col_key, c->ix[mode].n_cols,
-                   c->w, c->s);
+    lookup_columns(ml, J, c->sidx, c->ix[mode], c->w, c->s);
     merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
   }
   c->sampled_mode = mode;
@@ -405,6 +403,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     if (c->ix[k].val) c->allocs.push_back(c->ix[k].val);
     if (c->ix[k].col_key) c->allocs.push_back(c->ix[k].col_key);
     if (c->ix[k].col_ptr) c->allocs.push_back(c->ix[k].col_ptr);
+    if (c->ix[k].top) c->allocs.push_back(c->ix[k].top);
     if (!e.empty())
       throw Fail{e.find("63 bits") != std::string::npos ? CP_EUNSUPPORTED
                                                          : CP_ENOMEM, e};
@@ -474,6 +473,8 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.uq_cnt, J * 4);
   dalloc(c, &c->w.uq_w, J * 8);
   dalloc(c, &c->w.uq_off, (J + 1) * 8);
+  dalloc(c, &c->w.uq_base, J * 8);
+  c->w.max_u = J;
   dalloc(c, &c->w.counts, 16);
   dalloc(c, &c->w.stats, 4 * 8);
   dalloc(c, &c->w.scratch, (size_t)4 * J * 8);
@@ -508,6 +509,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   }
   c->w.rec_cap = cap;
   dalloc(c, &c->w.rec, (size_t)cap * bucket_record_bytes((int)ts));
+  dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);
   zero_fill<int64_t>(c->w.stats, 4, c->s);
   dalloc(c, &c->M, (size_t)c->max_I * R * ts);

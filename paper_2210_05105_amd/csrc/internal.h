@@ -57,6 +57,11 @@ struct ModeIndex {
   int64_t I = 0, n_cols = 0, max_col = 0;
   uint64_t *col_key = nullptr;  // n_cols sorted distinct column keys
   int64_t *col_ptr = nullptr;   // n_cols + 1 offsets
+  // first column whose key is >= v * top_stride, v = 0 .. n_top - 1 (v is
+  // the index of the slowest mode != j; top[n_top - 1] = n_cols)
+  int64_t *top = nullptr;
+  uint64_t top_stride = 1;
+  int64_t n_top = 0;
   int32_t *row = nullptr;       // nnz rows i_j
   void *val = nullptr;          // nnz values (float or double)
 };
@@ -156,6 +161,9 @@ struct SampleWork {
   int32_t *uq_cnt;   // J: number of draws of the column
   double *uq_w;      // J: weight count/(J p)
   int64_t *uq_off;   // J+1: extracted-nonzero offsets
+  int64_t *uq_base;  // J: index position of extracted nonzero e = uq_base + e
+  int64_t *tile_first;  // bucket_tiles(rec_cap): column at each tile start
+  int64_t max_u;     // J (bound on distinct columns)
   int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
   int64_t *scratch;  // 4 J: first-draw flags, lengths and their prefix sums
@@ -167,13 +175,13 @@ struct SampleWork {
 };
 int bucket_shift(int R, int tsize);
 int64_t bucket_max_items(int64_t rec_cap, int64_t nbk);
+int64_t bucket_tiles(int64_t rec_cap);
 size_t bucket_record_bytes(int tsize);
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
                      T *h, uint32_t *err, hipStream_t s);
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
-                    const uint64_t *col_key, int64_t n_cols, SampleWork &w,
-                    hipStream_t s);
+                    const ModeIndex &ix, SampleWork &w, hipStream_t s);
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    SampleWork &w, hipStream_t s);
 template <typename T>

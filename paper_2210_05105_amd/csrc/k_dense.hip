@@ -320,7 +320,9 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   // the eigendecomposition, whose cutoff defines the pseudo-inverse.
   const double tol = fmax(R * 0x1p-52 * tr, 1e-9 * dmax);
   __syncthreads();
-  bool ok = chol_inverse(A, R, tol, scratch, Gp, &flag);
+  // L^{-1} next to A in LDS when both fit (R <= 64), else in scratch
+  double *W = R <= 64 ? A + R * R : scratch;
+  bool ok = chol_inverse(A, R, tol, W, Gp, &flag);
   if (!ok) {
     __syncthreads();
     for (int e = t; e < R * R; e += PV_THREADS) A[e] = Gfull[e];
@@ -582,16 +584,16 @@ void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
                    double *ggt_out, double *trace_out, double *scratch,
                    uint32_t *err, hipStream_t s) {
   static bool attr_set = false;
-  if (!attr_set) {  // R x R doubles exceed the default 64 KiB for R > 90
+  if (!attr_set) {  // up to 2 R^2 (R <= 64) or R^2 doubles: beyond 64 KiB
     hipError_t e = hipFuncSetAttribute(
         reinterpret_cast<const void *>(&k_hadamard_pinv),
         hipFuncAttributeMaxDynamicSharedMemorySize, MAXR * MAXR * 8);
     if (e != hipSuccess) throw HipFail(e, __FILE__, __LINE__);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_hadamard_pinv, dim3(1), dim3(PV_THREADS),
-                     (size_t)R * R * sizeof(double), s, ml, R, Gfull, Gp,
-                     ggt_out, trace_out, scratch, err);
+  const size_t lds = (size_t)(R <= 64 ? 2 : 1) * R * R * sizeof(double);
+  hipLaunchKernelGGL(k_hadamard_pinv, dim3(1), dim3(PV_THREADS), lds, s, ml,
+                     R, Gfull, Gp, ggt_out, trace_out, scratch, err);
   CPR_LAUNCH_CHECK();
 }
 

@@ -165,6 +165,20 @@ __global__ void k_cols(const uint64_t *hi, int64_t n, int lo_bits,
   col_ptr[cid[p]] = p;
 }
 
+// offsets of the slowest mode's values in the sorted column keys
+__global__ void k_top(const uint64_t *col_key, int64_t n_cols,
+                      uint64_t top_stride, int64_t n_top, int64_t *top) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_top) return;
+  const uint64_t key = (uint64_t)v * top_stride;
+  int64_t lo = 0, hi = n_cols;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (col_key[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  top[v] = lo;
+}
+
 // longest column: grid-stride per thread, then wave and block maxima and
 // one atomicMax per block (same-address atomics serialise)
 __global__ void __launch_bounds__(256)
@@ -331,6 +345,18 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
       hipStreamSynchronize(s) != hipSuccess)
     return "hip error while building the mode index";
   out.max_col = (int64_t)mxh;
+  // offset table of the slowest mode != j
+  int last = -1;
+  for (int k = 0; k < N; ++k)
+    if (k != j) last = k;
+  out.top_stride = stride[last];
+  out.n_top = dims_h[last] + 1;
+  if (hipMalloc((void **)&out.top, out.n_top * 8) != hipSuccess)
+    return "out of device memory for the mode index";
+  hipLaunchKernelGGL(k_top, dim3(ceil_div(out.n_top, 256)), dim3(256), 0, s,
+                     out.col_key, out.n_cols, out.top_stride, out.n_top,
+                     out.top);
+  CPR_LAUNCH_CHECK();
   return "";
 }
 

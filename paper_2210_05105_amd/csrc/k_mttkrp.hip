@@ -6,11 +6,13 @@
 // 2. merge: draws of the same column are merged (count c, weight
 //    c / (J p)); distinct columns are compacted in first-draw order and the
 //    lengths of their nonzero ranges are prefix-summed.
-// 3. MTTKRP: the extracted nonzeros are consumed in place from the mode's
-//    index (no triple buffer): equal-size chunks of the concatenated ranges
-//    are spread over all waves, each nonzero (i, v) of column x adding
-//    w_x v h_x to M[i, :] with hardware float atomics.  Work is balanced by
-//    nonzeros, not by sample, so a heavy column does not serialise.
+// 3. MTTKRP by blocks of B output rows (the paper's transposition of the
+//    extracted nonzeros to row order, Section 4.3, as one counting-sort
+//    pass): count the extracted nonzeros per row block, scatter compact
+//    records (draw id, row % B, w v) grouped by block, then accumulate each
+//    block's records into an LDS copy of its B rows of M.  Positions of
+//    one column are row-sorted, so a wave's consecutive positions form a
+//    few runs of one block and count/scatter take one atomic per run.
 #include "internal.h"
 
 #include <algorithm>
@@ -40,9 +42,14 @@ __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
   h[e] = (T)v;
 }
 
+// Column of each draw: its key, then a binary search inside the range of
+// columns that share the slowest mode's index.  The first draw of a column
+// claims it with atomicMin (read first: most later draws see a smaller
+// owner and skip the atomic).
 __global__ void __launch_bounds__(LK_THREADS)
 k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *col_key,
-         int64_t n_cols, int32_t *col_id, int32_t *owner) {
+         const int64_t *top, uint64_t top_stride, int64_t n_top,
+         int32_t *col_id, int32_t *owner) {
   const int64_t s = (int64_t)blockIdx.x * LK_THREADS + threadIdx.x;
   if (s >= J) return;
   uint64_t key = 0;
@@ -52,24 +59,50 @@ k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *col_key,
     ok &= (i >= 0 && i < ml.I[q]);
     key += (uint64_t)i * ml.stride[q];
   }
-  int64_t lo = 0, hi = n_cols;
+  uint64_t tv = key / top_stride;
+  if (!ok || tv >= (uint64_t)(n_top - 1)) tv = 0;
+  int64_t lo = top[tv], hi = top[tv + 1];
   while (lo < hi) {  // first column key >= key
     int64_t mid = (lo + hi) >> 1;
     if (col_key[mid] < key) lo = mid + 1; else hi = mid;
   }
-  int32_t cid = (ok && lo < n_cols && col_key[lo] == key) ? (int32_t)lo : -1;
+  const int64_t end = top[tv + 1];
+  int32_t cid = (ok && lo < end && col_key[lo] == key) ? (int32_t)lo : -1;
   col_id[s] = cid;
-  if (cid >= 0) atomicMin(&owner[cid], (int32_t)s);
+  if (cid >= 0 && owner[cid] > (int32_t)s) atomicMin(&owner[cid], (int32_t)s);
 }
 
-__global__ void k_dup(int64_t J, const int32_t *col_id, const int32_t *owner,
-                      int32_t *dupcnt) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= J) return;
-  const int32_t cid = col_id[s];
-  if (cid < 0) return;
-  const int32_t o = owner[cid];
-  if (o != (int32_t)s) atomicAdd(&dupcnt[o], 1);
+// Extra draws per first draw, aggregated per block in an LDS hash table
+// (one global atomic per distinct first draw and block).
+constexpr int DUP_HASH = 2 * LK_THREADS;
+__global__ void __launch_bounds__(LK_THREADS)
+k_dup(int64_t J, const int32_t *col_id, const int32_t *owner,
+      int32_t *dupcnt) {
+  __shared__ int32_t hkey[DUP_HASH], hcnt[DUP_HASH];
+  for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS) {
+    hkey[e] = -1;
+    hcnt[e] = 0;
+  }
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * LK_THREADS + threadIdx.x;
+  if (s < J) {
+    const int32_t cid = col_id[s];
+    const int32_t o = cid >= 0 ? owner[cid] : (int32_t)s;
+    if (o != (int32_t)s) {
+      uint32_t hsh = ((uint32_t)o * 2654435761u) % DUP_HASH;
+      for (int probe = 0; probe < DUP_HASH; ++probe) {
+        const int32_t prev = atomicCAS(&hkey[hsh], -1, o);
+        if (prev == -1 || prev == o) {
+          atomicAdd(&hcnt[hsh], 1);
+          break;
+        }
+        hsh = (hsh + 1) % DUP_HASH;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS)
+    if (hkey[e] >= 0) atomicAdd(&dupcnt[hkey[e]], hcnt[e]);
 }
 
 // First draw of each column: flag and nonzero-range length (prefix-summed
@@ -90,9 +123,10 @@ __global__ void k_first(int64_t J, const int32_t *col_id, const int32_t *owner,
 __global__ void k_compact(int64_t J, const double *prob, const int32_t *col_id,
                           const int64_t *flag, const int64_t *len,
                           const int64_t *uidx, const int64_t *off,
-                          int32_t *owner, int32_t *dupcnt, int32_t *uq_s,
-                          int32_t *uq_cid, int32_t *uq_cnt, double *uq_w,
-                          int64_t *uq_off, int64_t *counts, int64_t *stats) {
+                          const int64_t *col_ptr, int32_t *owner,
+                          int32_t *dupcnt, int32_t *uq_s, int32_t *uq_cid,
+                          int32_t *uq_cnt, double *uq_w, int64_t *uq_off,
+                          int64_t *uq_base, int64_t *counts, int64_t *stats) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= J) return;
   if (flag[s]) {
@@ -104,6 +138,7 @@ __global__ void k_compact(int64_t J, const double *prob, const int32_t *col_id,
     uq_cnt[u] = cnt;
     uq_w[u] = (double)cnt / ((double)J * prob[s]);
     uq_off[u] = off[s];
+    uq_base[u] = col_ptr[cid] - off[s];  // index position = uq_base + e
     owner[cid] = INT_MAX;
   }
   dupcnt[s] = 0;
@@ -138,48 +173,99 @@ constexpr int BK_ITEMS = BK_TILE / MT_THREADS;
 constexpr int BK_LDS_MAX = 4096;  // buckets histogrammed in LDS
 constexpr int BK_SLICE = 4096;    // records per accumulation workgroup
 
-// last u in [lo, hi) with uq_off[u] <= e (uq_off[lo] <= e < uq_off[hi])
-__device__ __forceinline__ int64_t find_col(const int64_t *uq_off, int64_t lo,
-                                            int64_t hi, int64_t e) {
+// tile_first[t] = the distinct column holding position t BK_TILE
+__global__ void k_tile_first(const int64_t *counts, const int64_t *uq_off,
+                             int64_t *tile_first) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= counts[0]) return;
+  const int64_t a = uq_off[u], b = uq_off[u + 1];
+  for (int64_t t = (a + BK_TILE - 1) / BK_TILE; t * BK_TILE < b; ++t)
+    tile_first[t] = u;
+}
+
+// The distinct columns overlapping tile [e0, e1): [ub, ue).  Their start
+// positions relative to e0 go to LDS (cst); a position's column is then a
+// binary search in LDS.
+__device__ __forceinline__ void tile_columns(const int64_t *counts,
+                                             const int64_t *uq_off,
+                                             const int64_t *tile_first,
+                                             int64_t tile, int64_t ntile,
+                                             int64_t e0, int32_t *cst,
+                                             int64_t &ub, int &ncol) {
+  const int64_t nu = counts[0];
+  ub = tile_first[tile];
+  const int64_t ue = tile + 1 < ntile ? tile_first[tile + 1] + 1 : nu;
+  ncol = (int)(ue - ub);
+  for (int k = threadIdx.x; k < ncol; k += MT_THREADS)
+    cst[k] = (int32_t)(uq_off[ub + k] - e0);  // cst[0] <= 0
+}
+
+__device__ __forceinline__ int find_local(const int32_t *cst, int ncol,
+                                          int pos) {
+  int lo = 0, hi = ncol;  // last k with cst[k] <= pos
   while (hi - lo > 1) {
-    int64_t m = (lo + hi) >> 1;
-    if (uq_off[m] <= e) lo = m; else hi = m;
+    const int m = (lo + hi) >> 1;
+    if (cst[m] <= pos) lo = m; else hi = m;
   }
   return lo;
 }
 
-// distinct-column range [ub, ue) covering positions [e0, e1)
-__device__ void tile_cols(const int64_t *uq_off, int64_t nu, int64_t e0,
-                          int64_t e1, int64_t *ub, int64_t *ue) {
-  *ub = find_col(uq_off, 0, nu, e0);
-  *ue = find_col(uq_off, *ub, nu, e1 - 1) + 1;
+// Runs of equal bucket among the valid lanes of a wave (valid lanes are a
+// prefix, holding consecutive positions): the run's first lane and, for
+// that lane, the run length.
+__device__ __forceinline__ void bucket_runs(int bk, bool valid, int &leader,
+                                            int &len) {
+  const int l = lane_id();
+  const int prev = __shfl_up(bk, 1, WAVE);
+  const uint64_t sm = __ballot(valid && (l == 0 || bk != prev));
+  const uint64_t vm = __ballot(valid);
+  const uint64_t upto = sm & ((2ull << l) - 1);  // starts at or below l
+  leader = upto ? 63 - __clzll((long long)upto) : l;
+  const uint64_t above = sm & ~((2ull << l) - 1);
+  const int nxt = above ? __ffsll((long long)above) - 1
+                        : (vm ? 64 - __clzll((long long)vm) : 0);
+  len = nxt - l;
 }
 
 __global__ void __launch_bounds__(MT_THREADS)
-k_bk_count(const int64_t *counts, const int64_t *uq_off, const int32_t *uq_cid,
-           const int64_t *col_ptr, const int32_t *row, int nbk, int bb,
-           int64_t *bk_total) {
+k_bk_count(const int64_t *counts, const int64_t *uq_off,
+           const int64_t *tile_first, const int64_t *uq_base,
+           const int32_t *row, int nbk, int bb, int64_t *bk_total) {
   __shared__ uint32_t hist[BK_LDS_MAX];
-  __shared__ int64_t sh_ub, sh_ue;
-  const int64_t nu = counts[0], nz = counts[1];
+  __shared__ int32_t cst[BK_TILE + 1];
+  const int64_t nz = counts[1];
   const bool use_lds = nbk <= BK_LDS_MAX;
   const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
+  const int l = lane_id();
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int64_t e0 = tile * BK_TILE;
     const int64_t e1 = e0 + BK_TILE < nz ? e0 + BK_TILE : nz;
     if (use_lds)
       for (int b = threadIdx.x; b < nbk; b += MT_THREADS) hist[b] = 0;
-    if (threadIdx.x == 0) tile_cols(uq_off, nu, e0, e1, &sh_ub, &sh_ue);
+    int64_t ub;
+    int ncol;
+    tile_columns(counts, uq_off, tile_first, tile, ntile, e0, cst, ub, ncol);
     __syncthreads();
-    const int64_t ub = sh_ub, ue = sh_ue;
+    int64_t p[BK_ITEMS];
+#pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
-      const int64_t e = e0 + (int64_t)i * MT_THREADS + threadIdx.x;
-      if (e >= e1) break;
-      const int64_t u = find_col(uq_off, ub, ue, e);
-      const int32_t rr = row[col_ptr[uq_cid[u]] + (e - uq_off[u])];
-      const int bk = rr >> bb;
-      if (use_lds) atomicAdd(&hist[bk], 1u);
-      else atomicAdd((unsigned long long *)&bk_total[bk], 1ull);
+      const int pos = i * MT_THREADS + threadIdx.x;
+      const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
+      p[i] = uq_base[ub + find_local(cst, ncol, (int)(e - e0))] + e;
+    }
+    int rw[BK_ITEMS];
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) rw[i] = row[p[i]];
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      const bool valid = e0 + i * MT_THREADS + threadIdx.x < e1;
+      const int bk = rw[i] >> bb;
+      int leader, len;
+      bucket_runs(bk, valid, leader, len);
+      if (valid && leader == l) {
+        if (use_lds) atomicAdd(&hist[bk], (uint32_t)len);
+        else atomicAdd((unsigned long long *)&bk_total[bk], (unsigned long long)len);
+      }
     }
     __syncthreads();
     if (use_lds)
@@ -206,40 +292,53 @@ struct BkRec {
 
 template <typename T>
 __global__ void __launch_bounds__(MT_THREADS)
-k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const int32_t *uq_cid,
-             const double *uq_w, const int64_t *uq_off, const int64_t *col_ptr,
-             const int32_t *row, const T *val, int nbk, int bb,
-             const int64_t *bk_start, int64_t *bk_fill, BkRec<T> *rec) {
+k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
+             const int64_t *uq_off, const int64_t *tile_first,
+             const int64_t *uq_base, const int32_t *row, const T *val, int nbk,
+             int bb, const int64_t *bk_start, int64_t *bk_fill,
+             BkRec<T> *rec) {
   __shared__ uint32_t cnt[BK_LDS_MAX];
-  __shared__ uint32_t base[BK_LDS_MAX];
-  __shared__ int64_t sh_ub, sh_ue;
-  const int64_t nu = counts[0], nz = counts[1];
+  __shared__ uint32_t base[BK_LDS_MAX];  // record positions (< 2^32)
+  __shared__ int32_t cst[BK_TILE + 1];
+  const int64_t nz = counts[1];
   const bool use_lds = nbk <= BK_LDS_MAX;
   const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
   const uint32_t bmask = (1u << bb) - 1;
+  const int l = lane_id();
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int64_t e0 = tile * BK_TILE;
     const int64_t e1 = e0 + BK_TILE < nz ? e0 + BK_TILE : nz;
     if (use_lds)
       for (int b = threadIdx.x; b < nbk; b += MT_THREADS) cnt[b] = 0;
-    if (threadIdx.x == 0) tile_cols(uq_off, nu, e0, e1, &sh_ub, &sh_ue);
+    int64_t ub;
+    int ncol;
+    tile_columns(counts, uq_off, tile_first, tile, ntile, e0, cst, ub, ncol);
     __syncthreads();
-    const int64_t ub = sh_ub, ue = sh_ue;
-    int32_t my_row[BK_ITEMS];
+    int64_t u[BK_ITEMS], p[BK_ITEMS];
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      const int pos = i * MT_THREADS + threadIdx.x;
+      const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
+      u[i] = ub + find_local(cst, ncol, (int)(e - e0));
+      p[i] = uq_base[u[i]] + e;
+    }
+    int my_bk[BK_ITEMS], my_lead[BK_ITEMS], my_len[BK_ITEMS];
     uint32_t my_key[BK_ITEMS];
     T my_cf[BK_ITEMS];
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
-      const int64_t e = e0 + (int64_t)i * MT_THREADS + threadIdx.x;
-      my_row[i] = -1;
-      if (e < e1) {
-        const int64_t u = find_col(uq_off, ub, ue, e);
-        const int64_t p = col_ptr[uq_cid[u]] + (e - uq_off[u]);
-        my_row[i] = row[p];
-        my_key[i] = ((uint32_t)uq_s[u] << 8) | ((uint32_t)my_row[i] & bmask);
-        my_cf[i] = (T)(uq_w[u] * (double)val[p]);
-        if (use_lds) atomicAdd(&cnt[my_row[i] >> bb], 1u);
-      }
+      const int rw = row[p[i]];
+      my_key[i] = ((uint32_t)uq_s[u[i]] << 8) | ((uint32_t)rw & bmask);
+      my_cf[i] = (T)(uq_w[u[i]] * (double)val[p[i]]);
+      my_bk[i] = rw >> bb;
+    }
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
+      const bool valid = e0 + i * MT_THREADS + threadIdx.x < e1;
+      if (!valid) my_bk[i] = -1;
+      bucket_runs(my_bk[i], valid, my_lead[i], my_len[i]);
+      if (use_lds && valid && my_lead[i] == l)
+        atomicAdd(&cnt[my_bk[i]], (uint32_t)my_len[i]);
     }
     __syncthreads();
     if (use_lds)
@@ -254,13 +353,16 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const int32_t *uq_cid,
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
-      if (my_row[i] < 0) continue;
-      const int bk = my_row[i] >> bb;
-      const uint64_t dst =
-          use_lds ? (uint64_t)base[bk] + atomicAdd(&cnt[bk], 1u)
-                  : (uint64_t)bk_start[bk] +
-                        atomicAdd((unsigned long long *)&bk_fill[bk], 1ull);
-      rec[dst] = BkRec<T>{my_key[i], my_cf[i]};
+      const int bk = my_bk[i];
+      // the run's first lane reserves the run's slots; members follow it
+      int64_t off = 0;
+      if (bk >= 0 && my_lead[i] == l)
+        off = use_lds ? (int64_t)base[bk] + (int64_t)atomicAdd(&cnt[bk], (uint32_t)my_len[i])
+                      : bk_start[bk] + (int64_t)atomicAdd(
+                            (unsigned long long *)&bk_fill[bk],
+                            (unsigned long long)my_len[i]);
+      off = __shfl(off, my_lead[i], WAVE);
+      if (bk >= 0) rec[off + (l - my_lead[i])] = BkRec<T>{my_key[i], my_cf[i]};
     }
     __syncthreads();
   }
@@ -342,12 +444,20 @@ k_bk_accum(const int64_t *item_start, const int64_t *bk_start, int nbk, int bb,
 #pragma unroll
     for (int q = 0; q < CPL; ++q) acc[q] = T(0);
     int cur = c0 < c1 ? lr[c0] : -1;
+    // rows also held by the neighbouring chunks take LDS float atomics
+    // (slow); every other row belongs to this group alone and is stored
+    const int row_a = (c0 < c1 && c0 > 0 && lr[c0 - 1] == lr[c0]) ? lr[c0] : -1;
+    const int row_b = (c0 < c1 && c1 < n && lr[c1] == lr[c1 - 1]) ? lr[c1 - 1] : -1;
     auto flush = [&](int row) {
       T *br = blk + row * R;
+      const bool shared = row == row_a || row == row_b;
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
         const int c = gl + q * L;
-        if (q < ncl && c < R) atomicAdd(br + c, acc[q]);
+        if (q < ncl && c < R) {
+          if (shared) atomicAdd(br + c, acc[q]);
+          else br[c] = acc[q];
+        }
         acc[q] = T(0);
       }
     };
@@ -509,10 +619,10 @@ template void set_sample_rows<double>(const ModeList &, int64_t, int,
                                       hipStream_t);
 
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
-                    const uint64_t *col_key, int64_t n_cols, SampleWork &w,
-                    hipStream_t s) {
+                    const ModeIndex &ix, SampleWork &w, hipStream_t s) {
   hipLaunchKernelGGL(k_lookup, dim3(ceil_div(J, LK_THREADS)), dim3(LK_THREADS),
-                     0, s, ml, J, sidx, col_key, n_cols, w.col_id, w.owner);
+                     0, s, ml, J, sidx, ix.col_key, ix.top, ix.top_stride,
+                     ix.n_top, w.col_id, w.owner);
   CPR_LAUNCH_CHECK();
 }
 
@@ -521,15 +631,16 @@ void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
   const dim3 g(ceil_div(J, 256)), b(256);
   int64_t *flag = w.scratch, *len = w.scratch + J, *uidx = w.scratch + 2 * J,
           *off = w.scratch + 3 * J;
-  hipLaunchKernelGGL(k_dup, g, b, 0, s, J, w.col_id, w.owner, w.dupcnt);
+  hipLaunchKernelGGL(k_dup, dim3(ceil_div(J, LK_THREADS)), dim3(LK_THREADS), 0,
+                     s, J, w.col_id, w.owner, w.dupcnt);
   hipLaunchKernelGGL(k_first, g, b, 0, s, J, w.col_id, w.owner, col_ptr, flag,
                      len);
   CPR_LAUNCH_CHECK();
   exclusive_scan_i64(flag, uidx, J, w.scan_tmp, s);
   exclusive_scan_i64(len, off, J, w.scan_tmp, s);
   hipLaunchKernelGGL(k_compact, g, b, 0, s, J, prob, w.col_id, flag, len, uidx,
-                     off, w.owner, w.dupcnt, w.uq_s, w.uq_cid, w.uq_cnt,
-                     w.uq_w, w.uq_off, w.counts, w.stats);
+                     off, col_ptr, w.owner, w.dupcnt, w.uq_s, w.uq_cid,
+                     w.uq_cnt, w.uq_w, w.uq_off, w.uq_base, w.counts, w.stats);
   CPR_LAUNCH_CHECK();
 }
 
@@ -554,8 +665,10 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
           *item_start = w.bk + 4 * (nbk + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
   zero_fill<int64_t>(bk_total, 2 * (nbk + 1), s);  // totals and fill cursors
-  hipLaunchKernelGGL(k_bk_count, gt, b, 0, s, w.counts, w.uq_off, w.uq_cid,
-                     col_ptr, row, nbk, bb, bk_total);
+  hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
+                     w.counts, w.uq_off, w.tile_first);
+  hipLaunchKernelGGL(k_bk_count, gt, b, 0, s, w.counts, w.uq_off, w.tile_first,
+                     w.uq_base, row, nbk, bb, bk_total);
   CPR_LAUNCH_CHECK();
   exclusive_scan_i64(bk_total, bk_start, nbk + 1, w.scan_tmp, s);
   hipLaunchKernelGGL(k_bk_items, dim3(ceil_div(nbk + 1, 256)), b, 0, s,
@@ -564,8 +677,8 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   exclusive_scan_i64(items, item_start, nbk + 1, w.scan_tmp, s);
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
-  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 0, s, w.counts, w.uq_s,
-                     w.uq_cid, w.uq_w, w.uq_off, col_ptr, row, val, nbk, bb,
+  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 0, s, w.counts, w.uq_s, w.uq_w,
+                     w.uq_off, w.tile_first, w.uq_base, row, val, nbk, bb,
                      bk_start, bk_fill, rec);
   CPR_LAUNCH_CHECK();
   const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
@@ -591,6 +704,8 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                      part, M);
   CPR_LAUNCH_CHECK();
 }
+int64_t bucket_tiles(int64_t rec_cap) { return rec_cap / BK_TILE + 2; }
+
 int64_t bucket_max_items(int64_t rec_cap, int64_t nbk) {
   return rec_cap / BK_SLICE + nbk + 1;
 }

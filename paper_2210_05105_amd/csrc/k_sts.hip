@@ -48,45 +48,69 @@ __device__ __forceinline__ int packed_index(int a, int b, int R) {
 
 
 // ---------------------------------------------------------------------------
-// Build: leaf Grams on FP64 MFMA (one wave per leaf), then the subtree of
-// LB consecutive leaves of the block; upper levels by k_tree_level.
+// Build.  Block b computes the Grams of leaves [b LB, (b + 1) LB) on FP64
+// MFMA (one wave per leaf, 16 x 16 tiles), keeps them in LDS and writes the
+// internal nodes of its LB-leaf subtree (one thread per packed entry,
+// pairwise sums in registers).  Upper levels: k_tree_up sums groups of up to
+// 8 sibling subtree roots, three levels per launch.
 // ---------------------------------------------------------------------------
+template <int LBMAX>
+__device__ __forceinline__ void sum_up(double (&x)[LBMAX], int n, double *tree,
+                                       int64_t first, int P, int c) {
+  // x[0..n) are entry c of consecutive nodes first .. first + n - 1 of one
+  // level; write entry c of every ancestor up to their common root
+  for (int m = n / 2; m >= 1; m /= 2) {
+    first /= 2;
+#pragma unroll
+    for (int i = 0; i < LBMAX / 2; ++i)
+      if (i < m) {
+        x[i] = x[2 * i] + x[2 * i + 1];
+        tree[(first + i) * P + c] = x[i];
+      }
+  }
+}
+
+constexpr int TB_LBMAX = 16;
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(256)
-k_tree_leaves(const T *U, int64_t I, int R, int RP, int F, int64_t P2, int LB,
-              double *tree) {
-  constexpr int NTRI = NT * (NT + 1) / 2;
-  const int P = RP * (RP + 1) / 2;
+k_tree_build(const T *U, int64_t I, int R, int F, int64_t P2, int lb,
+             double *tree) {
+  constexpr int NTRI = NT * (NT + 1) / 2, RP = 16 * NT;
+  constexpr int P = RP * (RP + 1) / 2;
+  extern __shared__ double leaves[];  // LB x P
+  const int LB = 1 << lb;
   const int w = threadIdx.x / WAVE, l = lane_id();
   const int64_t leaf0 = (int64_t)blockIdx.x * LB;
   for (int lf = w; lf < LB; lf += 4) {
     const int64_t leaf = leaf0 + lf;
-    double *node = tree + (P2 + leaf) * (int64_t)P;
     const int64_t rbase = leaf * F;
     double4_t acc[NTRI];
 #pragma unroll
     for (int i = 0; i < NTRI; ++i) acc[i] = double4_t{0, 0, 0, 0};
-    if (rbase < I) {
-      for (int k0 = 0; k0 < F; k0 += 4) {
-        const int64_t r = rbase + k0 + l / 16;
-        const bool rv = r < I;
-        double col[NT];
+    for (int k0 = 0; k0 < F; k0 += 4) {
+      const int64_t r = rbase + k0 + l / 16;
+      const double rm = r < I ? 1.0 : 0.0;
+      const T *ur = U + (r < I ? r : I - 1) * R;
+      double col[NT];
 #pragma unroll
-        for (int ta = 0; ta < NT; ++ta) {
-          const int ca = ta * 16 + (l % 16);
-          col[ta] = (rv && ca < R) ? (double)U[r * R + ca] : 0.0;
-        }
-#pragma unroll
-        for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-          for (int tb = ta; tb < NT; ++tb) {
-            const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
-            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(col[ta], col[tb],
-                                                          acc[i], 0, 0, 0);
-          }
+      for (int ta = 0; ta < NT; ++ta) {
+        const int ca = ta * 16 + (l % 16);
+        col[ta] = (double)ur[ca < R ? ca : R - 1] * (ca < R ? rm : 0.0);
       }
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < NT; ++tb) {
+          const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(col[ta], col[tb],
+                                                        acc[i], 0, 0, 0);
+        }
     }
-    // tile (ta, tb), lane l, element v -> (ta*16 + l/16 + 4v, tb*16 + l%16)
+    // tile (ta, tb), lane l, element v -> (ta*16 + l/16 + 4v, tb*16 + l%16);
+    // entries beyond R are exact zeros (zero columns)
+    double *node = tree + (P2 + leaf) * (int64_t)P;
+    double *ln = leaves + lf * P;
 #pragma unroll
     for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
@@ -96,33 +120,35 @@ k_tree_leaves(const T *U, int64_t I, int R, int RP, int F, int64_t P2, int LB,
         for (int v = 0; v < 4; ++v) {
           const int ga = ta * 16 + (l / 16) + 4 * v;
           const int gb = tb * 16 + (l % 16);
-          // entries beyond R are exact zeros (zero columns)
-          if (ga < RP && gb < RP && ga <= gb)
-            node[packed_index(ga, gb, RP)] = acc[i][v];
+          if (ga <= gb) {
+            const int o = packed_index(ga, gb, RP);
+            node[o] = acc[i][v];
+            ln[o] = acc[i][v];
+          }
         }
       }
   }
-  __threadfence_block();
   __syncthreads();
-  // in-block subtree: parents of the block's leaves up to the block root
-  int64_t first = (P2 + leaf0) / 2;  // first node of the level above
-  for (int cnt = LB / 2; cnt >= 1; cnt /= 2, first /= 2) {
-    for (int64_t e = threadIdx.x; e < (int64_t)cnt * P; e += 256) {
-      const int64_t v = first + e / P;
-      const int c = (int)(e % P);
-      tree[v * P + c] = tree[(2 * v) * P + c] + tree[(2 * v + 1) * P + c];
-    }
-    __threadfence_block();
-    __syncthreads();
+  // internal nodes of the block's subtree
+  for (int c = threadIdx.x; c < P; c += 256) {
+    double x[TB_LBMAX];
+#pragma unroll
+    for (int i = 0; i < TB_LBMAX; ++i) x[i] = i < LB ? leaves[i * P + c] : 0.0;
+    sum_up<TB_LBMAX>(x, LB, tree, P2 + leaf0, P, c);
   }
 }
 
-__global__ void k_tree_level(double *tree, int64_t first, int64_t cnt, int P) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cnt * P) return;
-  const int64_t v = first + e / P;
-  const int c = (int)(e % P);
-  tree[v * P + c] = tree[(2 * v) * P + c] + tree[(2 * v + 1) * P + c];
+// group g of G consecutive nodes from `first` (one level): entry c of every
+// ancestor up to the group's common root
+__global__ void __launch_bounds__(256)
+k_tree_up(double *tree, int64_t first, int G, int P) {
+  const int64_t f = first + (int64_t)blockIdx.x * G;
+  for (int c = threadIdx.x; c < P; c += 256) {
+    double x[TB_LBMAX];
+#pragma unroll
+    for (int i = 0; i < TB_LBMAX; ++i) x[i] = i < G ? tree[(f + i) * P + c] : 0.0;
+    sum_up<TB_LBMAX>(x, G, tree, f, P, c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -220,12 +246,23 @@ __device__ __forceinline__ double lane_mass(const double (&ms)[4]) {
 
 // First factor (h = 1): every sample shares one conditional law, held as a
 // flat CDF of the row masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)}.
+// The search runs first over the last CDF entry of each group of cs rows
+// (staged in LDS), then inside the group.
+constexpr int FIRST_COARSE = 2048;
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST)
 k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
             const int64_t *lastp, const double *uni, int nq, int64_t J,
-            int32_t *sidx, double *hbuf, uint32_t *err) {
+            int cs, int32_t *sidx, double *hbuf, uint32_t *err) {
   constexpr int RP = 16 * NT;
+  __shared__ double coarse[FIRST_COARSE];
+  const int64_t nc = (I + cs - 1) / cs;
+  for (int64_t k = threadIdx.x; k < nc; k += ST) {
+    const int64_t e = (k + 1) * cs;
+    coarse[k] = cdf[(e < I ? e : I) - 1];
+  }
+  __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
   if (s >= J) return;
   double u = uni[s * nq];
@@ -234,7 +271,13 @@ k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
     u = 0.0;
   }
   const double t = u * *Zp;
-  int64_t lo = 0, hi = I;
+  int64_t klo = 0, khi = nc;
+  while (klo < khi) {
+    const int64_t mid = (klo + khi) >> 1;
+    if (t < coarse[mid]) khi = mid; else klo = mid + 1;
+  }
+  int64_t lo = klo * cs, hi = lo + cs < I ? lo + cs : I;
+  if (lo > I) lo = I;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if (t < cdf[mid]) hi = mid; else lo = mid + 1;
@@ -586,9 +629,11 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
              hipStream_t st) {
   const int nq = ml.n;
   const dim3 g(ceil_div(J, ST)), b(ST), gl(ceil_div(J, 16 * (ST / WAVE)));
+  int cs = 64;  // CDF rows per coarse entry
+  while ((ml.I[0] + cs - 1) / cs > FIRST_COARSE) cs *= 2;
   hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
                      static_cast<const T *>(ml.U[0]), ml.I[0], R, ml.cdf[0],
-                     ml.Z[0], ml.last[0], uni, nq, J, sidx, w.h, err);
+                     ml.Z[0], ml.last[0], uni, nq, J, cs, sidx, w.h, err);
   CPR_LAUNCH_CHECK();
   for (int q = 1; q < nq; ++q) {
     const double *tree = ml.tree[q], *Gg = ml.Ggt[q];
@@ -615,28 +660,39 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
 
 }  // namespace
 
+// leaves per block of the build: LB x P doubles in at most 48 KiB of LDS
+int tree_leaf_shift(int R, int64_t P2) {
+  const int64_t bytes = (int64_t)sts_packed(R) * 8;
+  int lb = 0;
+  while ((2 << lb) <= TB_LBMAX && (2 << lb) * bytes <= 49152 &&
+         (int64_t(2) << lb) <= P2)
+    ++lb;
+  return lb;
+}
+
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
                hipStream_t s) {
-  const int P = sts_packed(R), RP = sts_pad(R);
-  const int LB = (int)(P2 < 64 ? P2 : 64);
-  const int nt = (R + 15) / 16;
-  const dim3 g((unsigned)(P2 / LB)), b(256);
-  switch (nt) {
-    case 1: hipLaunchKernelGGL((k_tree_leaves<T, 1>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 2: hipLaunchKernelGGL((k_tree_leaves<T, 2>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 3: hipLaunchKernelGGL((k_tree_leaves<T, 3>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 4: hipLaunchKernelGGL((k_tree_leaves<T, 4>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 5: hipLaunchKernelGGL((k_tree_leaves<T, 5>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 6: hipLaunchKernelGGL((k_tree_leaves<T, 6>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    case 7: hipLaunchKernelGGL((k_tree_leaves<T, 7>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
-    default: hipLaunchKernelGGL((k_tree_leaves<T, 8>), g, b, 0, s, U, I, R, RP, F, P2, LB, tree); break;
+  const int lb = tree_leaf_shift(R, P2);
+  const size_t lds = ((size_t)1 << lb) * sts_packed(R) * 8;
+  const dim3 g((unsigned)(P2 >> lb)), b(256);
+  switch ((R + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_tree_build<T, 1>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
+    case 2: hipLaunchKernelGGL((k_tree_build<T, 2>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
+    case 3: hipLaunchKernelGGL((k_tree_build<T, 3>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
+    default: hipLaunchKernelGGL((k_tree_build<T, 4>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
   }
   CPR_LAUNCH_CHECK();
-  for (int64_t cnt = P2 / LB / 2; cnt >= 1; cnt /= 2) {
-    hipLaunchKernelGGL(k_tree_level, dim3(ceil_div(cnt * P, 256)), dim3(256),
-                       0, s, tree, cnt, cnt, P);
+  // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1
+  const int P = sts_packed(R);
+  for (int64_t n = P2 >> lb; n > 1;) {
+    int gs = 0;
+    while (gs < 3 && (int64_t(2) << gs) <= n) ++gs;
+    const int G = 1 << gs;
+    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(n / G)), dim3(256), 0, s,
+                       tree, n, G, P);
     CPR_LAUNCH_CHECK();
+    n /= G;
   }
 }
 template void sts_build<float>(const float *, int64_t, int, int, int64_t,
