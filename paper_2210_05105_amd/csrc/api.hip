@@ -510,6 +510,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   c->w.rec_cap = cap;
   dalloc(c, &c->w.rec, (size_t)cap * bucket_record_bytes((int)ts));
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
+  dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);
   dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);
   zero_fill<int64_t>(c->w.stats, 4, c->s);
   dalloc(c, &c->M, (size_t)c->max_I * R * ts);

@@ -163,6 +163,7 @@ struct SampleWork {
   int64_t *uq_off;   // J+1: extracted-nonzero offsets
   int64_t *uq_base;  // J: index position of extracted nonzero e = uq_base + e
   int64_t *tile_first;  // bucket_tiles(rec_cap): column at each tile start
+  int32_t *item_bk;  // bucket_max_items(rec_cap, buckets): bucket of an item
   int64_t max_u;     // J (bound on distinct columns)
   int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows

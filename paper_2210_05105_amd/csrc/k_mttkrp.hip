@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(MT_THREADS)
 k_bk_count(const int64_t *counts, const int64_t *uq_off,
            const int64_t *tile_first, const int64_t *uq_base,
            const int32_t *row, int nbk, int bb, int64_t *bk_total) {
-  __shared__ uint32_t hist[BK_LDS_MAX];
+  extern __shared__ uint32_t hist[];  // nbk when nbk <= BK_LDS_MAX
   __shared__ int32_t cst[BK_TILE + 1];
   const int64_t nz = counts[1];
   const bool use_lds = nbk <= BK_LDS_MAX;
@@ -283,6 +283,14 @@ __global__ void k_bk_items(const int64_t *bk_total, int nbk, int64_t *items) {
   items[b] = b < nbk ? (bk_total[b] + BK_SLICE - 1) / BK_SLICE : 0;
 }
 
+// item_bk[i] = bucket of accumulation item i
+__global__ void k_bk_itemmap(const int64_t *item_start, int nbk,
+                             int32_t *item_bk) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbk) return;
+  for (int64_t i = item_start[b]; i < item_start[b + 1]; ++i) item_bk[i] = b;
+}
+
 // One extracted nonzero in bucket order: key = (draw id << 8) | row % B.
 template <typename T>
 struct BkRec {
@@ -297,8 +305,8 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
              const int64_t *uq_base, const int32_t *row, const T *val, int nbk,
              int bb, const int64_t *bk_start, int64_t *bk_fill,
              BkRec<T> *rec) {
-  __shared__ uint32_t cnt[BK_LDS_MAX];
-  __shared__ uint32_t base[BK_LDS_MAX];  // record positions (< 2^32)
+  extern __shared__ uint32_t sc_lds[];  // cnt, base: nbk each (<= BK_LDS_MAX)
+  uint32_t *cnt = sc_lds, *base = sc_lds + nbk;  // base: record positions
   __shared__ int32_t cst[BK_TILE + 1];
   const int64_t nz = counts[1];
   const bool use_lds = nbk <= BK_LDS_MAX;
@@ -369,48 +377,53 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
 }
 
 // Accumulation without floating-point LDS atomics (they run at a small
-// fraction of LDS speed): the slice's records are counting-sorted by row of
-// the bucket in LDS (integer atomics only); each group of L lanes (lanes
-// over columns) then walks a contiguous chunk of the sorted records,
-// accumulating runs of one row in registers and adding each run to the LDS
-// copy of the bucket's rows once.  Only runs cut by a chunk boundary meet
-// another group on the same row, so the remaining float atomics are few.
-template <typename T, int L>
+// fraction of LDS speed): the slice's records (read once into registers)
+// are counting-sorted by row of the bucket in LDS with integer atomics;
+// each group of L lanes, VW consecutive columns per lane, then walks a
+// contiguous chunk of the sorted records, 16 records (and their h rows) in
+// flight at a time, accumulating runs of one row in registers.  A row inside
+// the chunk belongs to the group alone and is stored; only rows cut by a
+// chunk boundary are added with atomics.
+constexpr int AC_ITEMS = BK_SLICE / MT_THREADS;  // records per thread
+constexpr int AC_BATCH = 8;  // records per batch (two batches in flight)
+
+template <typename T, int L, int VW>
 __global__ void __launch_bounds__(MT_THREADS)
-k_bk_accum(const int64_t *item_start, const int64_t *bk_start, int nbk, int bb,
-           const BkRec<T> *rec, const T *h, int R, int64_t I, T *M, T *part) {
-  constexpr int G = MT_THREADS / L;         // lane groups per block
-  constexpr int CPL = (MAXR + L - 1) / L;   // columns per lane (max)
+k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
+           const int64_t *bk_start, int nbk, int bb, const BkRec<T> *rec,
+           const T *h, int R, int64_t I, T *M, T *part) {
+  constexpr int G = MT_THREADS / L;  // lane groups per block
   extern __shared__ unsigned char bk_lds_raw[];
-  T *blk = reinterpret_cast<T *>(bk_lds_raw);          // B x R
+  T *blk = reinterpret_cast<T *>(bk_lds_raw);                // B x R
   const int B = 1 << bb;
-  T *lc = blk + B * R;                                 // BK_SLICE coefs
-  int32_t *ls = reinterpret_cast<int32_t *>(lc + BK_SLICE);  // draw ids
-  uint8_t *lr = reinterpret_cast<uint8_t *>(ls + BK_SLICE);  // rows
+  T *lc = blk + B * R;                                       // BK_SLICE coefs
+  uint32_t *lk = reinterpret_cast<uint32_t *>(lc + BK_SLICE);  // keys
   __shared__ int32_t cnt[256 + 1];
   __shared__ int32_t wsum[MT_THREADS / WAVE];
   const int t = threadIdx.x, l = lane_id();
-  const int gl = l % L, g = t / L;
-  const int ncl = (R + L - 1) / L;
+  const int gl = t % L, g = t / L;
   const int64_t nitems = item_start[nbk];
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-    int64_t lo = 0, hi = nbk;  // bucket: last b with item_start[b] <= item
-    while (hi - lo > 1) {
-      int64_t m = (lo + hi) >> 1;
-      if (item_start[m] <= item) lo = m; else hi = m;
-    }
-    const int bk = (int)lo;
+    const int bk = item_bk[item];
     const int64_t k = item - item_start[bk];
     const int64_t r0 = bk_start[bk] + k * BK_SLICE;
     const int64_t r1 = r0 + BK_SLICE < bk_start[bk + 1] ? r0 + BK_SLICE
                                                           : bk_start[bk + 1];
     const int n = (int)(r1 - r0);
     const bool single = item_start[bk + 1] - item_start[bk] == 1;
+    // this thread's records: positions t, t + 256, ...
+    BkRec<T> my[AC_ITEMS];
+#pragma unroll
+    for (int i = 0; i < AC_ITEMS; ++i) {
+      const int e = i * MT_THREADS + t;
+      my[i] = rec[r0 + (e < n ? e : n - 1)];
+    }
     for (int e = t; e < B * R; e += MT_THREADS) blk[e] = T(0);
     for (int e = t; e <= 256; e += MT_THREADS) cnt[e] = 0;
     __syncthreads();
-    for (int e = t; e < n; e += MT_THREADS)
-      atomicAdd(&cnt[rec[r0 + e].key & 255u], 1);
+#pragma unroll
+    for (int i = 0; i < AC_ITEMS; ++i)
+      if (i * MT_THREADS + t < n) atomicAdd(&cnt[my[i].key & 255u], 1);
     __syncthreads();
     {  // exclusive scan of the 256 row counts (thread t owns row t)
       const int w = t / WAVE;
@@ -427,77 +440,81 @@ k_bk_accum(const int64_t *item_start, const int64_t *bk_start, int nbk, int bb,
       if (t < 256) cnt[t] = off + inc - v;  // becomes the fill cursor
       __syncthreads();
     }
-    for (int e = t; e < n; e += MT_THREADS) {
-      const BkRec<T> rc = rec[r0 + e];
-      const int rr = (int)(rc.key & 255u);
-      const int pos = atomicAdd(&cnt[rr], 1);
-      ls[pos] = (int32_t)(rc.key >> 8);
-      lc[pos] = rc.coef;
-      lr[pos] = (uint8_t)rr;
-    }
+#pragma unroll
+    for (int i = 0; i < AC_ITEMS; ++i)
+      if (i * MT_THREADS + t < n) {
+        const int pos = atomicAdd(&cnt[my[i].key & 255u], 1);
+        lk[pos] = my[i].key;
+        lc[pos] = my[i].coef;
+      }
     __syncthreads();
-    // group g: sorted records [c0, c1)
+    // group g: sorted records [c0, c1); lane gl owns columns gl VW ..
     const int per = (n + G - 1) / G;
     const int c0 = g * per < n ? g * per : n;
     const int c1 = c0 + per < n ? c0 + per : n;
-    T acc[CPL];
+    const int cb = gl * VW;
+    T acc[VW];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) acc[q] = T(0);
-    int cur = c0 < c1 ? lr[c0] : -1;
+    for (int q = 0; q < VW; ++q) acc[q] = T(0);
+    int cur = c0 < c1 ? (int)(lk[c0] & 255u) : -1;
     // rows also held by the neighbouring chunks take LDS float atomics
     // (slow); every other row belongs to this group alone and is stored
-    const int row_a = (c0 < c1 && c0 > 0 && lr[c0 - 1] == lr[c0]) ? lr[c0] : -1;
-    const int row_b = (c0 < c1 && c1 < n && lr[c1] == lr[c1 - 1]) ? lr[c1 - 1] : -1;
+    const int row_a = (c0 < c1 && c0 > 0 && ((lk[c0 - 1] ^ lk[c0]) & 255u) == 0)
+                          ? (int)(lk[c0] & 255u) : -1;
+    const int row_b = (c0 < c1 && c1 < n && ((lk[c1] ^ lk[c1 - 1]) & 255u) == 0)
+                          ? (int)(lk[c1 - 1] & 255u) : -1;
     auto flush = [&](int row) {
-      T *br = blk + row * R;
+      T *br = blk + row * R + cb;
       const bool shared = row == row_a || row == row_b;
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int c = gl + q * L;
-        if (q < ncl && c < R) {
-          if (shared) atomicAdd(br + c, acc[q]);
-          else br[c] = acc[q];
+      for (int q = 0; q < VW; ++q) {
+        if (cb + q < R) {
+          if (shared) atomicAdd(br + q, acc[q]);
+          else br[q] = acc[q];
         }
         acc[q] = T(0);
       }
     };
-    int kk = c0;
-    for (; kk + 4 <= c1; kk += 4) {
-      T hv[4][CPL];
-      int rw[4];
-      T cf[4];
+    // two batches of AC_BATCH records: the next is loaded while the
+    // current one is accumulated
+    struct Batch {
+      T hv[AC_BATCH][VW];
+      T cf[AC_BATCH];
+      int rw[AC_BATCH];
+    };
+    auto load_batch = [&](int kk, Batch &bt) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        rw[u] = lr[kk + u];
-        cf[u] = lc[kk + u];
-        const T *hr = h + (int64_t)ls[kk + u] * R;
+      for (int u = 0; u < AC_BATCH; ++u) {
+        const int kc = kk + u < c1 ? kk + u : c1 - 1;
+        const uint32_t key = lk[kc];
+        bt.rw[u] = kk + u < c1 ? (int)(key & 255u) : -1;
+        bt.cf[u] = lc[kc];
+        const T *hr = h + (int64_t)(key >> 8) * R;
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          const int c = gl + q * L;
-          hv[u][q] = hr[c < R ? c : 0];
-        }
+        for (int q = 0; q < VW; ++q)
+          bt.hv[u][q] = hr[cb + q < R ? cb + q : R - 1];
       }
+    };
+    auto run_batch = [&](const Batch &bt) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (rw[u] != cur) {
+      for (int u = 0; u < AC_BATCH; ++u) {
+        if (bt.rw[u] < 0) break;
+        if (bt.rw[u] != cur) {
           flush(cur);
-          cur = rw[u];
+          cur = bt.rw[u];
         }
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) acc[q] += cf[u] * hv[u][q];
+        for (int q = 0; q < VW; ++q) acc[q] += bt.cf[u] * bt.hv[u][q];
       }
-    }
-    for (; kk < c1; ++kk) {
-      const int rw = lr[kk];
-      if (rw != cur) {
-        flush(cur);
-        cur = rw;
-      }
-      const T *hr = h + (int64_t)ls[kk] * R;
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int c = gl + q * L;
-        acc[q] += lc[kk] * hr[c < R ? c : 0];
+    };
+    if (c0 < c1) {
+      Batch b0, b1;
+      load_batch(c0, b0);
+      for (int kk = c0; kk < c1; kk += 2 * AC_BATCH) {
+        if (kk + AC_BATCH < c1) load_batch(kk + AC_BATCH, b1);
+        run_batch(b0);
+        if (kk + 2 * AC_BATCH < c1) load_batch(kk + 2 * AC_BATCH, b0);
+        if (kk + AC_BATCH < c1) run_batch(b1);
       }
     }
     if (cur >= 0) flush(cur);
@@ -667,23 +684,27 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   zero_fill<int64_t>(bk_total, 2 * (nbk + 1), s);  // totals and fill cursors
   hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
                      w.counts, w.uq_off, w.tile_first);
-  hipLaunchKernelGGL(k_bk_count, gt, b, 0, s, w.counts, w.uq_off, w.tile_first,
-                     w.uq_base, row, nbk, bb, bk_total);
+  const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
+  hipLaunchKernelGGL(k_bk_count, gt, b, hl, s, w.counts, w.uq_off,
+                     w.tile_first, w.uq_base, row, nbk, bb, bk_total);
   CPR_LAUNCH_CHECK();
   exclusive_scan_i64(bk_total, bk_start, nbk + 1, w.scan_tmp, s);
   hipLaunchKernelGGL(k_bk_items, dim3(ceil_div(nbk + 1, 256)), b, 0, s,
                      bk_total, nbk, items);
   CPR_LAUNCH_CHECK();
   exclusive_scan_i64(items, item_start, nbk + 1, w.scan_tmp, s);
+  hipLaunchKernelGGL(k_bk_itemmap, dim3(ceil_div(nbk, 256)), b, 0, s,
+                     item_start, nbk, w.item_bk);
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
-  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 0, s, w.counts, w.uq_s, w.uq_w,
+  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 2 * hl, s, w.counts, w.uq_s, w.uq_w,
                      w.uq_off, w.tile_first, w.uq_base, row, val, nbk, bb,
                      bk_start, bk_fill, rec);
   CPR_LAUNCH_CHECK();
   const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
-                     (size_t)BK_SLICE * (sizeof(T) + 4 + 1);
-  static bool attr_set[2][4] = {};
+                     (size_t)BK_SLICE * (sizeof(T) + 4);
+  constexpr int VW = 16 / sizeof(T);  // columns per lane
+  static bool attr_set[2][7] = {};
   auto launch = [&](auto kern, int li) {
     if (!attr_set[sizeof(T) == 8][li]) {
       hipError_t e = hipFuncSetAttribute(
@@ -692,13 +713,17 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
       if (e != hipSuccess) throw HipFail(e, __FILE__, __LINE__);
       attr_set[sizeof(T) == 8][li] = true;
     }
-    hipLaunchKernelGGL(kern, gt, b, lds, s, item_start, bk_start, nbk, bb, rec,
-                       h, R, I, M, part);
+    hipLaunchKernelGGL(kern, gt, b, lds, s, item_start, w.item_bk, bk_start,
+                       nbk, bb, rec, h, R, I, M, part);
   };
-  if (R <= 8) launch(k_bk_accum<T, 8>, 0);
-  else if (R <= 16) launch(k_bk_accum<T, 16>, 1);
-  else if (R <= 32) launch(k_bk_accum<T, 32>, 2);
-  else launch(k_bk_accum<T, 64>, 3);
+  const int lanes = (R + VW - 1) / VW;  // lanes per record
+  if (lanes <= 1) launch(k_bk_accum<T, 1, VW>, 0);
+  else if (lanes <= 2) launch(k_bk_accum<T, 2, VW>, 1);
+  else if (lanes <= 4) launch(k_bk_accum<T, 4, VW>, 2);
+  else if (lanes <= 8) launch(k_bk_accum<T, 8, VW>, 3);
+  else if (lanes <= 16) launch(k_bk_accum<T, 16, VW>, 4);
+  else if (lanes <= 32) launch(k_bk_accum<T, 32, VW>, 5);
+  else launch(k_bk_accum<T, 64, VW>, 6);
   CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_bk_combine<T>), gt, b, 0, s, item_start, nbk, bb, R, I,
                      part, M);
