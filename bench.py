@@ -40,6 +40,10 @@ def parse():
     p.add_argument("--leaf", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
+    p.add_argument("--reduce-counters", nargs=3,
+                   metavar=("FETCH_DB", "WRITE_DB", "SOLVES"),
+                   help="reduce two rocprofv3 --pmc databases to HBM bytes "
+                        "per mode solve and exit")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also copy MIB MiB device to device (a plain copy "
                         "kernel of known size, to scale HBM counters)")
@@ -123,8 +127,66 @@ def cpu_baseline(T, w, ctx, J, N, R, sampler):
                 seconds_per_sweep_extrapolated=per_sweep)
 
 
+# kernel sets whose HBM traffic is reported, and the sources they come from
+KERNEL_SETS = {"sts_draw": ("k_sts_", ["k_sts.hip"]),
+               "sampled_mttkrp": ("k_bk_", ["k_mttkrp.hip"])}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf3_sts_fp32.json")
+
+
+def source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2210_05105_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def reduce_counters(fetch_db, write_db, solves, calib_mib):
+    """HBM bytes per mode solve of each kernel set, from two rocprofv3 --pmc
+    databases (FETCH_SIZE, WRITE_SIZE; KiB per dispatch).  Each counter is
+    scaled by the ratio of the known size of the first device-to-device
+    copies of the process (--copy-calibration) to what the counter reads for
+    them."""
+    import sqlite3
+    out = {}
+    for name, db in (("fetch", fetch_db), ("write", write_db)):
+        cur = sqlite3.connect(db).cursor()
+        rows = list(cur.execute(
+            "select kernel_name, value from counters_collection "
+            "order by dispatch_id"))
+        copies = [v for k, v in rows if "copyBuffer" in k][:3]
+        factor = calib_mib * 1024.0 / (sum(copies) / len(copies))
+        for ks, (prefix, _) in KERNEL_SETS.items():
+            kib = sum(v for k, v in rows if prefix in k)
+            d = out.setdefault(ks, {})
+            d[name + "_bytes_per_solve"] = kib * 1024.0 * factor / solves
+            d[name + "_factor"] = factor
+    for ks, (_, files) in KERNEL_SETS.items():
+        out[ks]["source_digest"] = source_digest(files)
+    return out
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel set from the committed counter
+    summary, or None if absent or taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest(KERNEL_SETS[kernel][1]):
+        return None
+    return t["fetch_bytes_per_solve"] + t["write_bytes_per_solve"]
+
+
 def main():
     a = parse()
+    if a.reduce_counters:
+        fdb, wdb, solves = a.reduce_counters
+        print(json.dumps(reduce_counters(fdb, wdb, float(solves),
+                                         a.copy_calibration or 256), indent=1))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the "
               f"multi-GPU layout is described in DESIGN.md", file=sys.stderr)
@@ -133,6 +195,15 @@ def main():
     from paper_2210_05105_amd import Context, load_library
     load_library()
     dev = torch.device("cuda:0")
+    if a.copy_calibration:  # first copies of the process: known size
+        n = a.copy_calibration * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {a.copy_calibration} MiB")
+        del src_t, dst_t
     w = dict(tg.WORKLOADS[a.workload])
     if a.workload == "zipf3":
         R, J, sampler = w["R"], w["J"], w["sampler"]
@@ -210,27 +281,19 @@ def main():
             ach = fl / (ms_dom * 1e-3) / 1e12
             roof = dict(kernel="sts_draw", bound="mfma", achieved=ach,
                         peak=FP64_PEAK_TFS, unit="TFLOP/s",
-                        frac=ach / FP64_PEAK_TFS, traffic=None,
+                        frac=ach / FP64_PEAK_TFS,
+                        traffic=measured_traffic("sts_draw"),
                         flops_per_launch=fl, ms_per_launch=ms_dom)
         elif dom == "mttkrp":
             roof = dict(kernel="sampled_mttkrp", bound="hbm",
                         achieved=mttkrp["achieved_GBs"], peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=mttkrp["frac_of_peak"],
-                        traffic=None, bytes_per_launch=mtt_bytes,
-                        ms_per_launch=ms_mtt)
+                        traffic=measured_traffic("sampled_mttkrp"),
+                        bytes_per_launch=mtt_bytes, ms_per_launch=ms_mtt)
         else:
             roof = dict(kernel=dom, bound="latency", achieved=None,
                         peak=None, unit=None, frac=None, traffic=None,
                         ms_per_launch=ms_dom)
-    if a.copy_calibration:
-        n = a.copy_calibration * (1 << 20) // 4
-        src_t = torch.ones(n, dtype=torch.float32, device=dev)
-        dst_t = torch.empty_like(src_t)
-        for _ in range(3):
-            dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {a.copy_calibration} MiB")
-        del src_t, dst_t
     cpu = None
     if not a.no_cpu_baseline:
         log("timing the oracle on the host ...")
