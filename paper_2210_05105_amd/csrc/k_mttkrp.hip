@@ -387,7 +387,24 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
 constexpr int AC_ITEMS = BK_SLICE / MT_THREADS;  // records per thread
 constexpr int AC_BATCH = 8;  // records per batch (two batches in flight)
 
-template <typename T, int L, int VW>
+// VW consecutive columns of an h row as one 16-byte load (R a multiple of
+// VW; rows are then 16-byte aligned) or VW clamped loads
+template <typename T, int VW, bool VEC>
+__device__ __forceinline__ void load_cols(const T *hr, int cb, int R,
+                                          T (&out)[VW]) {
+  if constexpr (VEC) {
+    const int c = cb <= R - VW ? cb : R - VW;
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    const vec_t v = *reinterpret_cast<const vec_t *>(hr + c);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) out[q] = v[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < VW; ++q) out[q] = hr[cb + q < R ? cb + q : R - 1];
+  }
+}
+
+template <typename T, int L, int VW, bool VEC>
 __global__ void __launch_bounds__(MT_THREADS)
 k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
            const int64_t *bk_start, int nbk, int bb, const BkRec<T> *rec,
@@ -489,10 +506,7 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
         const uint32_t key = lk[kc];
         bt.rw[u] = kk + u < c1 ? (int)(key & 255u) : -1;
         bt.cf[u] = lc[kc];
-        const T *hr = h + (int64_t)(key >> 8) * R;
-#pragma unroll
-        for (int q = 0; q < VW; ++q)
-          bt.hv[u][q] = hr[cb + q < R ? cb + q : R - 1];
+        load_cols<T, VW, VEC>(h + (int64_t)(key >> 8) * R, cb, R, bt.hv[u]);
       }
     };
     auto run_batch = [&](const Batch &bt) {
@@ -704,7 +718,7 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
                      (size_t)BK_SLICE * (sizeof(T) + 4);
   constexpr int VW = 16 / sizeof(T);  // columns per lane
-  static bool attr_set[2][7] = {};
+  static bool attr_set[2][14] = {};
   auto launch = [&](auto kern, int li) {
     if (!attr_set[sizeof(T) == 8][li]) {
       hipError_t e = hipFuncSetAttribute(
@@ -717,13 +731,23 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                        nbk, bb, rec, h, R, I, M, part);
   };
   const int lanes = (R + VW - 1) / VW;  // lanes per record
-  if (lanes <= 1) launch(k_bk_accum<T, 1, VW>, 0);
-  else if (lanes <= 2) launch(k_bk_accum<T, 2, VW>, 1);
-  else if (lanes <= 4) launch(k_bk_accum<T, 4, VW>, 2);
-  else if (lanes <= 8) launch(k_bk_accum<T, 8, VW>, 3);
-  else if (lanes <= 16) launch(k_bk_accum<T, 16, VW>, 4);
-  else if (lanes <= 32) launch(k_bk_accum<T, 32, VW>, 5);
-  else launch(k_bk_accum<T, 64, VW>, 6);
+  if (R % VW == 0) {
+    if (lanes <= 1) launch(k_bk_accum<T, 1, VW, true>, 0);
+    else if (lanes <= 2) launch(k_bk_accum<T, 2, VW, true>, 1);
+    else if (lanes <= 4) launch(k_bk_accum<T, 4, VW, true>, 2);
+    else if (lanes <= 8) launch(k_bk_accum<T, 8, VW, true>, 3);
+    else if (lanes <= 16) launch(k_bk_accum<T, 16, VW, true>, 4);
+    else if (lanes <= 32) launch(k_bk_accum<T, 32, VW, true>, 5);
+    else launch(k_bk_accum<T, 64, VW, true>, 6);
+  } else {
+    if (lanes <= 1) launch(k_bk_accum<T, 1, VW, false>, 7);
+    else if (lanes <= 2) launch(k_bk_accum<T, 2, VW, false>, 8);
+    else if (lanes <= 4) launch(k_bk_accum<T, 4, VW, false>, 9);
+    else if (lanes <= 8) launch(k_bk_accum<T, 8, VW, false>, 10);
+    else if (lanes <= 16) launch(k_bk_accum<T, 16, VW, false>, 11);
+    else if (lanes <= 32) launch(k_bk_accum<T, 32, VW, false>, 12);
+    else launch(k_bk_accum<T, 64, VW, false>, 13);
+  }
   CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_bk_combine<T>), gt, b, 0, s, item_start, nbk, bb, R, I,
                      part, M);
