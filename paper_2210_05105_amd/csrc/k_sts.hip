@@ -179,7 +179,9 @@ __device__ __forceinline__ void stage_pad(double *dst, const double *A, int R) {
   }
 }
 
-// B fragments of a zero-padded RP x RP matrix held in LDS
+// B fragments of a zero-padded symmetric RP x RP matrix held in LDS, for
+// tile_mass: block (k-tile, tile t) is used only for k-tile <= t, the blocks
+// below the diagonal doubled
 template <int NT>
 __device__ __forceinline__ void lds_bfrag(const double *sA,
                                           double (&f)[NT][4 * NT]) {
@@ -188,11 +190,17 @@ __device__ __forceinline__ void lds_bfrag(const double *sA,
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int ks = 0; ks < 4 * NT; ++ks)
-      f[t][ks] = sA[(4 * ks + l / 16) * RP + 16 * t + (l % 16)];
+    for (int ks = 0; ks < 4 * (t + 1); ++ks)
+      f[t][ks] = (ks / 4 < t ? 2.0 : 1.0) *
+                 sA[(4 * ks + l / 16) * RP + 16 * t + (l % 16)];
 }
 
-// masses of the 16 rows: lanes of group l / 16 get row l / 16 + 4 v in ms[v]
+// Masses x_i^T Q x_i of 16 rows for a symmetric Q: with X_t the 16-column
+// tiles of X and Q_{ut} the blocks of Q,
+//   x^T Q x = sum_t x_t^T (Q_tt x_t + 2 sum_{u<t} Q_ut^T x_u),
+// so tile t needs D_t = X_t Q_tt + 2 sum_{u<t} X_u Q_ut (k-tiles u <= t) and
+// the row-dot of D_t with X_t: NT (NT + 1) / 2 blocks of 4 MFMA k-steps
+// instead of NT^2.  Lanes of group l / 16 get row l / 16 + 4 v in ms[v].
 template <int NT>
 __device__ __forceinline__ void tile_mass(const double (&xA)[4 * NT],
                                           const double (&xD)[NT][4],
@@ -204,7 +212,7 @@ __device__ __forceinline__ void tile_mass(const double (&xA)[4 * NT],
   for (int t = 0; t < NT; ++t) {
     double4_t acc = double4_t{0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < 4 * NT; ++ks)
+    for (int ks = 0; ks < 4 * (t + 1); ++ks)
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xA[ks], qB[t][ks], acc, 0, 0,
                                                  0);
 #pragma unroll
@@ -234,6 +242,45 @@ __device__ __forceinline__ void load_hfrag(const double *hb, int32_t s,
     for (int t = 0; t < NT; ++t)
       xD[t][v] = hb[(int64_t)sd * RP + 16 * t + (l % 16)];
   }
+}
+
+// Order one wave's LDS writes before its reads of other lanes' data.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS row stride of a staged 16-row tile: RP + 1 doubles, so the 16 rows
+// of a fragment read fall in different banks
+template <int NT>
+constexpr int tile_stride() { return 16 * NT + 1; }
+
+// The h rows (stride RP, 16-byte aligned) of the 16 samples held by lanes
+// 0..15, staged in the wave's LDS buffer (16 x (RP + 1) doubles) with
+// 16-byte loads, then read in A and D fragment layouts.
+template <int NT>
+__device__ __forceinline__ void load_hfrag_lds(const double *hb, int32_t s,
+                                               double *buf,
+                                               double (&xA)[4 * NT],
+                                               double (&xD)[NT][4]) {
+  constexpr int RP = 16 * NT, RS = tile_stride<NT>(), CH = RP / 2;
+  const int l = lane_id();
+#pragma unroll
+  for (int i = 0; i < (16 * CH) / WAVE; ++i) {
+    const int e = i * WAVE + l, r = e / CH, c = e % CH;
+    const int32_t sr = __shfl(s, r, WAVE);
+    const double2 v = *reinterpret_cast<const double2 *>(hb + (int64_t)sr * RP + 2 * c);
+    buf[r * RS + 2 * c] = v.x;
+    buf[r * RS + 2 * c + 1] = v.y;
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int ks = 0; ks < 4 * NT; ++ks) xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) xD[t][v] = buf[(l / 16 + 4 * v) * RS + 16 * t + (l % 16)];
 }
 
 // mass of the tile row held by this lane (lane 16 tau + i gets row i)
@@ -306,6 +353,7 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
            SlotBuf out, uint32_t *err) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
   __shared__ double sQ[RP * RP];  // G_{>k} (*) G^root, zeros beyond R
+  __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
   const int64_t g0 = (int64_t)blockIdx.x * ST + threadIdx.x;
   for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * ST) {
     w.lc[i] = 0;
@@ -330,7 +378,7 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
   const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
   double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
   lds_bfrag<NT>(sQ, qB);
-  load_hfrag<NT>(w.h, s, 0, xA, xD);
+  load_hfrag_lds<NT>(w.h, s, sH[threadIdx.x / WAVE], xA, xD);
   tile_mass<NT>(xA, xD, qB, ms);
   const double Z = lane_mass(ms);
   if (!act) return;
@@ -361,6 +409,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   __shared__ double sh_t[64], sh_m[64];
   __shared__ int32_t sh_r[64];
   __shared__ double sG[RP * RP];  // G_{>k}, zeros beyond R
+  __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
   const int64_t pb = (int64_t)blockIdx.x * 64;
   if (pb >= J) return;
   const int l = lane_id(), wv = threadIdx.x / WAVE;
@@ -378,17 +427,17 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
   // h fragments of the 16 slots and the node of slot 0, loaded together
   double xA[4 * NT], xD[NT][4];
-  load_hfrag<NT>(w.h, s, 0, xA, xD);
+  load_hfrag_lds<NT>(w.h, s, sH[wv], xA, xD);
   const uint64_t actm = __ballot(act);
   const int ld0 = actm ? __ffsll((long long)actm) - 1 : 0;
   int32_t v0 = __shfl(v, ld0, WAVE);
-  double nv[NT][4 * NT];
+  double nv[NT][4 * NT];  // node blocks used by tile_mass (k-tile <= tile)
   auto load_node = [&](int32_t vn) {
     const double *nd = tree + (int64_t)(2 * vn) * P;
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-      for (int ks = 0; ks < 4 * NT; ++ks) {
+      for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
         const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
         nv[tt][ks] = nd[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
       }
@@ -409,9 +458,9 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-      for (int ks = 0; ks < 4 * NT; ++ks) {
+      for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
         const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
-        qB[tt][ks] = sG[k * RP + j] * nv[tt][ks];
+        qB[tt][ks] = (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j] * nv[tt][ks];
       }
     tile_mass<NT>(xA, xD, qB, ms);
     const double x = lane_mass(ms);
@@ -481,12 +530,13 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
 // sample's leaf; each sample accumulates its rows in order and takes
 // index = min{i : t < F(i)} over rows of positive mass.  Then h *= U[index].
 template <typename T, int NT>
-__global__ void __launch_bounds__(ST)
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(3)))
 k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
            int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
            uint32_t *err) {
   constexpr int RP = 16 * NT, KS = 4 * NT;
   __shared__ double sG[RP * RP];
+  __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
   stage_pad<RP>(sG, Gg, R);
   __syncthreads();
   const int l = lane_id();
@@ -500,53 +550,49 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
   const double t = in.t[ps];
   double gB[NT][KS], hA[KS], hD[NT][4];
   lds_bfrag<NT>(sG, gB);
-  load_hfrag<NT>(w.h, s, 0, hA, hD);
-  int64_t r0D[4];
+  double *buf = sH[threadIdx.x / WAVE];
+  load_hfrag_lds<NT>(w.h, s, buf, hA, hD);
+  // Pass r: row r of each slot's leaf, staged in the wave's LDS buffer with
+  // one coalesced load per lane and row (lane c < R: column c; rows past I
+  // give zeros).
+  constexpr int RS = tile_stride<NT>();
+  const int lc = l < R ? l : R - 1;
+  int32_t rr[16];  // first leaf row of slot i (rows < 2^31)
 #pragma unroll
-  for (int v = 0; v < 4; ++v) r0D[v] = __shfl(row0, l / 16 + 4 * v, WAVE);
-  // raw U fragments of row r of every slot's leaf, four rows in flight
-  struct RowBuf {
-    T a[KS];      // U[row0 + r][4 ks + l / 16]
-    T d[NT][4];   // U[row0(slot l / 16 + 4 v) + r][16 t + l % 16]
-  };
-  auto load_row = [&](int r, RowBuf &b) {
+  for (int i = 0; i < 16; ++i) rr[i] = __shfl((int32_t)row0, i, WAVE);
+  // raw U values of the next pass, loaded while this pass is on the MFMA
+  T raw[16];
+  auto load_pass = [&](int r) {
     r = r < F ? r : F - 1;
-    const int64_t row = row0 + r;
-    const T *ur = U + (row < I ? row : I - 1) * R;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k = 4 * ks + l / 16;
-      b.a[ks] = ur[k < R ? k : R - 1];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t rw = r0D[v] + r;
-      const T *uw = U + (rw < I ? rw : I - 1) * R;
-#pragma unroll
-      for (int tt = 0; tt < NT; ++tt) {
-        const int j = 16 * tt + (l % 16);
-        b.d[tt][v] = uw[j < R ? j : R - 1];
-      }
+    for (int i = 0; i < 16; ++i) {
+      const int64_t row = (int64_t)rr[i] + r;
+      raw[i] = U[(row < I ? row : I - 1) * R + lc];
     }
   };
   double pre = 0.0;
   int pick = -1, lastpos = -1;
-  // masses of row r from b, then b refilled with row r + 4
-  auto pass = [&](int r, RowBuf &b) {
-    double xA[KS], xD[NT][4], ms[4];
-    {
-      const double mask = row0 + r < I ? 1.0 : 0.0;
+  load_pass(0);
+  for (int r = 0; r < F; ++r) {
+    wave_lds_sync();  // the previous pass's fragment reads are done
+    if (l < RP) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) xA[ks] = (double)b.a[ks] * hA[ks] * mask;
+      for (int i = 0; i < 16; ++i) {
+        const int64_t row = (int64_t)rr[i] + r;
+        buf[i * RS + l] = (row < I && l < R) ? (double)raw[i] : 0.0;
+      }
     }
+    load_pass(r + 1);
+    wave_lds_sync();
+    double xA[KS], xD[NT][4], ms[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double mask = r0D[v] + r < I ? 1.0 : 0.0;
+    for (int ks = 0; ks < KS; ++ks)
+      xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16] * hA[ks];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
-        xD[tt][v] = (double)b.d[tt][v] * hD[tt][v] * mask;  // h zero beyond R
-    }
-    load_row(r + 4, b);
+        xD[tt][v] = buf[(l / 16 + 4 * v) * RS + 16 * tt + (l % 16)] * hD[tt][v];
     tile_mass<NT>(xA, xD, gB, ms);
     const double m = lane_mass(ms);  // lanes 0..15: row r of slot l
     if (pick < 0 && row0 + r < I && m > 0) {
@@ -554,17 +600,6 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
       lastpos = r;
       if (t < pre) pick = r;
     }
-  };
-  RowBuf b0, b1, b2, b3;
-  load_row(0, b0);
-  load_row(1, b1);
-  load_row(2, b2);
-  load_row(3, b3);
-  for (int r = 0; r < F; r += 4) {  // F is a multiple of 16
-    pass(r, b0);
-    pass(r + 1, b1);
-    pass(r + 2, b2);
-    pass(r + 3, b3);
   }
   const bool act = l < n;
   if (pick < 0) {
@@ -597,6 +632,7 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
             const double *trace, double *prob, T *h_out) {
   constexpr int RP = 16 * NT;
   __shared__ double sP[RP * RP];
+  __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
   stage_pad<RP>(sP, Gp, R);
   __syncthreads();
   const int l = lane_id();
@@ -606,7 +642,7 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
   const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
   double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
   lds_bfrag<NT>(sP, qB);
-  load_hfrag<NT>(hbuf, s, 0, xA, xD);
+  load_hfrag_lds<NT>(hbuf, s, sH[threadIdx.x / WAVE], xA, xD);
   tile_mass<NT>(xA, xD, qB, ms);
   const double mass = lane_mass(ms);
   if (l < n) prob[p0 + l] = mass / *trace;
