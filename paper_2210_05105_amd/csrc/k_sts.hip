@@ -401,7 +401,7 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
 // Wave 0 then places the block's 64 samples in their children's slot
 // ranges with one atomic per (node, side).
 template <int NT>
-__global__ void __launch_bounds__(ST)
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
 k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
             StsWork w, SlotBuf in, SlotBuf out) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
@@ -454,15 +454,18 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   uint64_t rem = actm;
   while (rem) {
     const uint64_t grp = __ballot(v == v0) & rem;
-    double qB[NT][4 * NT], ms[4];
+    // nv becomes the B fragments of G_{>k} (*) node in place; G_{>k} is
+    // read from LDS again in every pass rather than held in registers
+    asm volatile("" ::: "memory");
+    double ms[4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
         const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
-        qB[tt][ks] = (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j] * nv[tt][ks];
+        nv[tt][ks] *= (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j];
       }
-    tile_mass<NT>(xA, xD, qB, ms);
+    tile_mass<NT>(xA, xD, nv, ms);
     const double x = lane_mass(ms);
     if ((grp >> l) & 1ull) mL = x;
     rem &= ~grp;
@@ -530,7 +533,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
 // sample's leaf; each sample accumulates its rows in order and takes
 // index = min{i : t < F(i)} over rows of positive mass.  Then h *= U[index].
 template <typename T, int NT>
-__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
 k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
            int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
            uint32_t *err) {
@@ -548,8 +551,7 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
   const int32_t s = in.s[ps];
   const int64_t row0 = (int64_t)(in.v[ps] - P2) * F;
   const double t = in.t[ps];
-  double gB[NT][KS], hA[KS], hD[NT][4];
-  lds_bfrag<NT>(sG, gB);
+  double hA[KS], hD[NT][4];
   double *buf = sH[threadIdx.x / WAVE];
   load_hfrag_lds<NT>(w.h, s, buf, hA, hD);
   // Pass r: row r of each slot's leaf, staged in the wave's LDS buffer with
@@ -557,9 +559,9 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
   // give zeros).
   constexpr int RS = tile_stride<NT>();
   const int lc = l < R ? l : R - 1;
-  int32_t rr[16];  // first leaf row of slot i (rows < 2^31)
+  int32_t rr[16];  // first leaf row of slot i (rows < 2^31), wave-uniform
 #pragma unroll
-  for (int i = 0; i < 16; ++i) rr[i] = __shfl((int32_t)row0, i, WAVE);
+  for (int i = 0; i < 16; ++i) rr[i] = __builtin_amdgcn_readlane((int32_t)row0, i);
   // raw U values of the next pass, loaded while this pass is on the MFMA
   T raw[16];
   auto load_pass = [&](int r) {
@@ -584,7 +586,11 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
     }
     load_pass(r + 1);
     wave_lds_sync();
-    double xA[KS], xD[NT][4], ms[4];
+    // G_{>k} fragments are read from LDS again in every pass rather than
+    // held in registers
+    asm volatile("" ::: "memory");
+    double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
+    lds_bfrag<NT>(sG, gB);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
       xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16] * hA[ks];
