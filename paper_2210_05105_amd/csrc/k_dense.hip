@@ -204,6 +204,58 @@ __device__ bool chol_inverse(double *A, int R, double tol, double *W,
   return true;
 }
 
+// Inverse of the symmetric A (LDS, R <= 32) by Gauss-Jordan elimination
+// without row exchanges, in one wave: lane c < R holds column c of A and
+// lane R + c column c of the identity, R values each in registers.  Step k
+// scales row k by 1 / pivot and removes column k from every other row; the
+// multipliers (column k) come from lane k.  The pivots are those of the
+// LDL^T factorisation, all above tol for a clearly positive definite A;
+// the first one at or below tol stops it (returns false, Gp untouched).
+// Afterwards lane R + c holds column c of A^{-1}, written to Gp (global)
+// and sGp (LDS).
+__device__ __forceinline__ double readlane_f64(double x, int k) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, k);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ bool gj_inverse_wave(const double *A, int R,
+                                                double tol, double *Gp,
+                                                double *sGp) {
+  const int l = lane_id();
+  double c[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    c[i] = i >= R ? 0.0 : l < R ? A[i * R + l] : (l - R == i ? 1.0 : 0.0);
+  // rows i >= R stay zero: their multipliers are zero
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    if (k < R && ok) {
+      const double piv = readlane_f64(c[k], k);
+      if (piv > tol) {
+        const double r = c[k] / piv;
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if (i != k) c[i] = fma(-readlane_f64(c[i], k), r, c[i]);
+        c[k] = r;
+      } else {
+        ok = false;
+      }
+    }
+  }
+  if (!ok) return false;
+  if (l >= R && l < 2 * R)
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < R) {
+        Gp[i * R + (l - R)] = c[i];
+        sGp[i * R + (l - R)] = c[i];
+      }
+  return true;
+}
+
 // Cyclic Jacobi eigendecomposition of the symmetric A (LDS); V in global.
 // Gp = V diag(1/lambda, lambda > R 2^-52 lambda_max) V^T.
 __device__ bool jacobi_pinv(double *A, int R, double *V, double *Gp,
@@ -301,15 +353,41 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   const int t = threadIdx.x;
   double tr = 0, dmax = 0;
   bool bad = false;
-  for (int e = t; e < R * R; e += PV_THREADS) {
-    double v = 1;
-    for (int i = 0; i < ml.n; ++i) v *= ml.G[i][e];
-    A[e] = v;
-    Gfull[e] = v;
-    if (!isfinite(v)) bad = true;
-    if (e / R == e % R) {
-      tr += v;
-      dmax = fmax(dmax, v);
+  // Hadamard product of the other modes' Grams, 4 entries per thread at a
+  // time with the loads of one Gram issued together (clamped, then masked)
+  const int RR = R * R;
+  for (int e0 = 0; e0 < RR; e0 += 4 * PV_THREADS) {
+    double hv[4] = {1.0, 1.0, 1.0, 1.0};
+    for (int i = ml.n - 1; i >= 0; --i) {
+      // STS: ggt[i] = Hadamard product of the Grams after i (times G^+ below)
+      if (ggt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = e0 + t + q * PV_THREADS;
+          if (e < RR) ggt[(int64_t)i * RR + e] = hv[q];
+        }
+      const double *Gi = ml.G[i];
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + t + q * PV_THREADS;
+        x[q] = Gi[e < RR ? e : RR - 1];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hv[q] *= x[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + t + q * PV_THREADS;
+      if (e >= RR) break;
+      const double v = hv[q];
+      A[e] = v;
+      Gfull[e] = v;
+      if (!isfinite(v)) bad = true;
+      if (e / R == e % R) {
+        tr += v;
+        dmax = fmax(dmax, v);
+      }
     }
   }
   if (bad) atomicOr(err, ERR_NONFINITE);
@@ -322,7 +400,18 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   __syncthreads();
   // L^{-1} next to A in LDS when both fit (R <= 64), else in scratch
   double *W = R <= 64 ? A + R * R : scratch;
-  bool ok = chol_inverse(A, R, tol, W, Gp, &flag);
+  bool ok;
+  if (R <= 32) {
+    if (t < WAVE) {
+      const bool g = gj_inverse_wave(A, R, tol, Gp, A + RR);
+      if (t == 0) flag = g ? 1 : 0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    ok = flag != 0;
+  } else {
+    ok = chol_inverse(A, R, tol, W, Gp, &flag);
+  }
   if (!ok) {
     __syncthreads();
     for (int e = t; e < R * R; e += PV_THREADS) A[e] = Gfull[e];
@@ -332,19 +421,24 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   }
   __threadfence();
   __syncthreads();
+  // G^+ in LDS beside G when both fit (the one-wave inverse put it there)
+  const double *gps = Gp;
+  if (R <= 64) {
+    if (!(R <= 32 && ok)) {
+      for (int e = t; e < RR; e += PV_THREADS) A[RR + e] = Gp[e];
+      __syncthreads();
+    }
+    gps = A + RR;
+  }
   // <G^+, G> and, for STS, G_{>k} = G^+ (*) Hadamard of later Grams
   double ip = 0;
-  for (int e = t; e < R * R; e += PV_THREADS) ip += Gp[e] * Gfull[e];
+  for (int e = t; e < RR; e += PV_THREADS) {
+    const double gp = gps[e];
+    ip += gp * Gfull[e];
+    for (int q = 0; q < (ggt ? ml.n : 0); ++q) ggt[(int64_t)q * RR + e] *= gp;
+  }
   ip = block_sum(ip, red);
   if (trace_out && t == 0) *trace_out = ip;
-  if (ggt) {
-    for (int q = 0; q < ml.n; ++q)
-      for (int e = t; e < R * R; e += PV_THREADS) {
-        double v = Gp[e];
-        for (int p = q + 1; p < ml.n; ++p) v *= ml.G[p][e];
-        ggt[(int64_t)q * R * R + e] = v;
-      }
-  }
 }
 
 // ---------------------------------------------------------------------------
