@@ -43,8 +43,6 @@ struct cp_ctx {
   int64_t *last[MAXN] = {};
   double *tree[MAXN] = {};
   int64_t P2[MAXN] = {};
-  double *sts_lev = nullptr, *sts_cdf = nullptr, *sts_Z = nullptr;
-  int64_t *sts_last = nullptr;
   StsWork sw{};
   double *Gfull = nullptr, *Gp = nullptr, *ggt = nullptr, *trace = nullptr;
   double *pv_scratch = nullptr, *Gp1 = nullptr, *Gfull1 = nullptr;
@@ -264,14 +262,6 @@ void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
   {
     PhaseScope ps(c, PH_SAMPLE);
     if (sts) {
-      // first factor: CDF of the row masses U[i] G_{>k} U[i]^T (h = 1)
-      arls_build<T>(static_cast<const T *>(ml.U[0]), ml.I[0], c->R, c->ggt,
-                    c->sts_lev, c->sts_cdf, c->sts_Z, c->sts_last, c->tmp,
-                    c->d_err, c->s);
-      ml.lev[0] = c->sts_lev;
-      ml.cdf[0] = c->sts_cdf;
-      ml.Z[0] = c->sts_Z;
-      ml.last[0] = c->sts_last;
       sts_draw<T>(ml, J, c->R, c->F, uni, c->Gp, c->trace, c->sidx, c->prob,
                   static_cast<T *>(c->h), c->sw, c->d_err, c->s);
     } else {
@@ -434,10 +424,8 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   if (c->sampler == CP_SAMPLER_STS) {
     int64_t mI = 0;
     for (int k = 0; k < N; ++k) mI = std::max(mI, c->dims[k]);
-    dalloc(c, &c->sts_lev, mI * 8);
-    dalloc(c, &c->sts_cdf, mI * 8);
-    dalloc(c, &c->sts_Z, 8);
-    dalloc(c, &c->sts_last, 8);
+    dalloc(c, &c->sw.lev, sts_first_rows(mI) * 8);
+    dalloc(c, &c->sw.sub, sts_first_sums(mI) * 8);
     int64_t mP2 = 1;
     for (int k = 0; k < N; ++k) mP2 = std::max(mP2, c->P2[k]);
     const int64_t Js = std::max<int64_t>(c->max_J, 1);

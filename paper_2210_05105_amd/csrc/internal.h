@@ -127,7 +127,9 @@ void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
 
 // ---- STS-CP (k_sts.hip)
 int sts_pad(int R);     // rank padded to the draw width (row stride of StsWork::h)
-int64_t sts_counters(int64_t P2);  // entries of StsWork::lc and ::rc
+int64_t sts_counters(int64_t P2);
+int64_t sts_first_rows(int64_t I);
+int64_t sts_first_sums(int64_t I);  // entries of StsWork::lc and ::rc
 int sts_packed(int R);  // doubles per tree node: packed upper triangle of sts_pad(R)
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
@@ -141,6 +143,8 @@ struct SlotBuf {
 };
 struct StsWork {
   double *h;             // J x sts_pad(R): product of the rows drawn so far
+  double *lev;           // sts_first_rows(I): first-factor row masses
+  double *sub;           // sts_first_sums(I): their 64-row and group sums
   SlotBuf slot[2];       // J records, double-buffered across levels
   int32_t *lc, *rc;      // sts_counters(P2): samples sent left / right
   int32_t *sbeg, *send;  // 2 P2: slot range of a node

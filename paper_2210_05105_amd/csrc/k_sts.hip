@@ -39,6 +39,23 @@ int sts_packed(int R) {
   return RP * (RP + 1) / 2;
 }
 
+// First factor: row masses in groups of FIRST_SUB rows (one block pass),
+// 2^gshift such groups per top-level group, at most FIRST_GROUPS top-level
+// groups (their prefix sums are built in LDS by every draw block).
+constexpr int FIRST_SUB = 64, FIRST_GROUPS = 4096;
+static int64_t first_nsub(int64_t I) { return (I + FIRST_SUB - 1) / FIRST_SUB; }
+static int first_gshift(int64_t I) {
+  int g = 0;
+  while (((first_nsub(I) + (int64_t(1) << g) - 1) >> g) > FIRST_GROUPS) ++g;
+  return g;
+}
+static int64_t first_ngroups(int64_t I) {
+  const int g = first_gshift(I);
+  return (first_nsub(I) + (int64_t(1) << g) - 1) >> g;
+}
+int64_t sts_first_rows(int64_t I) { return first_nsub(I) * FIRST_SUB; }
+int64_t sts_first_sums(int64_t I) { return first_nsub(I) + first_ngroups(I); }
+
 namespace {
 
 __device__ __forceinline__ int packed_index(int a, int b, int R) {
@@ -291,25 +308,117 @@ __device__ __forceinline__ double lane_mass(const double (&ms)[4]) {
   return vv == 0 ? x0 : vv == 1 ? x1 : vv == 2 ? x2 : x3;
 }
 
-// First factor (h = 1): every sample shares one conditional law, held as a
-// flat CDF of the row masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)}.
-// The search runs first over the last CDF entry of each group of cs rows
-// (staged in LDS), then inside the group.
-constexpr int FIRST_COARSE = 2048;
+// First factor (h = 1): every sample shares one conditional law, the row
+// masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)} with F their
+// inclusive prefix sums.  No flat CDF is built: k_sts_mass writes the masses
+// (zero beyond I) with their sums per FIRST_SUB rows and per top-level
+// group, k_sts_first scans the group sums in LDS and, per sample, walks the
+// FIRST_SUB-row sums of its group and then the row masses.
 
+// Masses of FIRST_SUB rows per pass (16 per wave, one MFMA tile with the
+// symmetric G_{>k}); block b takes the 2^gshift passes of top-level group b.
+// Sums are formed in a fixed order.
+template <typename T, int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
+k_sts_mass(const T *U, int64_t I, int R, const double *Gg, int gshift,
+           double *lev, double *sub, double *grp, uint32_t *err) {
+  constexpr int RP = 16 * NT, KS = 4 * NT, RS = tile_stride<NT>();
+  static_assert(FIRST_SUB == 16 * (ST / WAVE), "one row tile per wave");
+  __shared__ double sG[RP * RP];
+  __shared__ double sH[ST / WAVE][16 * RS];
+  __shared__ double wsum[ST / WAVE];
+  stage_pad<RP>(sG, Gg, R);
+  __syncthreads();
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  double *buf = sH[wv];
+  const int lc = l < R ? l : R - 1;
+  const int64_t nsub = (I + FIRST_SUB - 1) / FIRST_SUB;
+  const int64_t sb0 = (int64_t)blockIdx.x << gshift;
+  const int64_t sb1 = sb0 + (int64_t(1) << gshift) < nsub
+                          ? sb0 + (int64_t(1) << gshift) : nsub;
+  double gs = 0.0;
+  for (int64_t sb = sb0; sb < sb1; ++sb) {
+    const int64_t row0 = sb * FIRST_SUB + 16 * wv;
+    T raw[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int64_t row = row0 + i;
+      raw[i] = U[(row < I ? row : I - 1) * R + lc];
+    }
+    wave_lds_sync();
+    if (l < RP) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        buf[i * RS + l] = (row0 + i < I && l < R) ? (double)raw[i] : 0.0;
+    }
+    wave_lds_sync();
+    asm volatile("" ::: "memory");
+    double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
+    lds_bfrag<NT>(sG, gB);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+        xD[tt][v] = buf[(l / 16 + 4 * v) * RS + 16 * tt + (l % 16)];
+    tile_mass<NT>(xA, xD, gB, ms);
+    double m = lane_mass(ms);  // lanes 0..15: row row0 + l
+    const int64_t r = row0 + l;
+    if (l < 16 && r < I && !isfinite(m)) atomicOr(err, ERR_NONFINITE);
+    m = (l < 16 && r < I && m > 0) ? m : 0.0;
+    if (l < 16) lev[r] = m;  // rows past I (up to the allocation) get 0
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) m += __shfl_xor(m, o, WAVE);
+    if (l == 0) wsum[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < ST / WAVE; ++q) x += wsum[q];
+      sub[sb] = x;
+      gs += x;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grp[blockIdx.x] = gs;
+}
+
+// One sample per thread.  Every block builds the inclusive prefix sums of
+// the group masses in LDS (contiguous runs per thread, then a block scan of
+// the run totals).  A target past every prefix (rounding) falls back to the
+// last row of positive mass, as do the walks inside a group.
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST)
-k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
-            const int64_t *lastp, const double *uni, int nq, int64_t J,
-            int cs, int32_t *sidx, double *hbuf, uint32_t *err) {
+k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
+            const double *grp, int gshift, const double *uni, int nq,
+            int64_t J, int32_t *sidx, double *hbuf, uint32_t *err) {
   constexpr int RP = 16 * NT;
-  __shared__ double coarse[FIRST_COARSE];
-  const int64_t nc = (I + cs - 1) / cs;
-  for (int64_t k = threadIdx.x; k < nc; k += ST) {
-    const int64_t e = (k + 1) * cs;
-    coarse[k] = cdf[(e < I ? e : I) - 1];
+  __shared__ double gc[FIRST_GROUPS];
+  __shared__ double wtot[ST / WAVE];
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  const int64_t nsub = (I + FIRST_SUB - 1) / FIRST_SUB;
+  const int ng = (int)((nsub + (int64_t(1) << gshift) - 1) >> gshift);
+  const int per = (ng + ST - 1) / ST;
+  const int k0 = threadIdx.x * per, k1 = k0 + per < ng ? k0 + per : ng;
+  double run = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    run += grp[k];
+    gc[k] = run;
   }
+  double x = run;  // inclusive scan of the run totals within the wave
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const double y = __shfl_up(x, o, WAVE);
+    if (l >= o) x += y;
+  }
+  if (l == WAVE - 1) wtot[wv] = x;
   __syncthreads();
+  double off = x - run;
+  for (int q = 0; q < wv; ++q) off += wtot[q];
+  for (int k = k0; k < k1; ++k) gc[k] += off;
+  __syncthreads();
+  const double Z = gc[ng - 1];
   const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
   if (s >= J) return;
   double u = uni[s * nq];
@@ -317,21 +426,57 @@ k_sts_first(const T *U, int64_t I, int R, const double *cdf, const double *Zp,
     atomicOr(err, ERR_UNIFORM);
     u = 0.0;
   }
-  const double t = u * *Zp;
-  int64_t klo = 0, khi = nc;
-  while (klo < khi) {
-    const int64_t mid = (klo + khi) >> 1;
-    if (t < coarse[mid]) khi = mid; else klo = mid + 1;
+  if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
+  double t = u * Z;
+  int glo = 0, ghi = ng;  // first group with t < prefix
+  while (glo < ghi) {
+    const int mid = (glo + ghi) >> 1;
+    if (t < gc[mid]) ghi = mid; else glo = mid + 1;
   }
-  int64_t lo = klo * cs, hi = lo + cs < I ? lo + cs : I;
-  if (lo > I) lo = I;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (t < cdf[mid]) hi = mid; else lo = mid + 1;
+  bool clamp = glo >= ng;
+  if (clamp) {  // last group of positive mass: first with prefix >= Z
+    int a = 0, b = ng - 1;
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if (gc[mid] >= Z) b = mid; else a = mid + 1;
+    }
+    glo = a;
   }
-  const int64_t last = *lastp;
-  if (lo > last) lo = last;
-  if (lo < 0) lo = 0;
+  t -= glo > 0 ? gc[glo - 1] : 0.0;
+  // FIRST_SUB-row sums of the group
+  const int64_t sb0 = (int64_t)glo << gshift;
+  const int64_t sb1 = sb0 + (int64_t(1) << gshift) < nsub
+                          ? sb0 + (int64_t(1) << gshift) : nsub;
+  int64_t sb = -1, lastsb = sb0;
+  for (int64_t k = sb0; k < sb1; ++k) {
+    const double y = sub[k];
+    if (y > 0) {
+      lastsb = k;
+      if (!clamp && t < y) { sb = k; break; }
+      t -= y;
+    }
+  }
+  if (sb < 0) {
+    sb = lastsb;
+    clamp = true;
+  }
+  // row masses of the FIRST_SUB rows (zero past I), 16 bytes per load
+  const double2 *lv = reinterpret_cast<const double2 *>(lev + sb * FIRST_SUB);
+  double2 mv[FIRST_SUB / 2];
+#pragma unroll
+  for (int i = 0; i < FIRST_SUB / 2; ++i) mv[i] = lv[i];
+  int pick = -1, lastpos = -1;
+#pragma unroll
+  for (int i = 0; i < FIRST_SUB; ++i) {
+    const double m = (i & 1) ? mv[i / 2].y : mv[i / 2].x;
+    if (pick < 0 && m > 0) {
+      lastpos = i;
+      if (!clamp && t < m) pick = i; else t -= m;
+    }
+  }
+  if (pick < 0) pick = lastpos < 0 ? 0 : lastpos;
+  int64_t lo = sb * FIRST_SUB + pick;
+  if (lo >= I) lo = I - 1;
   sidx[s * nq] = (int32_t)lo;
   const T *ur = U + lo * R;
   double2 *h2 = reinterpret_cast<double2 *>(hbuf + s * RP);
@@ -671,11 +816,16 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
              hipStream_t st) {
   const int nq = ml.n;
   const dim3 g(ceil_div(J, ST)), b(ST), gl(ceil_div(J, 16 * (ST / WAVE)));
-  int cs = 64;  // CDF rows per coarse entry
-  while ((ml.I[0] + cs - 1) / cs > FIRST_COARSE) cs *= 2;
+  const int64_t I0 = ml.I[0];
+  const int gs = first_gshift(I0);
+  double *grp = w.sub + first_nsub(I0);
+  hipLaunchKernelGGL((k_sts_mass<T, NT>), dim3((unsigned)first_ngroups(I0)), b,
+                     0, st, static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0],
+                     gs, w.lev, w.sub, grp, err);
+  CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
-                     static_cast<const T *>(ml.U[0]), ml.I[0], R, ml.cdf[0],
-                     ml.Z[0], ml.last[0], uni, nq, J, cs, sidx, w.h, err);
+                     static_cast<const T *>(ml.U[0]), I0, R, w.lev, w.sub, grp,
+                     gs, uni, nq, J, sidx, w.h, err);
   CPR_LAUNCH_CHECK();
   for (int q = 1; q < nq; ++q) {
     const double *tree = ml.tree[q], *Gg = ml.Ggt[q];

@@ -188,6 +188,22 @@ def test_sts_fp32_zipf_mode_solves(dev):
     ctx.close()
 
 
+def test_sts_long_first_factor(dev):
+    """First drawn factor of 300k rows: more 64-row blocks than one level of
+    group sums holds, so draws walk two 64-row blocks per group."""
+    T, _ = tg.tiny_tensor(48, (300_000, 60, 45), 60_000, rank=3,
+                          noise_var=0.01)
+    R, J = 8, 4096
+    ctx = make_ctx(dev, T, R, "sts", "fp64", J)
+    _, runi = init_ctx(ctx, T.dims, R, 11)
+    acc = 0
+    for j in (1, 2):  # mode 0 is drawn first
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-10)
+    assert acc <= 2
+    ctx.close()
+
+
 def test_arls_fp32_4way_mode_solves(dev):
     T = tg.zipf_tensor(43, (2000, 1000, 400, 20), 150_000, s=1.2)
     R, J = 24, 3000
