@@ -171,7 +171,7 @@ struct SampleWork {
   int64_t max_u;     // J (bound on distinct columns)
   int64_t *counts;   // [0] = distinct columns, [1] = extracted nonzeros
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
-  int64_t *scratch;  // 4 J: first-draw flags, lengths and their prefix sums
+  int64_t *scratch;  // 4 J: first-draw flags, lengths, per-block totals
   void *scan_tmp;    // scan_temp_bytes(max(J, buckets + 1))
   int64_t *bk;       // 5 (buckets + 1): per output-row bucket counts/offsets
   void *rec;         // cap records: extracted nonzeros grouped by bucket

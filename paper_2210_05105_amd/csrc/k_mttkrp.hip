@@ -72,86 +72,159 @@ k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *col_key,
   if (cid >= 0 && owner[cid] > (int32_t)s) atomicMin(&owner[cid], (int32_t)s);
 }
 
-// Extra draws per first draw, aggregated per block in an LDS hash table
-// (one global atomic per distinct first draw and block).
+// Merge in two launches.  Block b owns the contiguous draws
+// [b chunk, (b + 1) chunk), taken in passes of LK_THREADS.
+//   k_dup_first: extra draws per first draw, aggregated per pass in an LDS
+//     hash table (one global atomic per distinct first draw and pass); the
+//     first-draw flag and nonzero-range length of every draw, and the
+//     block's totals of both.
+//   k_compact: the block's offsets (sum of the earlier blocks' totals), a
+//     block scan per pass, and the compaction of the first draws in draw
+//     order (weight count / (J p)); restores owner and dupcnt for the next
+//     call (owner is not read after k_dup_first).
 constexpr int DUP_HASH = 2 * LK_THREADS;
-__global__ void __launch_bounds__(LK_THREADS)
-k_dup(int64_t J, const int32_t *col_id, const int32_t *owner,
-      int32_t *dupcnt) {
-  __shared__ int32_t hkey[DUP_HASH], hcnt[DUP_HASH];
-  for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS) {
-    hkey[e] = -1;
-    hcnt[e] = 0;
+constexpr int MG_MAXBLK = 1024;
+
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, WAVE);
+    if (l >= o) x += y;
+  }
+  return x;
+}
+
+// Block-wide exclusive scan of (a, b) per thread; totals through ta, tb.
+__device__ __forceinline__ void block_excl_scan2(int64_t &a, int64_t &b,
+                                                 int64_t &ta, int64_t &tb) {
+  __shared__ int64_t wa[LK_THREADS / WAVE], wb[LK_THREADS / WAVE];
+  const int w = threadIdx.x / WAVE, l = lane_id();
+  const int64_t ia = wave_incl_scan_i64(a), ib = wave_incl_scan_i64(b);
+  if (l == WAVE - 1) {
+    wa[w] = ia;
+    wb[w] = ib;
   }
   __syncthreads();
-  const int64_t s = (int64_t)blockIdx.x * LK_THREADS + threadIdx.x;
-  if (s < J) {
-    const int32_t cid = col_id[s];
-    const int32_t o = cid >= 0 ? owner[cid] : (int32_t)s;
-    if (o != (int32_t)s) {
-      uint32_t hsh = ((uint32_t)o * 2654435761u) % DUP_HASH;
-      for (int probe = 0; probe < DUP_HASH; ++probe) {
-        const int32_t prev = atomicCAS(&hkey[hsh], -1, o);
-        if (prev == -1 || prev == o) {
-          atomicAdd(&hcnt[hsh], 1);
-          break;
+  int64_t oa = 0, ob = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int i = 0; i < LK_THREADS / WAVE; ++i) {
+    if (i < w) {
+      oa += wa[i];
+      ob += wb[i];
+    }
+    ta += wa[i];
+    tb += wb[i];
+  }
+  __syncthreads();
+  a = oa + ia - a;
+  b = ob + ib - b;
+}
+
+__global__ void __launch_bounds__(LK_THREADS)
+k_dup_first(int64_t J, int64_t chunk, const int32_t *col_id,
+            const int32_t *owner, const int64_t *col_ptr, int32_t *dupcnt,
+            int64_t *first, int64_t *len, int64_t *part) {
+  __shared__ int32_t hkey[DUP_HASH], hcnt[DUP_HASH];
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = c0 + chunk < J ? c0 + chunk : J;
+  int64_t nf = 0, nl = 0;
+  for (int64_t p0 = c0; p0 < c1; p0 += LK_THREADS) {
+    for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS) {
+      hkey[e] = -1;
+      hcnt[e] = 0;
+    }
+    __syncthreads();
+    const int64_t s = p0 + threadIdx.x;
+    if (s < c1) {
+      const int32_t cid = col_id[s];
+      const int32_t o = cid >= 0 ? owner[cid] : (int32_t)s;
+      const bool f = cid >= 0 && o == (int32_t)s;
+      const int64_t ln = f ? col_ptr[cid + 1] - col_ptr[cid] : 0;
+      first[s] = f ? 1 : 0;
+      len[s] = ln;
+      nf += f ? 1 : 0;
+      nl += ln;
+      if (o != (int32_t)s) {  // at most LK_THREADS keys: a slot is found
+        uint32_t hsh = ((uint32_t)o * 2654435761u) % DUP_HASH;
+        for (int probe = 0; probe < DUP_HASH; ++probe) {
+          const int32_t prev = atomicCAS(&hkey[hsh], -1, o);
+          if (prev == -1 || prev == o) {
+            atomicAdd(&hcnt[hsh], 1);
+            break;
+          }
+          hsh = (hsh + 1) % DUP_HASH;
         }
-        hsh = (hsh + 1) % DUP_HASH;
       }
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS)
+      if (hkey[e] >= 0) atomicAdd(&dupcnt[hkey[e]], hcnt[e]);
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < DUP_HASH; e += LK_THREADS)
-    if (hkey[e] >= 0) atomicAdd(&dupcnt[hkey[e]], hcnt[e]);
+  int64_t ta, tb;
+  block_excl_scan2(nf, nl, ta, tb);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ta;
+    part[2 * blockIdx.x + 1] = tb;
+  }
 }
 
-// First draw of each column: flag and nonzero-range length (prefix-summed
-// next, to number the distinct columns in draw order and place their
-// nonzero ranges).
-__global__ void k_first(int64_t J, const int32_t *col_id, const int32_t *owner,
-                        const int64_t *col_ptr, int64_t *flag, int64_t *len) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= J) return;
-  const int32_t cid = col_id[s];
-  const bool first = cid >= 0 && owner[cid] == (int32_t)s;
-  flag[s] = first ? 1 : 0;
-  len[s] = first ? col_ptr[cid + 1] - col_ptr[cid] : 0;
-}
-
-// Compaction of the first draws (weights count / (J p)); restores owner and
-// dupcnt for the next call (owner is not read after k_first).
-__global__ void k_compact(int64_t J, const double *prob, const int32_t *col_id,
-                          const int64_t *flag, const int64_t *len,
-                          const int64_t *uidx, const int64_t *off,
-                          const int64_t *col_ptr, int32_t *owner,
-                          int32_t *dupcnt, int32_t *uq_s, int32_t *uq_cid,
-                          int32_t *uq_cnt, double *uq_w, int64_t *uq_off,
-                          int64_t *uq_base, int64_t *counts, int64_t *stats) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= J) return;
-  if (flag[s]) {
-    const int64_t u = uidx[s];
-    const int32_t cid = col_id[s];
-    const int32_t cnt = 1 + dupcnt[s];
-    uq_s[u] = (int32_t)s;
-    uq_cid[u] = cid;
-    uq_cnt[u] = cnt;
-    uq_w[u] = (double)cnt / ((double)J * prob[s]);
-    uq_off[u] = off[s];
-    uq_base[u] = col_ptr[cid] - off[s];  // index position = uq_base + e
-    owner[cid] = INT_MAX;
+__global__ void __launch_bounds__(LK_THREADS)
+k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
+          const int64_t *first, const int64_t *len, const int64_t *part,
+          const int64_t *col_ptr, int32_t *owner, int32_t *dupcnt,
+          int32_t *uq_s, int32_t *uq_cid, int32_t *uq_cnt, double *uq_w,
+          int64_t *uq_off, int64_t *uq_base, int64_t *counts, int64_t *stats) {
+  // offsets of this block: totals of the blocks before it
+  int64_t bu = 0, bo = 0;
+  for (int k = threadIdx.x; k < (int)blockIdx.x; k += LK_THREADS) {
+    bu += part[2 * k];
+    bo += part[2 * k + 1];
   }
-  dupcnt[s] = 0;
-  if (s == J - 1) {
-    const int64_t nu = uidx[s] + flag[s], nz = off[s] + len[s];
-    uq_off[nu] = nz;
-    counts[0] = nu;
-    counts[1] = nz;
-    if (stats) {  // cumulative: mode solves, distinct columns, nonzeros
-      stats[0] += 1;
-      stats[1] += nu;
-      stats[2] += nz;
+  {
+    int64_t ta, tb;
+    block_excl_scan2(bu, bo, ta, tb);
+    bu = ta;
+    bo = tb;
+  }
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = c0 + chunk < J ? c0 + chunk : J;
+  for (int64_t p0 = c0; p0 < c1; p0 += LK_THREADS) {
+    const int64_t s = p0 + threadIdx.x;
+    const bool in = s < c1;
+    const int64_t f = in ? first[s] : 0, ln = in ? len[s] : 0;
+    int64_t u = f, off = ln, ta, tb;
+    block_excl_scan2(u, off, ta, tb);
+    u += bu;
+    off += bo;
+    if (f) {
+      const int32_t cid = col_id[s];
+      const int32_t cnt = 1 + dupcnt[s];
+      uq_s[u] = (int32_t)s;
+      uq_cid[u] = cid;
+      uq_cnt[u] = cnt;
+      uq_w[u] = (double)cnt / ((double)J * prob[s]);
+      uq_off[u] = off;
+      uq_base[u] = col_ptr[cid] - off;  // index position = uq_base + e
+      owner[cid] = INT_MAX;
     }
+    if (in) dupcnt[s] = 0;
+    if (s == J - 1) {
+      const int64_t nu = u + f, nz = off + ln;
+      uq_off[nu] = nz;
+      counts[0] = nu;
+      counts[1] = nz;
+      if (stats) {  // cumulative: mode solves, distinct columns, nonzeros
+        stats[0] += 1;
+        stats[1] += nu;
+        stats[2] += nz;
+      }
+    }
+    bu += ta;
+    bo += tb;
   }
 }
 
@@ -277,18 +350,52 @@ k_bk_count(const int64_t *counts, const int64_t *uq_off,
   }
 }
 
-__global__ void k_bk_items(const int64_t *bk_total, int nbk, int64_t *items) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b > nbk) return;
-  items[b] = b < nbk ? (bk_total[b] + BK_SLICE - 1) / BK_SLICE : 0;
-}
-
-// item_bk[i] = bucket of accumulation item i
-__global__ void k_bk_itemmap(const int64_t *item_start, int nbk,
-                             int32_t *item_bk) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbk) return;
-  for (int64_t i = item_start[b]; i < item_start[b + 1]; ++i) item_bk[i] = b;
+// Accumulation plan in one workgroup: bk_start = exclusive prefix sums of
+// the bucket totals (nbk + 1 entries, the last the total), item_start the
+// same for the slices per bucket, item_bk[i] = bucket of slice i.  Thread t
+// takes a contiguous run of buckets.
+constexpr int PL_THREADS = 1024;
+__global__ void __launch_bounds__(PL_THREADS)
+k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
+          int64_t *item_start, int32_t *item_bk) {
+  __shared__ int64_t wa[PL_THREADS / WAVE], wb[PL_THREADS / WAVE];
+  const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
+  const int per = (nbk + 1 + PL_THREADS - 1) / PL_THREADS;
+  const int b0 = t * per, b1 = b0 + per < nbk + 1 ? b0 + per : nbk + 1;
+  int64_t sa = 0, sb = 0;
+  for (int b = b0; b < b1; ++b) {
+    const int64_t n = b < nbk ? bk_total[b] : 0;
+    sa += n;
+    sb += (n + BK_SLICE - 1) / BK_SLICE;
+  }
+  int64_t ia = sa, ib = sb;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t ya = __shfl_up(ia, o, WAVE), yb = __shfl_up(ib, o, WAVE);
+    if (l >= o) {
+      ia += ya;
+      ib += yb;
+    }
+  }
+  if (l == WAVE - 1) {
+    wa[w] = ia;
+    wb[w] = ib;
+  }
+  __syncthreads();
+  int64_t oa = ia - sa, ob = ib - sb;
+  for (int i = 0; i < w; ++i) {
+    oa += wa[i];
+    ob += wb[i];
+  }
+  for (int b = b0; b < b1; ++b) {
+    const int64_t n = b < nbk ? bk_total[b] : 0;
+    const int64_t ni = (n + BK_SLICE - 1) / BK_SLICE;
+    bk_start[b] = oa;
+    item_start[b] = ob;
+    for (int64_t i = 0; i < ni; ++i) item_bk[ob + i] = b;
+    oa += n;
+    ob += ni;
+  }
 }
 
 // One extracted nonzero in bucket order: key = (draw id << 8) | row % B.
@@ -659,19 +766,16 @@ void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
 
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    SampleWork &w, hipStream_t s) {
-  const dim3 g(ceil_div(J, 256)), b(256);
-  int64_t *flag = w.scratch, *len = w.scratch + J, *uidx = w.scratch + 2 * J,
-          *off = w.scratch + 3 * J;
-  hipLaunchKernelGGL(k_dup, dim3(ceil_div(J, LK_THREADS)), dim3(LK_THREADS), 0,
-                     s, J, w.col_id, w.owner, w.dupcnt);
-  hipLaunchKernelGGL(k_first, g, b, 0, s, J, w.col_id, w.owner, col_ptr, flag,
-                     len);
+  const int nb = (int)std::min<int64_t>(ceil_div(J, LK_THREADS), MG_MAXBLK);
+  const int64_t chunk = ceil_div(ceil_div(J, nb), LK_THREADS) * LK_THREADS;
+  int64_t *first = w.scratch, *len = w.scratch + J, *part = w.scratch + 2 * J;
+  hipLaunchKernelGGL(k_dup_first, dim3(nb), dim3(LK_THREADS), 0, s, J, chunk,
+                     w.col_id, w.owner, col_ptr, w.dupcnt, first, len, part);
   CPR_LAUNCH_CHECK();
-  exclusive_scan_i64(flag, uidx, J, w.scan_tmp, s);
-  exclusive_scan_i64(len, off, J, w.scan_tmp, s);
-  hipLaunchKernelGGL(k_compact, g, b, 0, s, J, prob, w.col_id, flag, len, uidx,
-                     off, col_ptr, w.owner, w.dupcnt, w.uq_s, w.uq_cid,
-                     w.uq_cnt, w.uq_w, w.uq_off, w.uq_base, w.counts, w.stats);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(LK_THREADS), 0, s, J, chunk,
+                     prob, w.col_id, first, len, part, col_ptr, w.owner,
+                     w.dupcnt, w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off,
+                     w.uq_base, w.counts, w.stats);
   CPR_LAUNCH_CHECK();
 }
 
@@ -692,8 +796,7 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   const int bb = bucket_shift(R, (int)sizeof(T));
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
   int64_t *bk_total = w.bk, *bk_fill = w.bk + (nbk + 1),
-          *bk_start = w.bk + 2 * (nbk + 1), *items = w.bk + 3 * (nbk + 1),
-          *item_start = w.bk + 4 * (nbk + 1);
+          *bk_start = w.bk + 2 * (nbk + 1), *item_start = w.bk + 3 * (nbk + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
   zero_fill<int64_t>(bk_total, 2 * (nbk + 1), s);  // totals and fill cursors
   hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
@@ -702,13 +805,9 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   hipLaunchKernelGGL(k_bk_count, gt, b, hl, s, w.counts, w.uq_off,
                      w.tile_first, w.uq_base, row, nbk, bb, bk_total);
   CPR_LAUNCH_CHECK();
-  exclusive_scan_i64(bk_total, bk_start, nbk + 1, w.scan_tmp, s);
-  hipLaunchKernelGGL(k_bk_items, dim3(ceil_div(nbk + 1, 256)), b, 0, s,
-                     bk_total, nbk, items);
+  hipLaunchKernelGGL(k_bk_plan, dim3(1), dim3(PL_THREADS), 0, s, bk_total,
+                     nbk, bk_start, item_start, w.item_bk);
   CPR_LAUNCH_CHECK();
-  exclusive_scan_i64(items, item_start, nbk + 1, w.scan_tmp, s);
-  hipLaunchKernelGGL(k_bk_itemmap, dim3(ceil_div(nbk, 256)), b, 0, s,
-                     item_start, nbk, w.item_bk);
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
   hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 2 * hl, s, w.counts, w.uq_s, w.uq_w,

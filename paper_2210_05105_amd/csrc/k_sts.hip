@@ -420,13 +420,16 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
   __syncthreads();
   const double Z = gc[ng - 1];
   const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
-  if (s >= J) return;
-  double u = uni[s * nq];
+  const int64_t sw0 = s - l;  // first sample of the wave
+  if (sw0 >= J) return;
+  // lanes past J draw for sample J - 1 and store nothing
+  const bool act = s < J;
+  double u = uni[(act ? s : J - 1) * nq];
   if (!(u >= 0.0 && u < 1.0)) {
-    atomicOr(err, ERR_UNIFORM);
+    if (act) atomicOr(err, ERR_UNIFORM);
     u = 0.0;
   }
-  if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
+  if (!(Z > 0) && act) atomicOr(err, ERR_ZERO_MASS);
   double t = u * Z;
   int glo = 0, ghi = ng;  // first group with t < prefix
   while (glo < ghi) {
@@ -443,12 +446,12 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
     glo = a;
   }
   t -= glo > 0 ? gc[glo - 1] : 0.0;
-  // FIRST_SUB-row sums of the group
+  // FIRST_SUB-row sums of the group (a group of one block is that block)
   const int64_t sb0 = (int64_t)glo << gshift;
   const int64_t sb1 = sb0 + (int64_t(1) << gshift) < nsub
                           ? sb0 + (int64_t(1) << gshift) : nsub;
-  int64_t sb = -1, lastsb = sb0;
-  for (int64_t k = sb0; k < sb1; ++k) {
+  int64_t sb = gshift == 0 ? sb0 : -1, lastsb = sb0;
+  for (int64_t k = sb0; k < sb1 && gshift > 0; ++k) {
     const double y = sub[k];
     if (y > 0) {
       lastsb = k;
@@ -477,14 +480,17 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
   if (pick < 0) pick = lastpos < 0 ? 0 : lastpos;
   int64_t lo = sb * FIRST_SUB + pick;
   if (lo >= I) lo = I - 1;
-  sidx[s * nq] = (int32_t)lo;
-  const T *ur = U + lo * R;
-  double2 *h2 = reinterpret_cast<double2 *>(hbuf + s * RP);
-#pragma unroll
-  for (int a = 0; a < RP; a += 2) {
-    const int a0 = a < R ? a : R - 1, a1 = a + 1 < R ? a + 1 : R - 1;
-    const double x0 = (double)ur[a0], x1 = (double)ur[a1];
-    h2[a / 2] = double2{a < R ? x0 : 0.0, a + 1 < R ? x1 : 0.0};
+  if (act) sidx[s * nq] = (int32_t)lo;
+  // h = U[lo] for the wave's samples, the rows read and written coalesced
+  const int nw = J - sw0 < WAVE ? (int)(J - sw0) : WAVE;
+#pragma unroll 8
+  for (int it = 0; it < RP; ++it) {  // WAVE samples x RP entries, WAVE per pass
+    const int e = it * WAVE + l, k = e / RP, a = e % RP;
+    const int64_t ik = __shfl(lo, k, WAVE);
+    if (k < nw) {
+      const double x = (double)U[ik * R + (a < R ? a : R - 1)];
+      hbuf[(sw0 + k) * RP + a] = a < R ? x : 0.0;
+    }
   }
 }
 
