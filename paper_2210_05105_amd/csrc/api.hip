@@ -272,7 +272,8 @@ void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
   {
     PhaseScope ps(c, PH_DEDUP);
     lookup_columns(ml, J, c->sidx, c->ix[mode], c->w, c->s);
-    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
+    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->h, c->R, (int)sizeof(T),
+                  c->w, c->s);
   }
   c->sampled_mode = mode;
   c->mttkrp_mode = -1;
@@ -293,7 +294,8 @@ void do_set_samples(cp_ctx *c, int mode, int64_t J, const int32_t *idx,
   {
     PhaseScope ps(c, PH_DEDUP);
     lookup_columns(ml, J, c->sidx, c->ix[mode], c->w, c->s);
-    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->w, c->s);
+    merge_samples(J, c->prob, c->ix[mode].col_ptr, c->h, c->R, (int)sizeof(T),
+                  c->w, c->s);
   }
   c->sampled_mode = mode;
   c->mttkrp_mode = -1;
@@ -305,15 +307,14 @@ void do_mttkrp(cp_ctx *c, int mode) {
   const ModeIndex &ix = c->ix[mode];
   T *M = static_cast<T *>(c->M);
   PhaseScope ps(c, PH_MTTKRP);
-  zero_fill<T>(M, c->dims[mode] * c->R, c->s);
   if (c->sampler == CP_SAMPLER_EXACT) {
+    zero_fill<T>(M, c->dims[mode] * c->R, c->s);
     const ModeList ml = make_ml(c, mode);
     exact_mttkrp<T>(ml, ix.n_cols, ix.col_key, ix.col_ptr, ix.row,
                     static_cast<const T *>(ix.val), c->R, M, c->s);
   } else {
     sampled_mttkrp<T>(c->w, c->dims[mode], ix.col_ptr, ix.row,
-                      static_cast<const T *>(ix.val),
-                      static_cast<const T *>(c->h), c->R, M, c->s);
+                      static_cast<const T *>(ix.val), c->R, M, c->s);
   }
   c->mttkrp_mode = mode;
 }
@@ -456,6 +457,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.col_id, J * 4);
   dalloc(c, &c->w.owner, c->max_cols * 4);
   dalloc(c, &c->w.dupcnt, J * 4);
+  dalloc(c, &c->w.hc, (size_t)J * R * ts);
   dalloc(c, &c->w.uq_s, J * 4);
   dalloc(c, &c->w.uq_cid, J * 4);
   dalloc(c, &c->w.uq_cnt, J * 4);

@@ -166,6 +166,7 @@ struct SampleWork {
   double *uq_w;      // J: weight count/(J p)
   int64_t *uq_off;   // J+1: extracted-nonzero offsets
   int64_t *uq_base;  // J: index position of extracted nonzero e = uq_base + e
+  void *hc;          // J x R (factor type): w_u h[first draw of u], by u
   int64_t *tile_first;  // bucket_tiles(rec_cap): column at each tile start
   int32_t *item_bk;  // bucket_max_items(rec_cap, buckets): bucket of an item
   int64_t max_u;     // J (bound on distinct columns)
@@ -188,11 +189,12 @@ void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
                     const ModeIndex &ix, SampleWork &w, hipStream_t s);
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
-                   SampleWork &w, hipStream_t s);
+                   const void *h, int R, int tsize, SampleWork &w,
+                   hipStream_t s);
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
-                    const int32_t *row, const T *val, const T *h, int R,
-                    T *M, hipStream_t s);
+                    const int32_t *row, const T *val, int R, T *M,
+                    hipStream_t s);
 template <typename T>
 void exact_mttkrp(const ModeList &ml, int64_t n_cols, const uint64_t *col_key,
                   const int64_t *col_ptr, const int32_t *row, const T *val,

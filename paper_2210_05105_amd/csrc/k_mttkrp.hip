@@ -4,15 +4,16 @@
 //    mode's sorted distinct column keys; the first draw of each column
 //    claims it with atomicMin.
 // 2. merge: draws of the same column are merged (count c, weight
-//    c / (J p)); distinct columns are compacted in first-draw order and the
-//    lengths of their nonzero ranges are prefix-summed.
+//    w = c / (J p)); distinct columns u are compacted in first-draw order,
+//    the lengths of their nonzero ranges are prefix-summed, and
+//    hc[u] = w h[first draw] holds the column's weighted Khatri-Rao row.
 // 3. MTTKRP by blocks of B output rows (the paper's transposition of the
 //    extracted nonzeros to row order, Section 4.3, as one counting-sort
 //    pass): count the extracted nonzeros per row block, scatter compact
-//    records (draw id, row % B, w v) grouped by block, then accumulate each
-//    block's records into an LDS copy of its B rows of M.  Positions of
-//    one column are row-sorted, so a wave's consecutive positions form a
-//    few runs of one block and count/scatter take one atomic per run.
+//    records (u, row % B, v) grouped by block, then accumulate each block's
+//    records into its B rows of M.  Positions of one column are row-sorted,
+//    so a wave's consecutive positions form a few runs of one block and
+//    count/scatter take one atomic per run.
 #include "internal.h"
 
 #include <algorithm>
@@ -172,12 +173,14 @@ k_dup_first(int64_t J, int64_t chunk, const int32_t *col_id,
   }
 }
 
+template <typename T>
 __global__ void __launch_bounds__(LK_THREADS)
 k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
           const int64_t *first, const int64_t *len, const int64_t *part,
-          const int64_t *col_ptr, int32_t *owner, int32_t *dupcnt,
-          int32_t *uq_s, int32_t *uq_cid, int32_t *uq_cnt, double *uq_w,
-          int64_t *uq_off, int64_t *uq_base, int64_t *counts, int64_t *stats) {
+          const int64_t *col_ptr, const T *h, int R, int32_t *owner,
+          int32_t *dupcnt, int32_t *uq_s, int32_t *uq_cid, int32_t *uq_cnt,
+          double *uq_w, int64_t *uq_off, int64_t *uq_base, T *hc,
+          int64_t *counts, int64_t *stats) {
   // offsets of this block: totals of the blocks before it
   int64_t bu = 0, bo = 0;
   for (int k = threadIdx.x; k < (int)blockIdx.x; k += LK_THREADS) {
@@ -203,13 +206,24 @@ k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
     if (f) {
       const int32_t cid = col_id[s];
       const int32_t cnt = 1 + dupcnt[s];
+      const double wu = (double)cnt / ((double)J * prob[s]);
       uq_s[u] = (int32_t)s;
       uq_cid[u] = cid;
       uq_cnt[u] = cnt;
-      uq_w[u] = (double)cnt / ((double)J * prob[s]);
+      uq_w[u] = wu;
       uq_off[u] = off;
       uq_base[u] = col_ptr[cid] - off;  // index position = uq_base + e
       owner[cid] = INT_MAX;
+      const T *hs = h + s * R;
+      T *hu = hc + u * R;
+      for (int c0 = 0; c0 < R; c0 += 16) {  // 16 loads in flight
+        T x[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = hs[c0 + j < R ? c0 + j : R - 1];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (c0 + j < R) hu[c0 + j] = (T)(wu * (double)x[j]);
+      }
     }
     if (in) dupcnt[s] = 0;
     if (s == J - 1) {
@@ -232,11 +246,12 @@ k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
 // extracted nonzeros to row order, Section 4.3, done as one counting-sort
 // pass by blocks of B output rows):
 //   count   : bucket (= row / B) histogram of the extracted nonzeros;
-//   scatter : compact records (row % B, draw id, w v) grouped by bucket;
+//   scatter : compact records (u, row % B, v) grouped by bucket;
 //   accum   : one workgroup per (bucket, slice of <= BK_SLICE records)
-//             adds w v h into an LDS copy of the bucket's B rows of M with
-//             LDS atomics, then writes the rows once (plain stores when
-//             the bucket is one slice, float atomics when it is split).
+//             adds v hc[u] into the bucket's B rows (sorted by row in LDS,
+//             runs summed in registers), then writes the rows once: to M
+//             when the bucket is one slice, else to a per-slice block that
+//             k_bk_combine adds in slice order.
 // Extracted nonzeros are never materialised: position e of the
 // concatenated sampled-column ranges is resolved to (distinct column,
 // position in the mode's index) by a binary search over uq_off.
@@ -352,8 +367,10 @@ k_bk_count(const int64_t *counts, const int64_t *uq_off,
 
 // Accumulation plan in one workgroup: bk_start = exclusive prefix sums of
 // the bucket totals (nbk + 1 entries, the last the total), item_start the
-// same for the slices per bucket, item_bk[i] = bucket of slice i.  Thread t
-// takes a contiguous run of buckets.
+// same for the slices per bucket, item_bk[i] = bucket of slice i.  Every
+// bucket gets at least one slice (an empty one writes zero rows), so the
+// accumulation writes every row of M.  Thread t takes a contiguous run of
+// buckets.
 constexpr int PL_THREADS = 1024;
 __global__ void __launch_bounds__(PL_THREADS)
 k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
@@ -363,10 +380,13 @@ k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
   const int per = (nbk + 1 + PL_THREADS - 1) / PL_THREADS;
   const int b0 = t * per, b1 = b0 + per < nbk + 1 ? b0 + per : nbk + 1;
   int64_t sa = 0, sb = 0;
+  auto slices = [&](int b, int64_t n) -> int64_t {
+    return b < nbk ? (n > BK_SLICE ? (n + BK_SLICE - 1) / BK_SLICE : 1) : 0;
+  };
   for (int b = b0; b < b1; ++b) {
     const int64_t n = b < nbk ? bk_total[b] : 0;
     sa += n;
-    sb += (n + BK_SLICE - 1) / BK_SLICE;
+    sb += slices(b, n);
   }
   int64_t ia = sa, ib = sb;
 #pragma unroll
@@ -389,7 +409,7 @@ k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
   }
   for (int b = b0; b < b1; ++b) {
     const int64_t n = b < nbk ? bk_total[b] : 0;
-    const int64_t ni = (n + BK_SLICE - 1) / BK_SLICE;
+    const int64_t ni = slices(b, n);
     bk_start[b] = oa;
     item_start[b] = ob;
     for (int64_t i = 0; i < ni; ++i) item_bk[ob + i] = b;
@@ -398,7 +418,8 @@ k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
   }
 }
 
-// One extracted nonzero in bucket order: key = (draw id << 8) | row % B.
+// One extracted nonzero in bucket order: key = (distinct column u << 8) |
+// row % B, coef = its value (the column's weight is folded into hc[u]).
 template <typename T>
 struct BkRec {
   uint32_t key;
@@ -407,8 +428,8 @@ struct BkRec {
 
 template <typename T>
 __global__ void __launch_bounds__(MT_THREADS)
-k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
-             const int64_t *uq_off, const int64_t *tile_first,
+k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
+             const int64_t *tile_first,
              const int64_t *uq_base, const int32_t *row, const T *val, int nbk,
              int bb, const int64_t *bk_start, int64_t *bk_fill,
              BkRec<T> *rec) {
@@ -429,31 +450,33 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
     int ncol;
     tile_columns(counts, uq_off, tile_first, tile, ntile, e0, cst, ub, ncol);
     __syncthreads();
-    int64_t u[BK_ITEMS], p[BK_ITEMS];
-#pragma unroll
-    for (int i = 0; i < BK_ITEMS; ++i) {
-      const int pos = i * MT_THREADS + threadIdx.x;
-      const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
-      u[i] = ub + find_local(cst, ncol, (int)(e - e0));
-      p[i] = uq_base[u[i]] + e;
-    }
-    int my_bk[BK_ITEMS], my_lead[BK_ITEMS], my_len[BK_ITEMS];
+    int64_t p[BK_ITEMS];
+    int my_bk[BK_ITEMS];
     uint32_t my_key[BK_ITEMS];
     T my_cf[BK_ITEMS];
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
+      const int pos = i * MT_THREADS + threadIdx.x;
+      const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
+      const int64_t u = ub + find_local(cst, ncol, (int)(e - e0));
+      my_key[i] = (uint32_t)u << 8;
+      p[i] = uq_base[u] + e;
+    }
+#pragma unroll
+    for (int i = 0; i < BK_ITEMS; ++i) {
       const int rw = row[p[i]];
-      my_key[i] = ((uint32_t)uq_s[u[i]] << 8) | ((uint32_t)rw & bmask);
-      my_cf[i] = (T)(uq_w[u[i]] * (double)val[p[i]]);
+      my_key[i] |= (uint32_t)rw & bmask;
+      my_cf[i] = val[p[i]];
       my_bk[i] = rw >> bb;
     }
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
       const bool valid = e0 + i * MT_THREADS + threadIdx.x < e1;
       if (!valid) my_bk[i] = -1;
-      bucket_runs(my_bk[i], valid, my_lead[i], my_len[i]);
-      if (use_lds && valid && my_lead[i] == l)
-        atomicAdd(&cnt[my_bk[i]], (uint32_t)my_len[i]);
+      int lead, len;
+      bucket_runs(my_bk[i], valid, lead, len);
+      if (use_lds && valid && lead == l)
+        atomicAdd(&cnt[my_bk[i]], (uint32_t)len);
     }
     __syncthreads();
     if (use_lds)
@@ -470,14 +493,16 @@ k_bk_scatter(const int64_t *counts, const int32_t *uq_s, const double *uq_w,
     for (int i = 0; i < BK_ITEMS; ++i) {
       const int bk = my_bk[i];
       // the run's first lane reserves the run's slots; members follow it
+      int lead, len;
+      bucket_runs(bk, bk >= 0, lead, len);
       int64_t off = 0;
-      if (bk >= 0 && my_lead[i] == l)
-        off = use_lds ? (int64_t)base[bk] + (int64_t)atomicAdd(&cnt[bk], (uint32_t)my_len[i])
+      if (bk >= 0 && lead == l)
+        off = use_lds ? (int64_t)base[bk] + (int64_t)atomicAdd(&cnt[bk], (uint32_t)len)
                       : bk_start[bk] + (int64_t)atomicAdd(
                             (unsigned long long *)&bk_fill[bk],
-                            (unsigned long long)my_len[i]);
-      off = __shfl(off, my_lead[i], WAVE);
-      if (bk >= 0) rec[off + (l - my_lead[i])] = BkRec<T>{my_key[i], my_cf[i]};
+                            (unsigned long long)len);
+      off = __shfl(off, lead, WAVE);
+      if (bk >= 0) rec[off + (l - lead)] = BkRec<T>{my_key[i], my_cf[i]};
     }
     __syncthreads();
   }
@@ -515,7 +540,7 @@ template <typename T, int L, int VW, bool VEC>
 __global__ void __launch_bounds__(MT_THREADS)
 k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
            const int64_t *bk_start, int nbk, int bb, const BkRec<T> *rec,
-           const T *h, int R, int64_t I, T *M, T *part) {
+           const T *hc, int R, int64_t I, T *M, T *part) {
   constexpr int G = MT_THREADS / L;  // lane groups per block
   extern __shared__ unsigned char bk_lds_raw[];
   T *blk = reinterpret_cast<T *>(bk_lds_raw);                // B x R
@@ -537,10 +562,12 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
     const bool single = item_start[bk + 1] - item_start[bk] == 1;
     // this thread's records: positions t, t + 256, ...
     BkRec<T> my[AC_ITEMS];
+    if (n > 0) {
 #pragma unroll
-    for (int i = 0; i < AC_ITEMS; ++i) {
-      const int e = i * MT_THREADS + t;
-      my[i] = rec[r0 + (e < n ? e : n - 1)];
+      for (int i = 0; i < AC_ITEMS; ++i) {
+        const int e = i * MT_THREADS + t;
+        my[i] = rec[r0 + (e < n ? e : n - 1)];
+      }
     }
     for (int e = t; e < B * R; e += MT_THREADS) blk[e] = T(0);
     for (int e = t; e <= 256; e += MT_THREADS) cnt[e] = 0;
@@ -577,30 +604,41 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
     const int c0 = g * per < n ? g * per : n;
     const int c1 = c0 + per < n ? c0 + per : n;
     const int cb = gl * VW;
-    T acc[VW];
-#pragma unroll
-    for (int q = 0; q < VW; ++q) acc[q] = T(0);
-    int cur = c0 < c1 ? (int)(lk[c0] & 255u) : -1;
     // rows also held by the neighbouring chunks take LDS float atomics
     // (slow); every other row belongs to this group alone and is stored
     const int row_a = (c0 < c1 && c0 > 0 && ((lk[c0 - 1] ^ lk[c0]) & 255u) == 0)
                           ? (int)(lk[c0] & 255u) : -1;
     const int row_b = (c0 < c1 && c1 < n && ((lk[c1] ^ lk[c1 - 1]) & 255u) == 0)
                           ? (int)(lk[c1 - 1] & 255u) : -1;
+    T acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = T(0);
     auto flush = [&](int row) {
       T *br = blk + row * R + cb;
-      const bool shared = row == row_a || row == row_b;
+      if (row == row_a || row == row_b) {
 #pragma unroll
-      for (int q = 0; q < VW; ++q) {
-        if (cb + q < R) {
-          if (shared) atomicAdd(br + q, acc[q]);
-          else br[q] = acc[q];
+        for (int q = 0; q < VW; ++q)
+          if (VEC ? cb < R : cb + q < R) atomicAdd(br + q, acc[q]);
+      } else if (VEC) {
+        if (cb < R) {
+          typedef T vec_t __attribute__((ext_vector_type(VW)));
+          vec_t v;
+#pragma unroll
+          for (int q = 0; q < VW; ++q) v[q] = acc[q];
+          *reinterpret_cast<vec_t *>(br) = v;
         }
-        acc[q] = T(0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < VW; ++q)
+          if (cb + q < R) br[q] = acc[q];
       }
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] = T(0);
     };
-    // two batches of AC_BATCH records: the next is loaded while the
-    // current one is accumulated
+    // batches of AC_BATCH records (indices clamped to the chunk, so every
+    // load is issued unconditionally); the next batch is in flight while
+    // the current one is accumulated.  A run of one row ends where the next
+    // record's row differs or the chunk ends.
     struct Batch {
       T hv[AC_BATCH][VW];
       T cf[AC_BATCH];
@@ -611,34 +649,31 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
       for (int u = 0; u < AC_BATCH; ++u) {
         const int kc = kk + u < c1 ? kk + u : c1 - 1;
         const uint32_t key = lk[kc];
-        bt.rw[u] = kk + u < c1 ? (int)(key & 255u) : -1;
-        bt.cf[u] = lc[kc];
-        load_cols<T, VW, VEC>(h + (int64_t)(key >> 8) * R, cb, R, bt.hv[u]);
+        bt.rw[u] = (int)(key & 255u);
+        bt.cf[u] = kk + u < c1 ? lc[kc] : T(0);
+        load_cols<T, VW, VEC>(hc + (int64_t)(key >> 8) * R, cb, R, bt.hv[u]);
       }
     };
-    auto run_batch = [&](const Batch &bt) {
+    auto run_batch = [&](int kk, const Batch &bt, int next_row) {
 #pragma unroll
       for (int u = 0; u < AC_BATCH; ++u) {
-        if (bt.rw[u] < 0) break;
-        if (bt.rw[u] != cur) {
-          flush(cur);
-          cur = bt.rw[u];
-        }
 #pragma unroll
-        for (int q = 0; q < VW; ++q) acc[q] += bt.cf[u] * bt.hv[u][q];
+        for (int q = 0; q < VW; ++q) acc[q] = fma(bt.cf[u], bt.hv[u][q], acc[q]);
+        const int nr = u + 1 < AC_BATCH ? bt.rw[u + 1] : next_row;
+        const bool last = kk + u + 1 >= c1;
+        if (kk + u < c1 && (last || nr != bt.rw[u])) flush(bt.rw[u]);
       }
     };
     if (c0 < c1) {
       Batch b0, b1;
       load_batch(c0, b0);
       for (int kk = c0; kk < c1; kk += 2 * AC_BATCH) {
-        if (kk + AC_BATCH < c1) load_batch(kk + AC_BATCH, b1);
-        run_batch(b0);
-        if (kk + 2 * AC_BATCH < c1) load_batch(kk + 2 * AC_BATCH, b0);
-        if (kk + AC_BATCH < c1) run_batch(b1);
+        load_batch(kk + AC_BATCH, b1);
+        run_batch(kk, b0, b1.rw[0]);
+        load_batch(kk + 2 * AC_BATCH, b0);
+        run_batch(kk + AC_BATCH, b1, b0.rw[0]);
       }
     }
-    if (cur >= 0) flush(cur);
     __syncthreads();
     // a bucket held by one slice goes straight to M; the slices of a split
     // bucket store their block in their own scratch slot for k_bk_combine
@@ -765,17 +800,26 @@ void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
 }
 
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
-                   SampleWork &w, hipStream_t s) {
+                   const void *h, int R, int tsize, SampleWork &w,
+                   hipStream_t s) {
   const int nb = (int)std::min<int64_t>(ceil_div(J, LK_THREADS), MG_MAXBLK);
   const int64_t chunk = ceil_div(ceil_div(J, nb), LK_THREADS) * LK_THREADS;
   int64_t *first = w.scratch, *len = w.scratch + J, *part = w.scratch + 2 * J;
   hipLaunchKernelGGL(k_dup_first, dim3(nb), dim3(LK_THREADS), 0, s, J, chunk,
                      w.col_id, w.owner, col_ptr, w.dupcnt, first, len, part);
   CPR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(LK_THREADS), 0, s, J, chunk,
-                     prob, w.col_id, first, len, part, col_ptr, w.owner,
-                     w.dupcnt, w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off,
-                     w.uq_base, w.counts, w.stats);
+  if (tsize == 4)
+    hipLaunchKernelGGL((k_compact<float>), dim3(nb), dim3(LK_THREADS), 0, s, J,
+                       chunk, prob, w.col_id, first, len, part, col_ptr,
+                       static_cast<const float *>(h), R, w.owner, w.dupcnt,
+                       w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off, w.uq_base,
+                       static_cast<float *>(w.hc), w.counts, w.stats);
+  else
+    hipLaunchKernelGGL((k_compact<double>), dim3(nb), dim3(LK_THREADS), 0, s, J,
+                       chunk, prob, w.col_id, first, len, part, col_ptr,
+                       static_cast<const double *>(h), R, w.owner, w.dupcnt,
+                       w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off, w.uq_base,
+                       static_cast<double *>(w.hc), w.counts, w.stats);
   CPR_LAUNCH_CHECK();
 }
 
@@ -791,8 +835,9 @@ size_t lds_cap() { return 160 * 1024 - 8 * 1024; }
 
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
-                    const int32_t *row, const T *val, const T *h, int R, T *M,
+                    const int32_t *row, const T *val, int R, T *M,
                     hipStream_t s) {
+  const T *hc = static_cast<const T *>(w.hc);
   const int bb = bucket_shift(R, (int)sizeof(T));
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
   int64_t *bk_total = w.bk, *bk_fill = w.bk + (nbk + 1),
@@ -810,9 +855,9 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   CPR_LAUNCH_CHECK();
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
-  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 2 * hl, s, w.counts, w.uq_s, w.uq_w,
-                     w.uq_off, w.tile_first, w.uq_base, row, val, nbk, bb,
-                     bk_start, bk_fill, rec);
+  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 2 * hl, s, w.counts, w.uq_off,
+                     w.tile_first, w.uq_base, row, val, nbk, bb, bk_start,
+                     bk_fill, rec);
   CPR_LAUNCH_CHECK();
   const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
                      (size_t)BK_SLICE * (sizeof(T) + 4);
@@ -827,7 +872,7 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
       attr_set[sizeof(T) == 8][li] = true;
     }
     hipLaunchKernelGGL(kern, gt, b, lds, s, item_start, w.item_bk, bk_start,
-                       nbk, bb, rec, h, R, I, M, part);
+                       nbk, bb, rec, hc, R, I, M, part);
   };
   const int lanes = (R + VW - 1) / VW;  // lanes per record
   if (R % VW == 0) {
@@ -863,12 +908,11 @@ size_t bucket_record_bytes(int tsize) {
 }
 template void sampled_mttkrp<float>(const SampleWork &, int64_t,
                                     const int64_t *, const int32_t *,
-                                    const float *, const float *, int, float *,
-                                    hipStream_t);
+                                    const float *, int, float *, hipStream_t);
 template void sampled_mttkrp<double>(const SampleWork &, int64_t,
                                      const int64_t *, const int32_t *,
-                                     const double *, const double *, int,
-                                     double *, hipStream_t);
+                                     const double *, int, double *,
+                                     hipStream_t);
 
 template <typename T>
 void exact_mttkrp(const ModeList &ml, int64_t n_cols, const uint64_t *col_key,
