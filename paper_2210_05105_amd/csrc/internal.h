@@ -57,8 +57,8 @@ struct ModeIndex {
   int64_t I = 0, n_cols = 0, max_col = 0;
   uint64_t *col_key = nullptr;  // n_cols sorted distinct column keys
   int64_t *col_ptr = nullptr;   // n_cols + 1 offsets
-  // first column whose key is >= v * top_stride, v = 0 .. n_top - 1 (v is
-  // the index of the slowest mode != j; top[n_top - 1] = n_cols)
+  // first column whose key is >= v * top_stride, v = 0 .. n_top - 1, with
+  // top_stride chosen for about 4 columns per entry; top[n_top - 1] = n_cols
   int64_t *top = nullptr;
   uint64_t top_stride = 1;
   int64_t n_top = 0;

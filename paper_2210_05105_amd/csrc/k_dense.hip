@@ -85,29 +85,50 @@ k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
   }
 }
 
-// out[c] = sum over b of P[b][c] (P is nrows x n), in a fixed order: 16
-// columns per block, 16 lanes per column stride over the rows, then the 16
-// lane sums are added in lane order.  Optionally out[c] = sqrt(sum).
+// out[c] = sum over b of P[b][c] (P is nrows x n), in a fixed order: CB
+// columns per block, 256 / CB row lanes per column striding over the rows
+// with 8 independent partial sums (loads in flight), combined pairwise;
+// then the lane sums are added in lane order.  Optionally out[c] =
+// sqrt(sum).
+template <int CB>
 __global__ void __launch_bounds__(256)
 k_colsum(const double *P, int nrows, int n, double *out, int take_sqrt,
          uint32_t *err) {
-  __shared__ double red[16][17];
-  const int cl = threadIdx.x % 16, rl = threadIdx.x / 16;
-  const int c = blockIdx.x * 16 + cl;
-  double s = 0;
-  if (c < n)
-    for (int b = rl; b < nrows; b += 16) s += P[(int64_t)b * n + c];
-  red[rl][cl] = s;
+  constexpr int RL = 256 / CB;
+  __shared__ double red[RL][CB + 1];
+  const int cl = threadIdx.x % CB, rl = threadIdx.x / CB;
+  const int c = blockIdx.x * CB + cl;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (c < n) {
+    int b = rl;
+    for (; b + 7 * RL < nrows; b += 8 * RL) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += P[(int64_t)(b + u * RL) * n + c];
+    }
+    for (; b < nrows; b += RL) a[0] += P[(int64_t)b * n + c];
+  }
+  red[rl][cl] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
   if (rl == 0 && c < n) {
     double t = 0;
-    for (int i = 0; i < 16; ++i) t += red[i][cl];
+    for (int i = 0; i < RL; ++i) t += red[i][cl];
     if (take_sqrt) {
       t = sqrt(t);
       if (!isfinite(t)) atomicOr(err, ERR_NONFINITE);
     }
     out[c] = t;
   }
+}
+
+// column sums with enough blocks to spread the rows' loads
+void colsum(const double *P, int nrows, int n, double *out, int take_sqrt,
+            uint32_t *err, hipStream_t s) {
+  if (n <= 128)
+    hipLaunchKernelGGL(k_colsum<4>, dim3(ceil_div(n, 4)), dim3(256), 0, s, P,
+                       nrows, n, out, take_sqrt, err);
+  else
+    hipLaunchKernelGGL(k_colsum<16>, dim3(ceil_div(n, 16)), dim3(256), 0, s,
+                       P, nrows, n, out, take_sqrt, err);
 }
 
 int gram_blocks(int64_t I, int64_t *rows_per_blk) {
@@ -665,8 +686,7 @@ void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
     case 6: case 5: launch_gram<T, 6>(U, I, R, Rp, partial, nblk, rpb, s); break;
     default: launch_gram<T, 9>(U, I, R, Rp, partial, nblk, rpb, s); break;
   }
-  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(R * R, 16)), dim3(256), 0, s,
-                     partial, nblk, R * R, G, 0, nullptr);
+  colsum(partial, nblk, R * R, G, 0, nullptr, s);
   CPR_LAUNCH_CHECK();
 }
 template void gram<float>(const float *, int64_t, int, double *, void *,
@@ -724,8 +744,7 @@ template <typename T>
 void finish_normalize(const double *X, int64_t I, int R, const double *partial,
                       int nblk, double *sigma, T *U, uint32_t *err,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(ceil_div(R, 16)), dim3(256), 0, s,
-                     partial, nblk, R, sigma, 1, err);
+  colsum(partial, nblk, R, sigma, 1, err, s);
   hipLaunchKernelGGL((k_scale_cols<T>), dim3(ceil_div(I * R, 256)), dim3(256),
                      0, s, X, I * R, R, sigma, U);
   CPR_LAUNCH_CHECK();

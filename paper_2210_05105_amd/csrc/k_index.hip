@@ -345,12 +345,16 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
       hipStreamSynchronize(s) != hipSuccess)
     return "hip error while building the mode index";
   out.max_col = (int64_t)mxh;
-  // offset table of the slowest mode != j
+  // offset table over the column-key space: entry v = first column with
+  // key >= v top_stride, the stride chosen for about 4 distinct columns per
+  // entry (a lookup then bisects a short range)
   int last = -1;
   for (int k = 0; k < N; ++k)
     if (k != j) last = k;
-  out.top_stride = stride[last];
-  out.n_top = dims_h[last] + 1;
+  const uint64_t key_space = stride[last] * (uint64_t)dims_h[last];
+  const uint64_t target = std::max<uint64_t>(1, (uint64_t)out.n_cols / 4);
+  out.top_stride = std::max<uint64_t>(1, (key_space + target - 1) / target);
+  out.n_top = (int64_t)((key_space + out.top_stride - 1) / out.top_stride) + 1;
   if (hipMalloc((void **)&out.top, out.n_top * 8) != hipSuccess)
     return "out of device memory for the mode index";
   hipLaunchKernelGGL(k_top, dim3(ceil_div(out.n_top, 256)), dim3(256), 0, s,

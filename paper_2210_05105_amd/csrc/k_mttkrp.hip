@@ -43,8 +43,8 @@ __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
   h[e] = (T)v;
 }
 
-// Column of each draw: its key, then a binary search inside the range of
-// columns that share the slowest mode's index.  The first draw of a column
+// Column of each draw: its key, then a binary search inside the short range
+// of columns given by the offset table (key / top_stride).  The first draw of a column
 // claims it with atomicMin (read first: most later draws see a smaller
 // owner and skip the atomic).
 __global__ void __launch_bounds__(LK_THREADS)
@@ -517,7 +517,7 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
 // the chunk belongs to the group alone and is stored; only rows cut by a
 // chunk boundary are added with atomics.
 constexpr int AC_ITEMS = BK_SLICE / MT_THREADS;  // records per thread
-constexpr int AC_BATCH = 8;  // records per batch (two batches in flight)
+constexpr int AC_BATCH = 6;  // records per batch (two batches in flight)
 
 // VW consecutive columns of an h row as one 16-byte load (R a multiple of
 // VW; rows are then 16-byte aligned) or VW clamped loads
@@ -538,19 +538,23 @@ __device__ __forceinline__ void load_cols(const T *hr, int cb, int R,
 
 template <typename T, int L, int VW, bool VEC>
 __global__ void __launch_bounds__(MT_THREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
 k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
            const int64_t *bk_start, int nbk, int bb, const BkRec<T> *rec,
            const T *hc, int R, int64_t I, T *M, T *part) {
   constexpr int G = MT_THREADS / L;  // lane groups per block
   extern __shared__ unsigned char bk_lds_raw[];
-  T *blk = reinterpret_cast<T *>(bk_lds_raw);                // B x R
   const int B = 1 << bb;
-  T *lc = blk + B * R;                                       // BK_SLICE coefs
+  T *lc = reinterpret_cast<T *>(bk_lds_raw);                   // coefs
   uint32_t *lk = reinterpret_cast<uint32_t *>(lc + BK_SLICE);  // keys
+  // partial sums of the runs cut by chunk boundaries: [group][first, last]
+  T *pr = reinterpret_cast<T *>(lk + BK_SLICE);
   __shared__ int32_t cnt[256 + 1];
   __shared__ int32_t wsum[MT_THREADS / WAVE];
+  __shared__ int32_t s_fa[G], s_fb[G];
   const int t = threadIdx.x, l = lane_id();
   const int gl = t % L, g = t / L;
+  const int cb = gl * VW;
   const int64_t nitems = item_start[nbk];
   for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int bk = item_bk[item];
@@ -560,6 +564,11 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
                                                           : bk_start[bk + 1];
     const int n = (int)(r1 - r0);
     const bool single = item_start[bk + 1] - item_start[bk] == 1;
+    const int64_t row0 = (int64_t)bk * B;
+    const int nrows = (int)(I - row0 < B ? I - row0 : B);
+    // a bucket held by one slice goes straight to M; the slices of a split
+    // bucket write their block to their own scratch slot for k_bk_combine
+    T *mo = single ? M + row0 * R : part + item * (int64_t)B * R;
     // this thread's records: positions t, t + 256, ...
     BkRec<T> my[AC_ITEMS];
     if (n > 0) {
@@ -569,16 +578,17 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
         my[i] = rec[r0 + (e < n ? e : n - 1)];
       }
     }
-    for (int e = t; e < B * R; e += MT_THREADS) blk[e] = T(0);
     for (int e = t; e <= 256; e += MT_THREADS) cnt[e] = 0;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < AC_ITEMS; ++i)
       if (i * MT_THREADS + t < n) atomicAdd(&cnt[my[i].key & 255u], 1);
     __syncthreads();
+    bool empty_row;  // row t of the bucket has no record in this slice
     {  // exclusive scan of the 256 row counts (thread t owns row t)
       const int w = t / WAVE;
       const int v = t < 256 ? cnt[t] : 0;
+      empty_row = v == 0;
       int inc = v;
       for (int o = 1; o < WAVE; o <<= 1) {
         int y = __shfl_up(inc, o, WAVE);
@@ -599,39 +609,51 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
         lc[pos] = my[i].coef;
       }
     __syncthreads();
-    // group g: sorted records [c0, c1); lane gl owns columns gl VW ..
+    // rows without records are zero
+    if (t < nrows && empty_row) {
+      T *zr = mo + (int64_t)t * R;
+      for (int c = 0; c < R; ++c) zr[c] = T(0);
+    }
+    // group g: sorted records [c0, c1); lane gl owns columns cb .. cb+VW-1
     const int per = (n + G - 1) / G;
     const int c0 = g * per < n ? g * per : n;
     const int c1 = c0 + per < n ? c0 + per : n;
-    const int cb = gl * VW;
-    // rows also held by the neighbouring chunks take LDS float atomics
-    // (slow); every other row belongs to this group alone and is stored
-    const int row_a = (c0 < c1 && c0 > 0 && ((lk[c0 - 1] ^ lk[c0]) & 255u) == 0)
-                          ? (int)(lk[c0] & 255u) : -1;
-    const int row_b = (c0 < c1 && c1 < n && ((lk[c1] ^ lk[c1 - 1]) & 255u) == 0)
-                          ? (int)(lk[c1 - 1] & 255u) : -1;
-    T acc[VW];
-#pragma unroll
-    for (int q = 0; q < VW; ++q) acc[q] = T(0);
-    auto flush = [&](int row) {
-      T *br = blk + row * R + cb;
-      if (row == row_a || row == row_b) {
-#pragma unroll
-        for (int q = 0; q < VW; ++q)
-          if (VEC ? cb < R : cb + q < R) atomicAdd(br + q, acc[q]);
-      } else if (VEC) {
+    // the chunk's first run continues the previous chunk's row (fa) and its
+    // last run goes on in the next chunk (fb); those two partial sums go to
+    // LDS, every other run is a whole row of this chunk and is stored
+    const int fa = (c0 < c1 && c0 > 0 && ((lk[c0 - 1] ^ lk[c0]) & 255u) == 0)
+                       ? (int)(lk[c0] & 255u) : -1;
+    const int fb = (c0 < c1 && c1 < n && ((lk[c1] ^ lk[c1 - 1]) & 255u) == 0)
+                       ? (int)(lk[c1 - 1] & 255u) : -1;
+    if (gl == 0) {
+      s_fa[g] = fa;
+      s_fb[g] = fb;
+    }
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    auto put = [&](T *dst, const T (&v)[VW]) {
+      if constexpr (VEC) {
         if (cb < R) {
-          typedef T vec_t __attribute__((ext_vector_type(VW)));
-          vec_t v;
+          vec_t x;
 #pragma unroll
-          for (int q = 0; q < VW; ++q) v[q] = acc[q];
-          *reinterpret_cast<vec_t *>(br) = v;
+          for (int q = 0; q < VW; ++q) x[q] = v[q];
+          *reinterpret_cast<vec_t *>(dst) = x;
         }
       } else {
 #pragma unroll
         for (int q = 0; q < VW; ++q)
-          if (cb + q < R) br[q] = acc[q];
+          if (cb + q < R) dst[q] = v[q];
       }
+    };
+    T acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = T(0);
+    auto flush = [&](int row) {
+      if (row == fa)
+        put(pr + (2 * g) * (L * VW) + cb, acc);
+      else if (row == fb)
+        put(pr + (2 * g + 1) * (L * VW) + cb, acc);
+      else
+        put(mo + (int64_t)row * R + cb, acc);
 #pragma unroll
       for (int q = 0; q < VW; ++q) acc[q] = T(0);
     };
@@ -675,12 +697,22 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
       }
     }
     __syncthreads();
-    // a bucket held by one slice goes straight to M; the slices of a split
-    // bucket store their block in their own scratch slot for k_bk_combine
-    const int64_t row0 = (int64_t)bk * B;
-    const int nrows = (int)(I - row0 < B ? I - row0 : B);
-    T *mo = single ? M + row0 * R : part + item * (int64_t)B * R;
-    for (int e = t; e < nrows * R; e += MT_THREADS) mo[e] = blk[e];
+    // a row cut by chunk boundaries is summed by the group where it starts:
+    // its last-run partial, then the first-run partials of the following
+    // groups in order
+    if (fb >= 0 && fb != fa) {
+      T sum[VW];
+      const T *p0 = pr + (2 * g + 1) * (L * VW) + cb;
+#pragma unroll
+      for (int q = 0; q < VW; ++q) sum[q] = p0[q];
+      for (int h2 = g + 1; h2 < G && s_fa[h2] == fb; ++h2) {
+        const T *p1 = pr + (2 * h2) * (L * VW) + cb;
+#pragma unroll
+        for (int q = 0; q < VW; ++q) sum[q] += p1[q];
+        if (s_fb[h2] != fb) break;
+      }
+      put(mo + (int64_t)fb * R + cb, sum);
+    }
     __syncthreads();
   }
 }
@@ -859,9 +891,13 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                      w.tile_first, w.uq_base, row, val, nbk, bb, bk_start,
                      bk_fill, rec);
   CPR_LAUNCH_CHECK();
-  const size_t lds = (size_t)(1 << bb) * R * sizeof(T) +
-                     (size_t)BK_SLICE * (sizeof(T) + 4);
   constexpr int VW = 16 / sizeof(T);  // columns per lane
+  // records, then the boundary partials: 2 per lane group, L VW columns
+  const int lanes_r = (R + VW - 1) / VW;
+  int lanes_p = 1;
+  while (lanes_p < lanes_r) lanes_p *= 2;
+  const size_t lds = (size_t)BK_SLICE * (sizeof(T) + 4) +
+                     (size_t)2 * (MT_THREADS / lanes_p) * lanes_p * VW * sizeof(T);
   static bool attr_set[2][14] = {};
   auto launch = [&](auto kern, int li) {
     if (!attr_set[sizeof(T) == 8][li]) {
