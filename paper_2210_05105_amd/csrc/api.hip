@@ -314,7 +314,8 @@ void do_mttkrp(cp_ctx *c, int mode) {
                     static_cast<const T *>(ix.val), c->R, M, c->s);
   } else {
     sampled_mttkrp<T>(c->w, c->dims[mode], ix.col_ptr, ix.row,
-                      static_cast<const T *>(ix.val), c->R, M, c->s);
+                      static_cast<const T *>(ix.val), ix.bk_start, c->R, M,
+                      c->s);
   }
   c->mttkrp_mode = mode;
 }
@@ -498,7 +499,16 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     }
   }
   c->w.rec_cap = cap;
-  dalloc(c, &c->w.rec, (size_t)cap * bucket_record_bytes((int)ts));
+  if (c->sampler != CP_SAMPLER_EXACT) {
+    // records sit in each bucket's fixed region: nnz of them at most
+    dalloc(c, &c->w.rec, (size_t)c->nnz * bucket_record_bytes((int)ts));
+    for (int k = 0; k < N; ++k) {
+      const int64_t nbk_k = (c->dims[k] + (1 << bb) - 1) >> bb;
+      dalloc(c, &c->ix[k].bk_start, (size_t)(nbk_k + 1) * 8);
+      bucket_regions(c->ix[k].row, c->nnz, c->dims[k], bb, c->ix[k].bk_start,
+                     c->w.bk, c->w.scan_tmp, c->s);
+    }
+  }
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);
   dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);

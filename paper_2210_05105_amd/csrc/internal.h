@@ -62,6 +62,9 @@ struct ModeIndex {
   int64_t *top = nullptr;
   uint64_t top_stride = 1;
   int64_t n_top = 0;
+  // sampled MTTKRP: record region start of each output-row bucket (set up
+  // by cp_init for the sampling samplers)
+  int64_t *bk_start = nullptr;
   int32_t *row = nullptr;       // nnz rows i_j
   void *val = nullptr;          // nnz values (float or double)
 };
@@ -174,8 +177,8 @@ struct SampleWork {
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
   int64_t *scratch;  // 4 J: first-draw flags, lengths, per-block totals
   void *scan_tmp;    // scan_temp_bytes(max(J, buckets + 1))
-  int64_t *bk;       // 5 (buckets + 1): per output-row bucket counts/offsets
-  void *rec;         // cap records: extracted nonzeros grouped by bucket
+  int64_t *bk;       // 5 (buckets + 1): bucket fill counts, ends, slices
+  void *rec;         // nnz records: extracted nonzeros in bucket regions
   int64_t rec_cap;
   void *part;        // per-slice blocks of split buckets (B x R each)
 };
@@ -193,7 +196,13 @@ void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    hipStream_t s);
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
-                    const int32_t *row, const T *val, int R, T *M,
+                    const int32_t *row, const T *val, const int64_t *bk_start,
+                    int R, T *M, hipStream_t s);
+// Fixed record regions of a mode's output-row buckets of 2^bb rows:
+// starts[b] = nonzeros of the mode in buckets < b (nbk + 1 entries); cnt is
+// nbk + 1 int64 of scratch.
+void bucket_regions(const int32_t *row, int64_t nnz, int64_t I, int bb,
+                    int64_t *starts, int64_t *cnt, void *scan_tmp,
                     hipStream_t s);
 template <typename T>
 void exact_mttkrp(const ModeList &ml, int64_t n_cols, const uint64_t *col_key,

@@ -315,107 +315,67 @@ __device__ __forceinline__ void bucket_runs(int bk, bool valid, int &leader,
   len = nxt - l;
 }
 
-__global__ void __launch_bounds__(MT_THREADS)
-k_bk_count(const int64_t *counts, const int64_t *uq_off,
-           const int64_t *tile_first, const int64_t *uq_base,
-           const int32_t *row, int nbk, int bb, int64_t *bk_total) {
-  extern __shared__ uint32_t hist[];  // nbk when nbk <= BK_LDS_MAX
-  __shared__ int32_t cst[BK_TILE + 1];
-  const int64_t nz = counts[1];
-  const bool use_lds = nbk <= BK_LDS_MAX;
-  const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
-  const int l = lane_id();
-  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int64_t e0 = tile * BK_TILE;
-    const int64_t e1 = e0 + BK_TILE < nz ? e0 + BK_TILE : nz;
-    if (use_lds)
-      for (int b = threadIdx.x; b < nbk; b += MT_THREADS) hist[b] = 0;
-    int64_t ub;
-    int ncol;
-    tile_columns(counts, uq_off, tile_first, tile, ntile, e0, cst, ub, ncol);
-    __syncthreads();
-    int64_t p[BK_ITEMS];
-#pragma unroll
-    for (int i = 0; i < BK_ITEMS; ++i) {
-      const int pos = i * MT_THREADS + threadIdx.x;
-      const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
-      p[i] = uq_base[ub + find_local(cst, ncol, (int)(e - e0))] + e;
-    }
-    int rw[BK_ITEMS];
-#pragma unroll
-    for (int i = 0; i < BK_ITEMS; ++i) rw[i] = row[p[i]];
-#pragma unroll
-    for (int i = 0; i < BK_ITEMS; ++i) {
-      const bool valid = e0 + i * MT_THREADS + threadIdx.x < e1;
-      const int bk = rw[i] >> bb;
-      int leader, len;
-      bucket_runs(bk, valid, leader, len);
-      if (valid && leader == l) {
-        if (use_lds) atomicAdd(&hist[bk], (uint32_t)len);
-        else atomicAdd((unsigned long long *)&bk_total[bk], (unsigned long long)len);
-      }
-    }
-    __syncthreads();
-    if (use_lds)
-      for (int b = threadIdx.x; b < nbk; b += MT_THREADS)
-        if (hist[b])
-          atomicAdd((unsigned long long *)&bk_total[b],
-                    (unsigned long long)hist[b]);
-    __syncthreads();
-  }
-}
-
-// Accumulation plan in one workgroup: bk_start = exclusive prefix sums of
-// the bucket totals (nbk + 1 entries, the last the total), item_start the
-// same for the slices per bucket, item_bk[i] = bucket of slice i.  Every
-// bucket gets at least one slice (an empty one writes zero rows), so the
-// accumulation writes every row of M.  Thread t takes a contiguous run of
-// buckets.
+// Accumulation plan in one workgroup: bucket b's records occupy
+// [bk_start[b], bk_start[b] + bk_fill[b]) of its fixed region; bk_end is
+// that end, item_start the exclusive prefix sums of the slices per bucket
+// and item_bk[i] the bucket of slice i.  Every bucket gets at least one
+// slice (an empty one writes zero rows), so the accumulation writes every
+// row of M.  Thread t takes a contiguous run of buckets.
 constexpr int PL_THREADS = 1024;
 __global__ void __launch_bounds__(PL_THREADS)
-k_bk_plan(const int64_t *bk_total, int nbk, int64_t *bk_start,
-          int64_t *item_start, int32_t *item_bk) {
-  __shared__ int64_t wa[PL_THREADS / WAVE], wb[PL_THREADS / WAVE];
+k_bk_plan(const int64_t *bk_start, const int64_t *bk_fill, int nbk,
+          int64_t *bk_end, int64_t *item_start, int32_t *item_bk) {
+  __shared__ int64_t wb[PL_THREADS / WAVE];
   const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
   const int per = (nbk + 1 + PL_THREADS - 1) / PL_THREADS;
   const int b0 = t * per, b1 = b0 + per < nbk + 1 ? b0 + per : nbk + 1;
-  int64_t sa = 0, sb = 0;
-  auto slices = [&](int b, int64_t n) -> int64_t {
-    return b < nbk ? (n > BK_SLICE ? (n + BK_SLICE - 1) / BK_SLICE : 1) : 0;
+  auto slices = [&](int b) -> int64_t {
+    if (b >= nbk) return 0;
+    const int64_t n = bk_fill[b];
+    return n > BK_SLICE ? (n + BK_SLICE - 1) / BK_SLICE : 1;
   };
-  for (int b = b0; b < b1; ++b) {
-    const int64_t n = b < nbk ? bk_total[b] : 0;
-    sa += n;
-    sb += slices(b, n);
-  }
-  int64_t ia = sa, ib = sb;
+  int64_t sb = 0;
+  for (int b = b0; b < b1; ++b) sb += slices(b);
+  int64_t ib = sb;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
-    const int64_t ya = __shfl_up(ia, o, WAVE), yb = __shfl_up(ib, o, WAVE);
-    if (l >= o) {
-      ia += ya;
-      ib += yb;
-    }
+    const int64_t yb = __shfl_up(ib, o, WAVE);
+    if (l >= o) ib += yb;
   }
-  if (l == WAVE - 1) {
-    wa[w] = ia;
-    wb[w] = ib;
-  }
+  if (l == WAVE - 1) wb[w] = ib;
   __syncthreads();
-  int64_t oa = ia - sa, ob = ib - sb;
-  for (int i = 0; i < w; ++i) {
-    oa += wa[i];
-    ob += wb[i];
-  }
+  int64_t ob = ib - sb;
+  for (int i = 0; i < w; ++i) ob += wb[i];
   for (int b = b0; b < b1; ++b) {
-    const int64_t n = b < nbk ? bk_total[b] : 0;
-    const int64_t ni = slices(b, n);
-    bk_start[b] = oa;
+    const int64_t ni = slices(b);
+    if (b < nbk) bk_end[b] = bk_start[b] + bk_fill[b];
     item_start[b] = ob;
     for (int64_t i = 0; i < ni; ++i) item_bk[ob + i] = b;
-    oa += n;
     ob += ni;
   }
+}
+
+// Fixed record regions of the output-row buckets of one mode (built once):
+// the bucket's nonzeros in the whole mode bound the nonzeros any solve can
+// extract into it (extracted positions are distinct).  starts = exclusive
+// prefix sums of the row-bucket histogram (nbk + 1 entries).
+__global__ void __launch_bounds__(MT_THREADS)
+k_bucket_hist(const int32_t *row, int64_t nnz, int nbk, int bb, int64_t *cnt) {
+  extern __shared__ uint32_t bh[];  // nbk when nbk <= BK_LDS_MAX
+  const bool use_lds = nbk <= BK_LDS_MAX;
+  if (use_lds)
+    for (int b = threadIdx.x; b < nbk; b += MT_THREADS) bh[b] = 0;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * MT_THREADS + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * MT_THREADS) {
+    const int b = row[e] >> bb;
+    if (use_lds) atomicAdd(&bh[b], 1u);
+    else atomicAdd((unsigned long long *)&cnt[b], 1ull);
+  }
+  __syncthreads();
+  if (use_lds)
+    for (int b = threadIdx.x; b < nbk; b += MT_THREADS)
+      if (bh[b]) atomicAdd((unsigned long long *)&cnt[b], (unsigned long long)bh[b]);
 }
 
 // One extracted nonzero in bucket order: key = (distinct column u << 8) |
@@ -433,8 +393,9 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
              const int64_t *uq_base, const int32_t *row, const T *val, int nbk,
              int bb, const int64_t *bk_start, int64_t *bk_fill,
              BkRec<T> *rec) {
-  extern __shared__ uint32_t sc_lds[];  // cnt, base: nbk each (<= BK_LDS_MAX)
-  uint32_t *cnt = sc_lds, *base = sc_lds + nbk;  // base: record positions
+  extern __shared__ int64_t sc_lds[];  // base, cnt: nbk each (<= BK_LDS_MAX)
+  int64_t *base = sc_lds;  // record position of the tile's first record
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(sc_lds + nbk);
   __shared__ int32_t cst[BK_TILE + 1];
   const int64_t nz = counts[1];
   const bool use_lds = nbk <= BK_LDS_MAX;
@@ -483,9 +444,9 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
       for (int b = threadIdx.x; b < nbk; b += MT_THREADS) {
         const uint32_t c = cnt[b];
         if (c)
-          base[b] = (uint32_t)(bk_start[b] +
-                               (int64_t)atomicAdd((unsigned long long *)&bk_fill[b],
-                                                  (unsigned long long)c));
+          base[b] = bk_start[b] +
+                    (int64_t)atomicAdd((unsigned long long *)&bk_fill[b],
+                                       (unsigned long long)c);
         cnt[b] = 0;
       }
     __syncthreads();
@@ -497,7 +458,7 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
       bucket_runs(bk, bk >= 0, lead, len);
       int64_t off = 0;
       if (bk >= 0 && lead == l)
-        off = use_lds ? (int64_t)base[bk] + (int64_t)atomicAdd(&cnt[bk], (uint32_t)len)
+        off = use_lds ? base[bk] + (int64_t)atomicAdd(&cnt[bk], (uint32_t)len)
                       : bk_start[bk] + (int64_t)atomicAdd(
                             (unsigned long long *)&bk_fill[bk],
                             (unsigned long long)len);
@@ -540,7 +501,8 @@ template <typename T, int L, int VW, bool VEC>
 __global__ void __launch_bounds__(MT_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
 k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
-           const int64_t *bk_start, int nbk, int bb, const BkRec<T> *rec,
+           const int64_t *bk_start, const int64_t *bk_end, int nbk, int bb,
+           const BkRec<T> *rec,
            const T *hc, int R, int64_t I, T *M, T *part) {
   constexpr int G = MT_THREADS / L;  // lane groups per block
   extern __shared__ unsigned char bk_lds_raw[];
@@ -560,8 +522,7 @@ k_bk_accum(const int64_t *item_start, const int32_t *item_bk,
     const int bk = item_bk[item];
     const int64_t k = item - item_start[bk];
     const int64_t r0 = bk_start[bk] + k * BK_SLICE;
-    const int64_t r1 = r0 + BK_SLICE < bk_start[bk + 1] ? r0 + BK_SLICE
-                                                          : bk_start[bk + 1];
+    const int64_t r1 = r0 + BK_SLICE < bk_end[bk] ? r0 + BK_SLICE : bk_end[bk];
     const int n = (int)(r1 - r0);
     const bool single = item_start[bk + 1] - item_start[bk] == 1;
     const int64_t row0 = (int64_t)bk * B;
@@ -867,29 +828,26 @@ size_t lds_cap() { return 160 * 1024 - 8 * 1024; }
 
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
-                    const int32_t *row, const T *val, int R, T *M,
-                    hipStream_t s) {
+                    const int32_t *row, const T *val, const int64_t *bk_start,
+                    int R, T *M, hipStream_t s) {
   const T *hc = static_cast<const T *>(w.hc);
   const int bb = bucket_shift(R, (int)sizeof(T));
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
-  int64_t *bk_total = w.bk, *bk_fill = w.bk + (nbk + 1),
-          *bk_start = w.bk + 2 * (nbk + 1), *item_start = w.bk + 3 * (nbk + 1);
+  int64_t *bk_fill = w.bk, *bk_end = w.bk + (nbk + 1),
+          *item_start = w.bk + 2 * (nbk + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
-  zero_fill<int64_t>(bk_total, 2 * (nbk + 1), s);  // totals and fill cursors
+  zero_fill<int64_t>(bk_fill, nbk + 1, s);  // fill cursors
   hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
                      w.counts, w.uq_off, w.tile_first);
   const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
-  hipLaunchKernelGGL(k_bk_count, gt, b, hl, s, w.counts, w.uq_off,
-                     w.tile_first, w.uq_base, row, nbk, bb, bk_total);
-  CPR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bk_plan, dim3(1), dim3(PL_THREADS), 0, s, bk_total,
-                     nbk, bk_start, item_start, w.item_bk);
-  CPR_LAUNCH_CHECK();
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
-  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 2 * hl, s, w.counts, w.uq_off,
+  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 3 * hl, s, w.counts, w.uq_off,
                      w.tile_first, w.uq_base, row, val, nbk, bb, bk_start,
                      bk_fill, rec);
+  CPR_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bk_plan, dim3(1), dim3(PL_THREADS), 0, s, bk_start,
+                     bk_fill, nbk, bk_end, item_start, w.item_bk);
   CPR_LAUNCH_CHECK();
   constexpr int VW = 16 / sizeof(T);  // columns per lane
   // records, then the boundary partials: 2 per lane group, L VW columns
@@ -908,6 +866,7 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
       attr_set[sizeof(T) == 8][li] = true;
     }
     hipLaunchKernelGGL(kern, gt, b, lds, s, item_start, w.item_bk, bk_start,
+                       bk_end,
                        nbk, bb, rec, hc, R, I, M, part);
   };
   const int lanes = (R + VW - 1) / VW;  // lanes per record
@@ -944,11 +903,25 @@ size_t bucket_record_bytes(int tsize) {
 }
 template void sampled_mttkrp<float>(const SampleWork &, int64_t,
                                     const int64_t *, const int32_t *,
-                                    const float *, int, float *, hipStream_t);
+                                    const float *, const int64_t *, int,
+                                    float *, hipStream_t);
 template void sampled_mttkrp<double>(const SampleWork &, int64_t,
                                      const int64_t *, const int32_t *,
-                                     const double *, int, double *,
-                                     hipStream_t);
+                                     const double *, const int64_t *, int,
+                                     double *, hipStream_t);
+
+void bucket_regions(const int32_t *row, int64_t nnz, int64_t I, int bb,
+                    int64_t *starts, int64_t *cnt, void *scan_tmp,
+                    hipStream_t s) {
+  const int nbk = (int)((I + (1 << bb) - 1) >> bb);
+  zero_fill<int64_t>(cnt, nbk + 1, s);
+  const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
+  const int64_t g = std::min<int64_t>(std::max<int64_t>(ceil_div(nnz, MT_THREADS), 1), 2048);
+  hipLaunchKernelGGL(k_bucket_hist, dim3((unsigned)g), dim3(MT_THREADS), hl, s,
+                     row, nnz, nbk, bb, cnt);
+  CPR_LAUNCH_CHECK();
+  exclusive_scan_i64(cnt, starts, nbk + 1, scan_tmp, s);
+}
 
 template <typename T>
 void exact_mttkrp(const ModeList &ml, int64_t n_cols, const uint64_t *col_key,
