@@ -683,14 +683,30 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
 // (U[row0 + r] (*) h)^T G_{>k} (U[row0 + r] (*) h) of row r of every
 // sample's leaf; each sample accumulates its rows in order and takes
 // index = min{i : t < F(i)} over rows of positive mass.  Then h *= U[index].
+// A sample's leaf is F consecutive rows of U: they are read PB rows at a
+// time as 16-byte chunks spread over all 64 lanes, staged in LDS in the
+// factor's precision, and the next batch is in flight while the current
+// one's PB passes run on the MFMA.
 template <typename T, int NT>
+constexpr int leaf_pb() {  // rows per batch (F is a multiple)
+  return 2;
+}
+
+template <typename T, int NT, bool VEC>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
 k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
            int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
            uint32_t *err) {
-  constexpr int RP = 16 * NT, KS = 4 * NT;
+  constexpr int RP = 16 * NT, KS = 4 * NT, PB = leaf_pb<T, NT>();
+  constexpr int CE = VEC ? 16 / (int)sizeof(T) : 1;  // elements per chunk
+  constexpr int RSU = RP + 16 / (int)sizeof(T);      // staged row stride
+  constexpr int NCH = (16 * PB * RP / CE + WAVE - 1) / WAVE;
+  constexpr int HB = 16 * tile_stride<NT>() * 8;     // h staging bytes
+  constexpr int UB = PB * 16 * RSU * (int)sizeof(T);
+  constexpr int WB = (HB > UB ? HB : UB) / 8;        // doubles per wave
   __shared__ double sG[RP * RP];
-  __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
+  __shared__ double sW[ST / WAVE][WB];
+  __shared__ int64_t sR0[ST / WAVE][16];  // first leaf row of each slot
   stage_pad<RP>(sG, Gg, R);
   __syncthreads();
   const int l = lane_id();
@@ -703,59 +719,89 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
   const int64_t row0 = (int64_t)(in.v[ps] - P2) * F;
   const double t = in.t[ps];
   double hA[KS], hD[NT][4];
-  double *buf = sH[threadIdx.x / WAVE];
+  double *buf = sW[threadIdx.x / WAVE];
   load_hfrag_lds<NT>(w.h, s, buf, hA, hD);
-  // Pass r: row r of each slot's leaf, staged in the wave's LDS buffer with
-  // one coalesced load per lane and row (lane c < R: column c; rows past I
-  // give zeros).
-  constexpr int RS = tile_stride<NT>();
-  const int lc = l < R ? l : R - 1;
-  int32_t rr[16];  // first leaf row of slot i (rows < 2^31), wave-uniform
+  T *stg = reinterpret_cast<T *>(buf);  // [PB][16][RSU], after h
+  int64_t *r0s = sR0[threadIdx.x / WAVE];
+  if (l < 16) r0s[l] = row0;
+  // chunk j of this lane: sample i, row r of the batch, column c, packed
+  // as (i << 24) | (r << 16) | c (i = 16: no chunk); rows past I are read
+  // clamped and staged as zeros
+  const int cps = PB * R / CE;  // chunks per sample and batch
+  int cm[NCH];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) rr[i] = __builtin_amdgcn_readlane((int32_t)row0, i);
-  // raw U values of the next pass, loaded while this pass is on the MFMA
-  T raw[16];
-  auto load_pass = [&](int r) {
-    r = r < F ? r : F - 1;
+  for (int j = 0; j < NCH; ++j) {
+    const int qq = l + WAVE * j;
+    if (qq < 16 * cps) {
+      const int i = qq / cps, e = (qq - i * cps) * CE;
+      cm[j] = (i << 24) | ((e / R) << 16) | (e % R);
+    } else {
+      cm[j] = 16 << 24;
+    }
+  }
+  typedef T chunk_t __attribute__((ext_vector_type(CE)));
+  chunk_t ch[NCH];
+  wave_lds_sync();  // h fragments read, r0s written
+  auto chunk_row = [&](int j, int bt) -> int64_t {
+    const int i = cm[j] >> 24;
+    return r0s[i < 16 ? i : 0] + (int64_t)bt * PB + ((cm[j] >> 16) & 255);
+  };
+  auto load_batch = [&](int bt) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int64_t row = (int64_t)rr[i] + r;
-      raw[i] = U[(row < I ? row : I - 1) * R + lc];
+    for (int j = 0; j < NCH; ++j) {
+      int64_t row = chunk_row(j, bt);
+      row = row < I ? row : I - 1;
+      ch[j] = *reinterpret_cast<const chunk_t *>(U + row * R + (cm[j] & 65535));
     }
   };
+  if (R < RP)  // columns R .. RP - 1 stay zero
+    for (int e = l; e < PB * 16 * (RP - R); e += WAVE) {
+      const int pr = e / (RP - R), c = R + e % (RP - R);
+      stg[pr * RSU + c] = T(0);
+    }
   double pre = 0.0;
   int pick = -1, lastpos = -1;
-  load_pass(0);
-  for (int r = 0; r < F; ++r) {
-    wave_lds_sync();  // the previous pass's fragment reads are done
-    if (l < RP) {
+  const int nb = F / PB;
+  load_batch(0);
+  for (int bt = 0; bt < nb; ++bt) {
+    wave_lds_sync();  // the previous batch's fragment reads are done
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int64_t row = (int64_t)rr[i] + r;
-        buf[i * RS + l] = (row < I && l < R) ? (double)raw[i] : 0.0;
+    for (int j = 0; j < NCH; ++j) {
+      const int i = cm[j] >> 24;
+      if (i < 16) {
+        const bool ok = chunk_row(j, bt) < I;
+        T *d = stg + (((cm[j] >> 16) & 255) * 16 + i) * RSU + (cm[j] & 65535);
+#pragma unroll
+        for (int c = 0; c < CE; ++c) d[c] = ok ? ch[j][c] : T(0);
       }
     }
-    load_pass(r + 1);
+    load_batch(bt + 1 < nb ? bt + 1 : bt);
     wave_lds_sync();
-    // G_{>k} fragments are read from LDS again in every pass rather than
-    // held in registers
-    asm volatile("" ::: "memory");
-    double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
-    lds_bfrag<NT>(sG, gB);
+#pragma unroll 1
+    for (int pp = 0; pp < PB; ++pp) {
+      const int r = bt * PB + pp;
+      const T *sp = stg + pp * 16 * RSU;
+      // G_{>k} fragments are read from LDS again in every pass rather than
+      // held in registers
+      asm volatile("" ::: "memory");
+      double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
+      lds_bfrag<NT>(sG, gB);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16] * hA[ks];
+      for (int ks = 0; ks < KS; ++ks)
+        xA[ks] = (double)sp[(l % 16) * RSU + 4 * ks + l / 16] * hA[ks];
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt)
-        xD[tt][v] = buf[(l / 16 + 4 * v) * RS + 16 * tt + (l % 16)] * hD[tt][v];
-    tile_mass<NT>(xA, xD, gB, ms);
-    const double m = lane_mass(ms);  // lanes 0..15: row r of slot l
-    if (pick < 0 && row0 + r < I && m > 0) {
-      pre += m;
-      lastpos = r;
-      if (t < pre) pick = r;
+        for (int tt = 0; tt < NT; ++tt)
+          xD[tt][v] = (double)sp[(l / 16 + 4 * v) * RSU + 16 * tt + (l % 16)] *
+                      hD[tt][v];
+      tile_mass<NT>(xA, xD, gB, ms);
+      const double m = lane_mass(ms);  // lanes 0..15: row r of slot l
+      if (pick < 0 && row0 + r < I && m > 0) {
+        pre += m;
+        lastpos = r;
+        if (t < pre) pick = r;
+      }
     }
   }
   const bool act = l < n;
@@ -846,9 +892,14 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
       CPR_LAUNCH_CHECK();
       cur ^= 1;
     }
-    hipLaunchKernelGGL((k_sts_leaf<T, NT>), gl, b, 0, st,
-                       static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2, Gg,
-                       J, w, w.slot[cur], q, nq, sidx, err);
+    if (R % (16 / (int)sizeof(T)) == 0)
+      hipLaunchKernelGGL((k_sts_leaf<T, NT, true>), gl, b, 0, st,
+                         static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2,
+                         Gg, J, w, w.slot[cur], q, nq, sidx, err);
+    else
+      hipLaunchKernelGGL((k_sts_leaf<T, NT, false>), gl, b, 0, st,
+                         static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2,
+                         Gg, J, w, w.slot[cur], q, nq, sidx, err);
     CPR_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL((k_sts_final<T, NT>), gl, b, 0, st, R, J, w.h, Gp, trace,
