@@ -487,21 +487,34 @@ __device__ __forceinline__ double afrag(const double *A, int R, int t, int ks,
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(SV_THREADS)
+__attribute__((amdgpu_waves_per_eu(NT <= 2 ? 4 : 1)))
 k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         double *X, double *partial, int64_t *rows_out) {
   constexpr int KS = 4 * NT;          // k-steps
-  constexpr bool REG = NT <= 2;       // G, G^+ fragments held in registers
+  constexpr int RP = 16 * NT;
+  constexpr bool LDS = NT <= 4;       // G, G^+ staged in LDS (zero padded)
   const int l = lane_id(), w = threadIdx.x / WAVE;
-  double gpf[REG ? NT * KS : 1], gf[REG ? NT * KS : 1];
-  if (REG) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        gpf[t * KS + ks] = afrag<NT>(Gp, R, t, ks, l);
-        gf[t * KS + ks] = afrag<NT>(G, R, t, ks, l);
-      }
+  __shared__ double sG[LDS ? 2 * RP * RP : 1];
+  if (LDS) {
+    for (int e = threadIdx.x; e < RP * RP; e += SV_THREADS) {
+      const int a = e / RP, b = e % RP;
+      const bool in = a < R && b < R;
+      const int ec = in ? a * R + b : 0;
+      const double gp = Gp[ec], g = G[ec];
+      sG[e] = in ? gp : 0.0;
+      sG[RP * RP + e] = in ? g : 0.0;
+    }
+    __syncthreads();
   }
+  // (A^T)[i][k] fragments, i = 16 t + l % 16, k = 4 ks + l / 16
+  auto fp = [&](int t, int ks) -> double {
+    return LDS ? sG[(4 * ks + l / 16) * RP + 16 * t + (l % 16)]
+               : afrag<NT>(Gp, R, t, ks, l);
+  };
+  auto fg = [&](int t, int ks) -> double {
+    return LDS ? sG[RP * RP + (4 * ks + l / 16) * RP + 16 * t + (l % 16)]
+               : afrag<NT>(G, R, t, ks, l);
+  };
   double ss[NT][4];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
@@ -513,6 +526,9 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
        tile < ntiles; tile += (int64_t)gridDim.x * (SV_THREADS / WAVE)) {
     const int64_t row = tile * 16 + (l % 16);
     const int64_t rc = row < I ? row : I - 1;
+    // G, G^+ fragments are read from LDS in every tile rather than held in
+    // registers
+    if (LDS) asm volatile("" ::: "memory");
     // B fragments of M^T: M[row][4 ks + l / 16]
     double mf[KS];
     bool nz = false;
@@ -533,8 +549,8 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
       ax[t] = double4_t{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const double a = REG ? gpf[t * KS + ks] : afrag<NT>(Gp, R, t, ks, l);
-        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, mf[ks], ax[t], 0, 0, 0);
+        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fp(t, ks), mf[ks], ax[t],
+                                                     0, 0, 0);
       }
     }
     // R^T = M^T - G X^T
@@ -544,9 +560,8 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
       double4_t ar = double4_t{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const double a = REG ? gf[t * KS + ks] : afrag<NT>(G, R, t, ks, l);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ax[ks / 4][ks % 4], ar,
-                                                  0, 0, 0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(fg(t, ks), ax[ks / 4][ks % 4],
+                                                  ar, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) rf[4 * t + v] = mf[4 * t + v] - ar[v];
@@ -556,8 +571,8 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const double a = REG ? gpf[t * KS + ks] : afrag<NT>(Gp, R, t, ks, l);
-        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rf[ks], ax[t], 0, 0, 0);
+        ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fp(t, ks), rf[ks], ax[t],
+                                                     0, 0, 0);
       }
     }
     if (row < I) {

@@ -69,7 +69,7 @@ __device__ __forceinline__ int packed_index(int a, int b, int R) {
 // MFMA (one wave per leaf, 16 x 16 tiles), keeps them in LDS and writes the
 // internal nodes of its LB-leaf subtree (one thread per packed entry,
 // pairwise sums in registers).  Upper levels: k_tree_up sums groups of up to
-// 8 sibling subtree roots, three levels per launch.
+// 16 sibling subtree roots, four levels per launch.
 // ---------------------------------------------------------------------------
 template <int LBMAX>
 __device__ __forceinline__ void sum_up(double (&x)[LBMAX], int n, double *tree,
@@ -935,8 +935,8 @@ void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
   // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1
   const int P = sts_packed(R);
   for (int64_t n = P2 >> lb; n > 1;) {
-    int gs = 0;
-    while (gs < 3 && (int64_t(2) << gs) <= n) ++gs;
+    int gs = 0;  // up to four levels (TB_LBMAX nodes) per launch
+    while ((2 << gs) <= TB_LBMAX && (int64_t(2) << gs) <= n) ++gs;
     const int G = 1 << gs;
     hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(n / G)), dim3(256), 0, s,
                        tree, n, G, P);
