@@ -321,7 +321,10 @@ __device__ __forceinline__ double lane_mass(const double (&ms)[4]) {
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
 k_sts_mass(const T *U, int64_t I, int R, const double *Gg, int gshift,
-           double *lev, double *sub, double *grp, uint32_t *err) {
+           double *lev, double *sub, double *grp, int32_t *topc, int ntopc,
+           uint32_t *err) {
+  if (blockIdx.x == 0)  // counters of the tree factors' top stages
+    for (int i = threadIdx.x; i < ntopc; i += ST) topc[i] = 0;
   constexpr int RP = 16 * NT, KS = 4 * NT, RS = tile_stride<NT>();
   static_assert(FIRST_SUB == 16 * (ST / WAVE), "one row tile per wave");
   __shared__ double sG[RP * RP];
@@ -543,6 +546,166 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
   out.v[g] = 1;
   out.t[g] = u * Z;
   out.m[g] = Z;
+}
+
+// Top of a tree factor (trees of at least 2 TOP_N leaves): instead of the
+// root and TOP_D levels, each sample takes a depth-TOP_D node directly by
+// inverse CDF over the TOP_N node masses <(h h^T) (*) G_{>k}, G^v> in node
+// order (their sum is the root mass Z; t = u Z).  16 samples per wave, one
+// MFMA tile per node, the TOP_N products G_{>k} (*) G^v packed in LDS.
+// Writes (node, t - mass before it, node mass) per sample in sample order,
+// counts per node (one atomic per block and node) and clears the placement
+// counters of the levels below.
+constexpr int TOP_D = 3, TOP_N = 1 << TOP_D;
+constexpr int TOP_ST = 512;  // 8 waves per block share the staged nodes
+
+template <int NT>
+__global__ void __launch_bounds__(TOP_ST)
+k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
+          const double *uni, int q, int nq, int64_t J, StsWork w,
+          SlotBuf out, int32_t *topc, uint32_t *err) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2, KS = 4 * NT;
+  __shared__ double sN[TOP_N * P];  // node Grams TOP_N .., packed
+  __shared__ double sG[RP * RP];    // G_{>k}, zeros beyond R
+  __shared__ double sH[TOP_ST / WAVE][16 * tile_stride<NT>()];
+  __shared__ int32_t scnt[TOP_N];
+  const int64_t g0 = (int64_t)blockIdx.x * TOP_ST + threadIdx.x;
+  for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * TOP_ST) {
+    w.lc[i] = 0;
+    w.rc[i] = 0;
+  }
+  if (threadIdx.x < TOP_N) scnt[threadIdx.x] = 0;
+  {  // nodes TOP_N .. 2 TOP_N - 1 are contiguous in the tree
+    const double *src = tree + (int64_t)TOP_N * P;
+    for (int e = threadIdx.x; e < TOP_N * P; e += TOP_ST) sN[e] = src[e];
+    for (int e = threadIdx.x; e < RP * RP; e += TOP_ST) {
+      const int a = e / RP, b = e % RP;
+      const bool in = a < R && b < R;
+      const double x = Gg[in ? a * R + b : 0];
+      sG[e] = in ? x : 0.0;
+    }
+  }
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (TOP_ST / WAVE) + threadIdx.x / WAVE) * 16;
+  const int64_t g = p0 + l;
+  const bool act = p0 < J && l < 16 && g < J;
+  if (p0 < J) {
+    const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
+    double xA[KS], xD[NT][4], mm[TOP_N];
+    load_hfrag_lds<NT>(w.h, s, sH[threadIdx.x / WAVE], xA, xD);
+#pragma unroll 1
+    for (int v = 0; v < TOP_N; ++v) {
+      const double *nv = sN + v * P;
+      double qB[NT][KS], ms[4];
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
+          const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
+          qB[tt][ks] = (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j] *
+                       nv[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
+        }
+      tile_mass<NT>(xA, xD, qB, ms);
+      const double x = lane_mass(ms);  // lanes 0..15: sample l
+#pragma unroll
+      for (int i = 0; i < TOP_N; ++i)
+        if (i == v) mm[i] = x;
+    }
+    double Z = 0.0;
+#pragma unroll
+    for (int i = 0; i < TOP_N; ++i) Z += mm[i] > 0 ? mm[i] : 0.0;
+    if (act) {
+      double u = uni[g * nq + q];
+      if (!(u >= 0.0 && u < 1.0)) {
+        atomicOr(err, ERR_UNIFORM);
+        u = 0.0;
+      }
+      if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
+      // first node with t < cumulative mass (t then relative to it); past
+      // the end (rounding): the last node of positive mass with t at its
+      // mass, so that the levels below end in its last row of positive mass
+      double t = u * Z, mv = 0.0, lastm = 0.0;
+      int pick = -1, lastpos = -1;
+#pragma unroll
+      for (int i = 0; i < TOP_N; ++i) {
+        const double x = mm[i];
+        if (pick < 0 && x > 0) {
+          lastpos = i;
+          lastm = x;
+          if (t < x) {
+            pick = i;
+            mv = x;
+          } else {
+            t -= x;
+          }
+        }
+      }
+      if (pick < 0) {
+        pick = lastpos < 0 ? 0 : lastpos;
+        mv = lastm;
+        t = mv;
+      }
+      out.s[g] = (int32_t)g;
+      out.v[g] = TOP_N + pick;
+      out.t[g] = t;
+      out.m[g] = mv;
+      atomicAdd(&scnt[pick], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < TOP_N && scnt[threadIdx.x])
+    atomicAdd(&topc[threadIdx.x], scnt[threadIdx.x]);
+}
+
+// Place the samples of the top stage in their node's slot range (nodes in
+// order, ranges contiguous); sets the ranges and left counts of the nodes
+// one level up so that the next level finds them as it does below a level.
+// A block places ST consecutive samples: per-node counts and ranks in LDS,
+// one atomic per block and node (issued together) for the block's base.
+__global__ void __launch_bounds__(ST)
+k_sts_top_place(int64_t J, StsWork w, SlotBuf in, SlotBuf out,
+                const int32_t *topc_cnt, int32_t *topc_fill) {
+  __shared__ int32_t start[TOP_N + 1], bcnt[TOP_N], bbase[TOP_N];
+  if (threadIdx.x == 0) {
+    int32_t a = 0;
+    for (int i = 0; i < TOP_N; ++i) {
+      start[i] = a;
+      a += topc_cnt[i];
+    }
+    start[TOP_N] = a;
+  }
+  if (threadIdx.x < TOP_N) bcnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < TOP_N / 2) {  // parents TOP_N/2 ..
+    const int p = TOP_N / 2 + threadIdx.x, i = 2 * threadIdx.x;
+    w.sbeg[p] = start[i];
+    w.send[p] = start[i + 2];
+    w.lc[cslot(p)] = start[i + 1] - start[i];
+  }
+  const int64_t g = (int64_t)blockIdx.x * ST + threadIdx.x;
+  const bool a = g < J;
+  int32_t s = 0, v = 0;
+  double t = 0.0, m = 0.0;
+  int32_t rank = 0;
+  if (a) {
+    s = in.s[g];
+    v = in.v[g];
+    t = in.t[g];
+    m = in.m[g];
+    rank = atomicAdd(&bcnt[v - TOP_N], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < TOP_N && bcnt[threadIdx.x])
+    bbase[threadIdx.x] = atomicAdd(&topc_fill[threadIdx.x], bcnt[threadIdx.x]);
+  __syncthreads();
+  if (a) {
+    const int32_t pos = start[v - TOP_N] + bbase[v - TOP_N] + rank;
+    out.s[pos] = s;
+    out.v[pos] = v;
+    out.t[pos] = t;
+    out.m[pos] = m;
+  }
 }
 
 // One level.  A block owns 64 consecutive slots; wave i takes slots
@@ -873,7 +1036,7 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
   double *grp = w.sub + first_nsub(I0);
   hipLaunchKernelGGL((k_sts_mass<T, NT>), dim3((unsigned)first_ngroups(I0)), b,
                      0, st, static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0],
-                     gs, w.lev, w.sub, grp, err);
+                     gs, w.lev, w.sub, grp, w.topc, STS_TOPC * nq, err);
   CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
                      static_cast<const T *>(ml.U[0]), I0, R, w.lev, w.sub, grp,
@@ -882,11 +1045,29 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
   for (int q = 1; q < nq; ++q) {
     const double *tree = ml.tree[q], *Gg = ml.Ggt[q];
     const int64_t P2 = ml.P2[q];
-    hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R, uni,
-                       q, nq, J, w, w.slot[0], err);
-    CPR_LAUNCH_CHECK();
     int cur = 0;
-    for (int64_t n = 1; n < P2; n <<= 1) {
+    int64_t n0 = 1;
+    bool top = false;
+    if constexpr (NT <= 3) {  // the packed node products fit LDS
+      if (P2 >= 2 * TOP_N) {  // top stage: nodes TOP_N .. 2 TOP_N - 1
+        int32_t *tc = w.topc + STS_TOPC * q;
+        hipLaunchKernelGGL((k_sts_top<NT>), dim3(ceil_div(J, 16 * (TOP_ST / WAVE))),
+                           dim3(TOP_ST), 0, st, tree, Gg, P2, R, uni, q, nq, J,
+                           w, w.slot[1], tc, err);
+        CPR_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sts_top_place, g, b, 0, st, J, w, w.slot[1],
+                           w.slot[0], tc, tc + TOP_N);
+        CPR_LAUNCH_CHECK();
+        n0 = TOP_N;
+        top = true;
+      }
+    }
+    if (!top) {
+      hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R, uni,
+                         q, nq, J, w, w.slot[0], err);
+      CPR_LAUNCH_CHECK();
+    }
+    for (int64_t n = n0; n < P2; n <<= 1) {
       hipLaunchKernelGGL((k_sts_level<NT>), gl, b, 0, st, tree, Gg, R, J, w,
                          w.slot[cur], w.slot[cur ^ 1]);
       CPR_LAUNCH_CHECK();
