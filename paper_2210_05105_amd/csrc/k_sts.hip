@@ -181,6 +181,7 @@ k_tree_up(double *tree, int64_t first, int G, int P) {
 // v_mfma_f64_16x16x4f64 (lane l, k-step ks, 16-column tile t):
 //   A: A[l % 16][4 ks + l / 16]      B: Q[4 ks + l / 16][16 t + l % 16]
 //   D: element v of lane l holds D[l / 16 + 4 v][16 t + l % 16]
+// (tile_mass_t forms the product transposed, see there).
 // ---------------------------------------------------------------------------
 constexpr int ST = 256;
 
@@ -196,9 +197,9 @@ __device__ __forceinline__ void stage_pad(double *dst, const double *A, int R) {
   }
 }
 
-// B fragments of a zero-padded symmetric RP x RP matrix held in LDS, for
-// tile_mass: block (k-tile, tile t) is used only for k-tile <= t, the blocks
-// below the diagonal doubled
+// Fragments of a zero-padded symmetric RP x RP matrix held in LDS, for
+// tile_mass_t: block (tile t, k-tile) is used only for k-tile <= t, the
+// blocks off the diagonal doubled
 template <int NT>
 __device__ __forceinline__ void lds_bfrag(const double *sA,
                                           double (&f)[NT][4 * NT]) {
@@ -212,53 +213,35 @@ __device__ __forceinline__ void lds_bfrag(const double *sA,
                  sA[(4 * ks + l / 16) * RP + 16 * t + (l % 16)];
 }
 
-// Masses x_i^T Q x_i of 16 rows for a symmetric Q: with X_t the 16-column
-// tiles of X and Q_{ut} the blocks of Q,
-//   x^T Q x = sum_t x_t^T (Q_tt x_t + 2 sum_{u<t} Q_ut^T x_u),
-// so tile t needs D_t = X_t Q_tt + 2 sum_{u<t} X_u Q_ut (k-tiles u <= t) and
-// the row-dot of D_t with X_t: NT (NT + 1) / 2 blocks of 4 MFMA k-steps
-// instead of NT^2.  Lanes of group l / 16 get row l / 16 + 4 v in ms[v].
+// Masses x_i^T Q x_i of the 16 rows of X for a symmetric Q.  With X_t the
+// 16-column tiles of X and Q_tu the blocks of Q,
+//   x^T Q x = sum_t x_t^T (Q_tt x_t + 2 sum_{u<t} Q_tu x_u),
+// so tile t needs (X Q')_t^T = sum_{u<=t} c_tu Q_tu X_u^T (c = 2 off the
+// diagonal): NT (NT + 1) / 2 blocks of 4 MFMA k-steps instead of NT^2.  The
+// product is formed transposed (A = Q fragments, which for symmetric Q are
+// the B-layout values of lds_bfrag; B = X^T, which are the A-layout values
+// xA of X): lane l, element v of tile t then holds (X Q')[l % 16][16 t +
+// l / 16 + 4 v], whose matching X entry is the lane's own xA[4 t + v].  The
+// row-dot is a local sum over the lane's 4 NT products and two shuffles
+// over the four lanes of one row.  Every lane returns the mass of row
+// l % 16.
 template <int NT>
-__device__ __forceinline__ void tile_mass(const double (&xA)[4 * NT],
-                                          const double (&xD)[NT][4],
-                                          const double (&qB)[NT][4 * NT],
-                                          double (&ms)[4]) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v) ms[v] = 0.0;
+__device__ __forceinline__ double tile_mass_t(const double (&xA)[4 * NT],
+                                              const double (&qB)[NT][4 * NT]) {
+  double s = 0.0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     double4_t acc = double4_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < 4 * (t + 1); ++ks)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xA[ks], qB[t][ks], acc, 0, 0,
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qB[t][ks], xA[ks], acc, 0, 0,
                                                  0);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ms[v] = fma(acc[v], xD[t][v], ms[v]);
+    for (int v = 0; v < 4; ++v) s = fma(acc[v], xA[4 * t + v], s);
   }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    for (int o = 1; o < 16; o <<= 1) ms[v] += __shfl_xor(ms[v], o, WAVE);
-}
-
-// A and D-layout fragments of the h rows of the 16 samples held by lanes
-// 16 tau .. 16 tau + 15 (rows of stride 16 NT, zeros beyond R)
-template <int NT>
-__device__ __forceinline__ void load_hfrag(const double *hb, int32_t s,
-                                           int tau, double (&xA)[4 * NT],
-                                           double (&xD)[NT][4]) {
-  constexpr int RP = 16 * NT;
-  const int l = lane_id();
-  const int32_t sa = __shfl(s, 16 * tau + (l % 16), WAVE);
-#pragma unroll
-  for (int ks = 0; ks < 4 * NT; ++ks)
-    xA[ks] = hb[(int64_t)sa * RP + 4 * ks + l / 16];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int32_t sd = __shfl(s, 16 * tau + l / 16 + 4 * v, WAVE);
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      xD[t][v] = hb[(int64_t)sd * RP + 16 * t + (l % 16)];
-  }
+  s += __shfl_xor(s, 16, WAVE);
+  s += __shfl_xor(s, 32, WAVE);
+  return s;
 }
 
 // Order one wave's LDS writes before its reads of other lanes' data.
@@ -300,13 +283,6 @@ __device__ __forceinline__ void load_hfrag_lds(const double *hb, int32_t s,
     for (int t = 0; t < NT; ++t) xD[t][v] = buf[(l / 16 + 4 * v) * RS + 16 * t + (l % 16)];
 }
 
-// mass of the tile row held by this lane (lane 16 tau + i gets row i)
-__device__ __forceinline__ double lane_mass(const double (&ms)[4]) {
-  const int l = lane_id(), src = (l & 3) * 16, vv = (l >> 2) & 3;
-  const double x0 = __shfl(ms[0], src, WAVE), x1 = __shfl(ms[1], src, WAVE);
-  const double x2 = __shfl(ms[2], src, WAVE), x3 = __shfl(ms[3], src, WAVE);
-  return vv == 0 ? x0 : vv == 1 ? x1 : vv == 2 ? x2 : x3;
-}
 
 // First factor (h = 1): every sample shares one conditional law, the row
 // masses U[i] G_{>k} U[i]^T; index = min{i : uZ < F(i)} with F their
@@ -356,17 +332,11 @@ k_sts_mass(const T *U, int64_t I, int R, const double *Gg, int gshift,
     }
     wave_lds_sync();
     asm volatile("" ::: "memory");
-    double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
+    double gB[NT][KS], xA[KS];
     lds_bfrag<NT>(sG, gB);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int tt = 0; tt < NT; ++tt)
-        xD[tt][v] = buf[(l / 16 + 4 * v) * RS + 16 * tt + (l % 16)];
-    tile_mass<NT>(xA, xD, gB, ms);
-    double m = lane_mass(ms);  // lanes 0..15: row row0 + l
+    double m = tile_mass_t<NT>(xA, gB);  // lanes 0..15: row row0 + l
     const int64_t r = row0 + l;
     if (l < 16 && r < I && !isfinite(m)) atomicOr(err, ERR_NONFINITE);
     m = (l < 16 && r < I && m > 0) ? m : 0.0;
@@ -530,11 +500,10 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
   const int64_t g = p0 + l;
   const bool act = l < 16 && g < J;
   const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
-  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
+  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4];
   lds_bfrag<NT>(sQ, qB);
   load_hfrag_lds<NT>(w.h, s, sH[threadIdx.x / WAVE], xA, xD);
-  tile_mass<NT>(xA, xD, qB, ms);
-  const double Z = lane_mass(ms);
+  const double Z = tile_mass_t<NT>(xA, qB);
   if (!act) return;
   double u = uni[g * nq + q];
   if (!(u >= 0.0 && u < 1.0)) {
@@ -597,7 +566,7 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
 #pragma unroll 1
     for (int v = 0; v < TOP_N; ++v) {
       const double *nv = sN + v * P;
-      double qB[NT][KS], ms[4];
+      double qB[NT][KS];
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -606,8 +575,7 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
           qB[tt][ks] = (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j] *
                        nv[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
         }
-      tile_mass<NT>(xA, xD, qB, ms);
-      const double x = lane_mass(ms);  // lanes 0..15: sample l
+      const double x = tile_mass_t<NT>(xA, qB);  // lanes 0..15: sample l
 #pragma unroll
       for (int i = 0; i < TOP_N; ++i)
         if (i == v) mm[i] = x;
@@ -745,7 +713,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   const uint64_t actm = __ballot(act);
   const int ld0 = actm ? __ffsll((long long)actm) - 1 : 0;
   int32_t v0 = __shfl(v, ld0, WAVE);
-  double nv[NT][4 * NT];  // node blocks used by tile_mass (k-tile <= tile)
+  double nv[NT][4 * NT];  // node blocks used by tile_mass_t (k-tile <= tile)
   auto load_node = [&](int32_t vn) {
     const double *nd = tree + (int64_t)(2 * vn) * P;
 #pragma unroll
@@ -771,7 +739,6 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
     // nv becomes the B fragments of G_{>k} (*) node in place; G_{>k} is
     // read from LDS again in every pass rather than held in registers
     asm volatile("" ::: "memory");
-    double ms[4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
@@ -779,8 +746,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
         const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
         nv[tt][ks] *= (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j];
       }
-    tile_mass<NT>(xA, xD, nv, ms);
-    const double x = lane_mass(ms);
+    const double x = tile_mass_t<NT>(xA, nv);
     if ((grp >> l) & 1ull) mL = x;
     rem &= ~grp;
     if (rem) {
@@ -856,7 +822,8 @@ constexpr int leaf_pb() {  // rows per batch (F is a multiple)
 }
 
 template <typename T, int NT, bool VEC>
-__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(ST)
+__attribute__((amdgpu_waves_per_eu(VEC ? 4 : 2)))
 k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
            int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
            uint32_t *err) {
@@ -947,19 +914,12 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
       // G_{>k} fragments are read from LDS again in every pass rather than
       // held in registers
       asm volatile("" ::: "memory");
-      double gB[NT][KS], xA[KS], xD[NT][4], ms[4];
+      double gB[NT][KS], xA[KS];
       lds_bfrag<NT>(sG, gB);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
         xA[ks] = (double)sp[(l % 16) * RSU + 4 * ks + l / 16] * hA[ks];
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int tt = 0; tt < NT; ++tt)
-          xD[tt][v] = (double)sp[(l / 16 + 4 * v) * RSU + 16 * tt + (l % 16)] *
-                      hD[tt][v];
-      tile_mass<NT>(xA, xD, gB, ms);
-      const double m = lane_mass(ms);  // lanes 0..15: row r of slot l
+      const double m = tile_mass_t<NT>(xA, gB);  // lanes 0..15: row r of slot l
       if (pick < 0 && row0 + r < I && m > 0) {
         pre += m;
         lastpos = r;
@@ -1006,11 +966,10 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
   if (p0 >= J) return;
   const int n = J - p0 < 16 ? (int)(J - p0) : 16;
   const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
-  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4], ms[4];
+  double qB[NT][4 * NT], xA[4 * NT], xD[NT][4];
   lds_bfrag<NT>(sP, qB);
   load_hfrag_lds<NT>(hbuf, s, sH[threadIdx.x / WAVE], xA, xD);
-  tile_mass<NT>(xA, xD, qB, ms);
-  const double mass = lane_mass(ms);
+  const double mass = tile_mass_t<NT>(xA, qB);
   if (l < n) prob[p0 + l] = mass / *trace;
   // the 16 rows of h in the path precision, coalesced
   const int ne = n * R;
