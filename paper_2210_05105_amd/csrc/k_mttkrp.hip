@@ -817,9 +817,10 @@ void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
 }
 
 int bucket_shift(int R, int tsize) {
-  // B rows of M per bucket: 256, or fewer so that the B x R block fits
-  // 32 KiB of LDS beside the sorted slice
-  int bb = 8;
+  // B rows of M per bucket: 128 (measured best at R = 32: larger buckets
+  // split into more slices that k_bk_combine must add, smaller ones take
+  // more scatter atomics), fewer when a B x R block exceeds 32 KiB
+  int bb = 7;
   while (bb > 0 && ((1 << bb) * R * tsize) > 32768) --bb;
   return bb;
 }
