@@ -215,6 +215,11 @@ void check_factors(cp_ctx *c) {
     require(c->factor_set[k], CP_ESTATE, "cp_set_factor not called for every mode");
 }
 
+// The factors != j are drawn in ascending mode order and the first one
+// (h = 1) needs no tree: mode 0 is never drawn from a tree, mode 1 only when
+// some j >= 2 exists.
+bool sts_tree_factor(int N, int k) { return k >= 2 || (k == 1 && N >= 3); }
+
 template <typename T>
 void rebuild_sampler(cp_ctx *c, int k) {
   PhaseScope ps(c, PH_SAMPLER_BUILD);
@@ -228,7 +233,7 @@ void rebuild_sampler(cp_ctx *c, int k) {
                   c->d_err, c->s);
     arls_build<T>(U, c->dims[k], c->R, c->Gp1, c->lev[k], c->cdf[k], c->Zd[k],
                   c->last[k], c->tmp, c->d_err, c->s);
-  } else if (c->sampler == CP_SAMPLER_STS) {
+  } else if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, k)) {
     sts_build<T>(U, c->dims[k], c->R, c->F, c->P2[k], c->tree[k], c->s);
   }
 }

@@ -440,7 +440,8 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
     if (!jacobi_pinv(A, R, scratch, Gp, red, rot) && t == 0)
       atomicOr(err, ERR_PINV);
   }
-  __threadfence();
+  // G^+ (global) was written by other threads of this workgroup
+  __threadfence_block();
   __syncthreads();
   // G^+ in LDS beside G when both fit (the one-wave inverse put it there)
   const double *gps = Gp;

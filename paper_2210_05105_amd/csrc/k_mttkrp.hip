@@ -261,10 +261,14 @@ constexpr int BK_ITEMS = BK_TILE / MT_THREADS;
 constexpr int BK_LDS_MAX = 4096;  // buckets histogrammed in LDS
 constexpr int BK_SLICE = 4096;    // records per accumulation workgroup
 
-// tile_first[t] = the distinct column holding position t BK_TILE
+// tile_first[t] = the distinct column holding position t BK_TILE; also
+// clears the n_zero bucket fill cursors
 __global__ void k_tile_first(const int64_t *counts, const int64_t *uq_off,
-                             int64_t *tile_first) {
+                             int64_t *tile_first, int64_t *zero,
+                             int64_t n_zero) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = u; i < n_zero; i += (int64_t)gridDim.x * blockDim.x)
+    zero[i] = 0;
   if (u >= counts[0]) return;
   const int64_t a = uq_off[u], b = uq_off[u + 1];
   for (int64_t t = (a + BK_TILE - 1) / BK_TILE; t * BK_TILE < b; ++t)
@@ -837,9 +841,9 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   int64_t *bk_fill = w.bk, *bk_end = w.bk + (nbk + 1),
           *item_start = w.bk + 2 * (nbk + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
-  zero_fill<int64_t>(bk_fill, nbk + 1, s);  // fill cursors
   hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
-                     w.counts, w.uq_off, w.tile_first);
+                     w.counts, w.uq_off, w.tile_first, bk_fill,
+                     (int64_t)nbk + 1);
   const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
