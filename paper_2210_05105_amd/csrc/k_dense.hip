@@ -229,41 +229,54 @@ __device__ bool chol_inverse(double *A, int R, double tol, double *W,
 // without row exchanges, in one wave: lane c < R holds column c of A and
 // lane R + c column c of the identity, R values each in registers.  Step k
 // scales row k by 1 / pivot and removes column k from every other row; the
-// multipliers (column k) come from lane k.  The pivots are those of the
-// LDL^T factorisation, all above tol for a clearly positive definite A;
-// the first one at or below tol stops it (returns false, Gp untouched).
+// multipliers (column k) are written to LDS by lane k and read back by all
+// lanes as broadcast loads.  The pivots are those of the LDL^T
+// factorisation, all above tol for a clearly positive definite A; the
+// first one at or below tol stops it (returns false, Gp untouched).
 // Afterwards lane R + c holds column c of A^{-1}, written to Gp (global)
-// and sGp (LDS).
-__device__ __forceinline__ double readlane_f64(double x, int k) {
-  const uint64_t b = (uint64_t)__double_as_longlong(x);
-  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, k);
-  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+// and sGp (LDS).  col: 32 doubles of LDS.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ bool gj_inverse_wave(const double *A, int R,
                                                 double tol, double *Gp,
-                                                double *sGp) {
+                                                double *sGp, double *col) {
   const int l = lane_id();
   double c[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i)
     c[i] = i >= R ? 0.0 : l < R ? A[i * R + l] : (l - R == i ? 1.0 : 0.0);
   // rows i >= R stay zero: their multipliers are zero
+  double2 *col2 = reinterpret_cast<double2 *>(col);
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < 32; ++k) {
     if (k < R && ok) {
-      const double piv = readlane_f64(c[k], k);
+      if (l == k)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) col2[i] = double2{c[2 * i], c[2 * i + 1]};
+      wave_lds_fence();
+      double m[32];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const double2 x = col2[i];
+        m[2 * i] = x.x;
+        m[2 * i + 1] = x.y;
+      }
+      const double piv = m[k];
       if (piv > tol) {
         const double r = c[k] / piv;
 #pragma unroll
         for (int i = 0; i < 32; ++i)
-          if (i != k) c[i] = fma(-readlane_f64(c[i], k), r, c[i]);
+          if (i != k) c[i] = fma(-m[i], r, c[i]);
         c[k] = r;
       } else {
         ok = false;
       }
+      wave_lds_fence();  // every lane has read col before the next write
     }
   }
   if (!ok) return false;
@@ -369,6 +382,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
                 double *trace_out, double *scratch, uint32_t *err) {
   extern __shared__ double A[];  // R x R
   __shared__ double red[PV_THREADS / WAVE];
+  __shared__ __align__(16) double gjcol[32];  // pivot column of the one-wave inverse
   __shared__ double rot[4 * (MAXR / 2 + 1)];
   __shared__ int flag;
   const int t = threadIdx.x;
@@ -424,7 +438,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   bool ok;
   if (R <= 32) {
     if (t < WAVE) {
-      const bool g = gj_inverse_wave(A, R, tol, Gp, A + RR);
+      const bool g = gj_inverse_wave(A, R, tol, Gp, A + RR, gjcol);
       if (t == 0) flag = g ? 1 : 0;
     }
     __threadfence_block();
