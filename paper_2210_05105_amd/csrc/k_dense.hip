@@ -49,11 +49,23 @@ k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
   for (int64_t c0 = r0; c0 < r1; c0 += GR_ROWS) {
     const int nrow = (int)std::min<int64_t>(GR_ROWS, r1 - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < GR_ROWS * Rp; e += GR_THREADS) {
-      int rr = e / Rp, cc = e - rr * Rp;
-      double v = 0;
-      if (rr < nrow && cc < R) v = (double)U[(c0 + rr) * R + cc];
-      lds[e] = v;
+    // 8 clamped loads in flight per thread, masked when stored
+    constexpr int PE = 8;
+    for (int e0 = 0; e0 < GR_ROWS * Rp; e0 += PE * GR_THREADS) {
+      double v[PE];
+#pragma unroll
+      for (int q = 0; q < PE; ++q) {
+        const int e = e0 + q * GR_THREADS + threadIdx.x;
+        const int rr = e / Rp, cc = e - rr * Rp;
+        const int rc = rr < nrow ? rr : nrow - 1, ccc = cc < R ? cc : R - 1;
+        v[q] = (double)U[(c0 + rc) * R + ccc];
+      }
+#pragma unroll
+      for (int q = 0; q < PE; ++q) {
+        const int e = e0 + q * GR_THREADS + threadIdx.x;
+        const int rr = e / Rp, cc = e - rr * Rp;
+        if (e < GR_ROWS * Rp) lds[e] = (rr < nrow && cc < R) ? v[q] : 0.0;
+      }
     }
     __syncthreads();
     for (int k0 = 0; k0 < GR_ROWS; k0 += 4) {

@@ -374,11 +374,22 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
   const int ng = (int)((nsub + (int64_t(1) << gshift) - 1) >> gshift);
   const int per = (ng + ST - 1) / ST;
   const int k0 = threadIdx.x * per, k1 = k0 + per < ng ? k0 + per : ng;
+  // this thread's uniform, issued before the scan
+  const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
+  const bool act = s < J;
+  double u = uni[(act ? s : J - 1) * nq];
+  // the run's group sums, loaded together (clamped, then masked)
+  constexpr int GPT = FIRST_GROUPS / ST;
+  double gv[GPT];
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) gv[j] = grp[k0 + j < ng ? k0 + j : ng - 1];
   double run = 0.0;
-  for (int k = k0; k < k1; ++k) {
-    run += grp[k];
-    gc[k] = run;
-  }
+#pragma unroll
+  for (int j = 0; j < GPT; ++j)
+    if (k0 + j < k1) {
+      run += gv[j];
+      gc[k0 + j] = run;
+    }
   double x = run;  // inclusive scan of the run totals within the wave
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
@@ -392,12 +403,9 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
   for (int k = k0; k < k1; ++k) gc[k] += off;
   __syncthreads();
   const double Z = gc[ng - 1];
-  const int64_t s = (int64_t)blockIdx.x * ST + threadIdx.x;
   const int64_t sw0 = s - l;  // first sample of the wave
   if (sw0 >= J) return;
   // lanes past J draw for sample J - 1 and store nothing
-  const bool act = s < J;
-  double u = uni[(act ? s : J - 1) * nq];
   if (!(u >= 0.0 && u < 1.0)) {
     if (act) atomicOr(err, ERR_UNIFORM);
     u = 0.0;
