@@ -232,8 +232,12 @@ def main():
                          dtype=np.float64 if precision == "fp64" else np.float32)
     for k in range(N):
         ctx.set_factor(k, torch.from_numpy(U0[k]))
+    # after the timed sweeps, a short pass with events on every phase gives
+    # the breakdown (events cost the stream a few microseconds each, so the
+    # timed sweeps record them only around the two phases the line reports)
+    extra = 0 if a.no_profile else min(a.steps, 5)
     uni = torch.from_numpy(
-        tg.uniform_blocks(runi, a.warmup + a.steps, J, N)).to(dev)
+        tg.uniform_blocks(runi, a.warmup + a.steps + extra, J, N)).to(dev)
     torch.cuda.synchronize()
     per = J * N * (N - 1)
     if a.warmup:
@@ -241,17 +245,24 @@ def main():
     ctx.sync()
     ctx.counters(reset=True)
     if not a.no_profile:
-        ctx.profile(True)
+        ctx.profile(True, phases=["sample", "mttkrp"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.sweep(a.steps, J, uni[a.warmup:a.warmup + a.steps])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.sync()
-    ph = ctx.profile_read() if not a.no_profile else {}
+    ph_timed = ctx.profile_read() if not a.no_profile else {}
     ctx.profile(False)
     cnt = ctx.counters()
     fit = ctx.fit()
+    ph = {}
+    if extra:
+        ctx.profile(True)
+        ctx.sweep(extra, J, uni[a.warmup + a.steps:])
+        ctx.sync()
+        ph = ctx.profile_read()
+        ctx.profile(False)
     log(f"timed {a.steps} sweeps in {dt:.4f}s; fit {fit:.6f}; counters {cnt}")
     sweeps_per_s = a.steps / dt
 
@@ -263,8 +274,13 @@ def main():
     phases = {k: dict(ms_total=v[0], launches=v[1]) for k, v in ph.items()}
     roof = None
     mttkrp = None
+
+    def per_launch(k):  # from the timed sweeps when they timed phase k
+        src = ph_timed if ph_timed.get(k, (0, 0))[1] else ph
+        return src[k][0] / max(src[k][1], 1)
+
     if ph:
-        ms_mtt = ph["mttkrp"][0] / max(ph["mttkrp"][1], 1)
+        ms_mtt = per_launch("mttkrp")
         mtt_gbs = mtt_bytes / (ms_mtt * 1e-3) / 1e9
         mttkrp = dict(algorithmic_bytes_per_launch=mtt_bytes,
                       ms_per_launch=ms_mtt, achieved_GBs=mtt_gbs,
@@ -273,7 +289,7 @@ def main():
                       distinct_columns_per_solve=cnt["unique"] / solves,
                       rows_out_per_solve=cnt["rows"] / solves)
         dom = max(ph, key=lambda k: ph[k][0])
-        ms_dom = ph[dom][0] / max(ph[dom][1], 1)
+        ms_dom = per_launch(dom)
         if dom == "sample" and sampler == "sts":
             F = a.leaf or 16
             fl = np.mean([sts_flops_per_solve(T.dims, j, R, J, F)
@@ -313,6 +329,7 @@ def main():
                    "sts_leaf": a.leaf or 16, "parallelism": "single-gpu"},
         "fit": fit, "init_s": t_init,
         "sampled_mttkrp": mttkrp, "phases": phases,
+        "phases_sweeps": extra,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

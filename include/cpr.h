@@ -215,6 +215,13 @@ cp_status cp_get_extracted(cp_ctx *ctx, uint64_t *col_key, int32_t *row,
  */
 #define CP_NPHASE 8
 cp_status cp_profile(cp_ctx *ctx, int32_t enable);
+/*
+ * cp_profile_phases - as cp_profile(ctx, 1), but events are recorded only
+ * around the phases whose bit is set in mask (bit p = phase p); each event
+ * pair costs the stream a few microseconds, so a timed run can restrict
+ * them to the phases it reports.  mask 0 stops accumulation.
+ */
+cp_status cp_profile_phases(cp_ctx *ctx, uint32_t mask);
 cp_status cp_profile_read(cp_ctx *ctx, double *ms, int64_t *launches);
 const char *cp_phase_name(int32_t phase);
 

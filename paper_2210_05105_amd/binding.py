@@ -82,6 +82,7 @@ def load_library(path=LIB_PATH):
         "cp_get_unique": [P, P, P, P, P, I64, C.POINTER(I64)],
         "cp_get_extracted": [P, P, P, P, I64, C.POINTER(I64)],
         "cp_profile": [P, I32],
+        "cp_profile_phases": [P, C.c_uint32],
         "cp_profile_read": [P, P, P],
         "cp_index_stats": [P, I32, C.POINTER(I64), C.POINTER(I64)],
         "cp_counters": [P, P, I32],
@@ -278,8 +279,15 @@ class Context:
         k = min(n.value, cap)
         return dict(col_key=ck[:k], row=row[:k], rep=rep[:k], n=n.value)
 
-    def profile(self, enable=True):
-        self._check(self.lib.cp_profile(self._h, int(bool(enable))))
+    def profile(self, enable=True, phases=None):
+        """Per-phase HIP-event timing; phases: names to time (default all)."""
+        if phases is None or not enable:
+            self._check(self.lib.cp_profile(self._h, int(bool(enable))))
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << PHASES.index(name)
+            self._check(self.lib.cp_profile_phases(self._h, mask))
 
     def profile_read(self):
         ms = (C.c_double * 8)()

@@ -59,6 +59,7 @@ struct cp_ctx {
   int64_t cur_J = 0;
   bool factor_set[MAXN] = {};
   bool prof = false;
+  uint32_t prof_mask = 0;  // phases whose events are recorded
   std::vector<ProfEv> evs;
   size_t ev_used = 0;
   std::vector<void *> allocs;
@@ -103,7 +104,7 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 class PhaseScope {
  public:
   PhaseScope(cp_ctx *c, int ph) : c_(c) {
-    if (!c_->prof) return;
+    if (!c_->prof || !((c_->prof_mask >> ph) & 1u)) return;
     if (c_->ev_used == c_->evs.size()) {
       ProfEv e{ph, nullptr, nullptr};
       hip_ok(hipEventCreate(&e.a), "hipEventCreate");
@@ -796,10 +797,15 @@ cp_status cp_get_extracted(cp_ctx *c, uint64_t *col_key, int32_t *row,
 }
 
 cp_status cp_profile(cp_ctx *c, int32_t enable) {
+  return cp_profile_phases(c, enable ? (1u << CP_NPHASE) - 1 : 0u);
+}
+
+cp_status cp_profile_phases(cp_ctx *c, uint32_t mask) {
   if (!c || !c->N) return CP_EINVAL;
   return guard(c, [&] {
-    if (enable) c->ev_used = 0;
-    c->prof = enable != 0;
+    if (mask) c->ev_used = 0;
+    c->prof = mask != 0;
+    c->prof_mask = mask;
   });
 }
 
