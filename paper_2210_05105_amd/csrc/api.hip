@@ -484,6 +484,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.scan_tmp, std::max(scan_temp_bytes(J),
                                      scan_temp_bytes(nbk + 1)));
   dalloc(c, &c->w.bk, (size_t)5 * (nbk + 1) * 8);
+  c->w.bk_max = nbk;
   int64_t cap = 1;
   if (c->sampler != CP_SAMPLER_EXACT) {
     for (int k = 0; k < N; ++k) {
@@ -516,6 +517,9 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
                      c->w.bk, c->w.scan_tmp, c->s);
     }
   }
+  // bucket fill cursors start at zero; the accumulation plan clears them
+  // again after every sampled MTTKRP
+  zero_fill<int64_t>(c->w.bk, (size_t)5 * (nbk + 1), c->s);
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);
   dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);

@@ -179,7 +179,9 @@ struct SampleWork {
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
   int64_t *scratch;  // 4 J: first-draw flags, lengths, per-block totals
   void *scan_tmp;    // scan_temp_bytes(max(J, buckets + 1))
-  int64_t *bk;       // 5 (buckets + 1): bucket fill counts, ends, slices
+  int64_t *bk;       // 5 (bk_max + 1): fill cursors, ends, slice starts at
+                     // fixed offsets 0, bk_max + 1, 2 (bk_max + 1)
+  int64_t bk_max;    // buckets of the largest mode
   void *rec;         // nnz records: extracted nonzeros in bucket regions
   int64_t rec_cap;
   void *part;        // per-slice blocks of split buckets (B x R each)

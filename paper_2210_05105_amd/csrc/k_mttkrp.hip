@@ -23,6 +23,7 @@ namespace cpr {
 namespace {
 
 constexpr int LK_THREADS = 256;
+constexpr int BK_TILE = 4096;  // positions per scatter tile
 
 template <typename T>
 __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
@@ -180,7 +181,7 @@ k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
           const int64_t *col_ptr, const T *h, int R, int32_t *owner,
           int32_t *dupcnt, int32_t *uq_s, int32_t *uq_cid, int32_t *uq_cnt,
           double *uq_w, int64_t *uq_off, int64_t *uq_base, T *hc,
-          int64_t *counts, int64_t *stats) {
+          int64_t *tile_first, int64_t *counts, int64_t *stats) {
   // offsets of this block: totals of the blocks before it
   int64_t bu = 0, bo = 0;
   for (int k = threadIdx.x; k < (int)blockIdx.x; k += LK_THREADS) {
@@ -214,6 +215,11 @@ k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
       uq_off[u] = off;
       uq_base[u] = col_ptr[cid] - off;  // index position = uq_base + e
       owner[cid] = INT_MAX;
+      // tile_first[t] = the distinct column holding extracted position
+      // t BK_TILE
+      for (int64_t tt = (off + BK_TILE - 1) / BK_TILE; tt * BK_TILE < off + ln;
+           ++tt)
+        tile_first[tt] = u;
       const T *hs = h + s * R;
       T *hu = hc + u * R;
       for (int c0 = 0; c0 < R; c0 += 16) {  // 16 loads in flight
@@ -256,24 +262,9 @@ k_compact(int64_t J, int64_t chunk, const double *prob, const int32_t *col_id,
 // concatenated sampled-column ranges is resolved to (distinct column,
 // position in the mode's index) by a binary search over uq_off.
 constexpr int MT_THREADS = 256;
-constexpr int BK_TILE = 4096;     // positions per count/scatter tile
 constexpr int BK_ITEMS = BK_TILE / MT_THREADS;
 constexpr int BK_LDS_MAX = 4096;  // buckets histogrammed in LDS
 constexpr int BK_SLICE = 4096;    // records per accumulation workgroup
-
-// tile_first[t] = the distinct column holding position t BK_TILE; also
-// clears the n_zero bucket fill cursors
-__global__ void k_tile_first(const int64_t *counts, const int64_t *uq_off,
-                             int64_t *tile_first, int64_t *zero,
-                             int64_t n_zero) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = u; i < n_zero; i += (int64_t)gridDim.x * blockDim.x)
-    zero[i] = 0;
-  if (u >= counts[0]) return;
-  const int64_t a = uq_off[u], b = uq_off[u + 1];
-  for (int64_t t = (a + BK_TILE - 1) / BK_TILE; t * BK_TILE < b; ++t)
-    tile_first[t] = u;
-}
 
 // The distinct columns overlapping tile [e0, e1): [ub, ue).  Their start
 // positions relative to e0 go to LDS (cst); a position's column is then a
@@ -327,7 +318,7 @@ __device__ __forceinline__ void bucket_runs(int bk, bool valid, int &leader,
 // row of M.  Thread t takes a contiguous run of buckets.
 constexpr int PL_THREADS = 1024;
 __global__ void __launch_bounds__(PL_THREADS)
-k_bk_plan(const int64_t *bk_start, const int64_t *bk_fill, int nbk,
+k_bk_plan(const int64_t *bk_start, int64_t *bk_fill, int nbk,
           int64_t *bk_end, int64_t *item_start, int32_t *item_bk) {
   __shared__ int64_t wb[PL_THREADS / WAVE];
   const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
@@ -357,6 +348,8 @@ k_bk_plan(const int64_t *bk_start, const int64_t *bk_fill, int nbk,
     for (int64_t i = 0; i < ni; ++i) item_bk[ob + i] = b;
     ob += ni;
   }
+  __syncthreads();  // every fill cursor read: clear them for the next call
+  for (int b = b0; b < b1; ++b) bk_fill[b] = 0;
 }
 
 // Fixed record regions of the output-row buckets of one mode (built once):
@@ -810,13 +803,15 @@ void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                        chunk, prob, w.col_id, first, len, part, col_ptr,
                        static_cast<const float *>(h), R, w.owner, w.dupcnt,
                        w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off, w.uq_base,
-                       static_cast<float *>(w.hc), w.counts, w.stats);
+                       static_cast<float *>(w.hc), w.tile_first, w.counts,
+                       w.stats);
   else
     hipLaunchKernelGGL((k_compact<double>), dim3(nb), dim3(LK_THREADS), 0, s, J,
                        chunk, prob, w.col_id, first, len, part, col_ptr,
                        static_cast<const double *>(h), R, w.owner, w.dupcnt,
                        w.uq_s, w.uq_cid, w.uq_cnt, w.uq_w, w.uq_off, w.uq_base,
-                       static_cast<double *>(w.hc), w.counts, w.stats);
+                       static_cast<double *>(w.hc), w.tile_first, w.counts,
+                       w.stats);
   CPR_LAUNCH_CHECK();
 }
 
@@ -838,12 +833,11 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   const T *hc = static_cast<const T *>(w.hc);
   const int bb = bucket_shift(R, (int)sizeof(T));
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
-  int64_t *bk_fill = w.bk, *bk_end = w.bk + (nbk + 1),
-          *item_start = w.bk + 2 * (nbk + 1);
+  // fixed offsets: the fill cursors of every mode stay zero between calls
+  // (each plan clears the ones it read), whatever the mode's bucket count
+  int64_t *bk_fill = w.bk, *bk_end = w.bk + (w.bk_max + 1),
+          *item_start = w.bk + 2 * (w.bk_max + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
-  hipLaunchKernelGGL(k_tile_first, dim3(ceil_div(w.max_u, 256)), b, 0, s,
-                     w.counts, w.uq_off, w.tile_first, bk_fill,
-                     (int64_t)nbk + 1);
   const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);

@@ -69,7 +69,7 @@ __device__ __forceinline__ int packed_index(int a, int b, int R) {
 // MFMA (one wave per leaf, 16 x 16 tiles), keeps them in LDS and writes the
 // internal nodes of its LB-leaf subtree (one thread per packed entry,
 // pairwise sums in registers).  Upper levels: k_tree_up sums groups of up to
-// 16 sibling subtree roots, four levels per launch.
+// TU_MAX = 16 sibling subtree roots, four levels per launch.
 // ---------------------------------------------------------------------------
 template <int LBMAX>
 __device__ __forceinline__ void sum_up(double (&x)[LBMAX], int n, double *tree,
@@ -157,14 +157,18 @@ k_tree_build(const T *U, int64_t I, int R, int F, int64_t P2, int lb,
 
 // group g of G consecutive nodes from `first` (one level): entry c of every
 // ancestor up to the group's common root
+constexpr int TU_MAX = 16;
 __global__ void __launch_bounds__(256)
 k_tree_up(double *tree, int64_t first, int G, int P) {
   const int64_t f = first + (int64_t)blockIdx.x * G;
   for (int c = threadIdx.x; c < P; c += 256) {
-    double x[TB_LBMAX];
+    double x[TU_MAX];
 #pragma unroll
-    for (int i = 0; i < TB_LBMAX; ++i) x[i] = i < G ? tree[(f + i) * P + c] : 0.0;
-    sum_up<TB_LBMAX>(x, G, tree, f, P, c);
+    for (int i = 0; i < TU_MAX; ++i) {  // clamped loads, then masked
+      const double y = tree[(f + (i < G ? i : G - 1)) * P + c];
+      x[i] = i < G ? y : 0.0;
+    }
+    sum_up<TU_MAX>(x, G, tree, f, P, c);
   }
 }
 
@@ -1083,8 +1087,8 @@ void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
   // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1
   const int P = sts_packed(R);
   for (int64_t n = P2 >> lb; n > 1;) {
-    int gs = 0;  // up to four levels (TB_LBMAX nodes) per launch
-    while ((2 << gs) <= TB_LBMAX && (int64_t(2) << gs) <= n) ++gs;
+    int gs = 0;  // up to four levels (TU_MAX nodes) per launch
+    while ((2 << gs) <= TU_MAX && (int64_t(2) << gs) <= n) ++gs;
     const int G = 1 << gs;
     hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(n / G)), dim3(256), 0, s,
                        tree, n, G, P);

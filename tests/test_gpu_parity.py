@@ -204,6 +204,21 @@ def test_sts_long_first_factor(dev):
     ctx.close()
 
 
+def test_mode_order_with_growing_bucket_count(dev):
+    """Solves in the order 0, 1, 2, 1 where mode 1 has the most output-row
+    buckets: per-mode bucket state must not leak between modes."""
+    T, _ = tg.tiny_tensor(49, (200, 700, 300), 20_000, rank=3, noise_var=0.01)
+    R, J = 8, 512
+    ctx = make_ctx(dev, T, R, "sts", "fp64", J)
+    _, runi = init_ctx(ctx, T.dims, R, 12)
+    acc = 0
+    for j in (0, 1, 2, 1):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-10)
+    assert acc <= 2
+    ctx.close()
+
+
 def test_arls_fp32_4way_mode_solves(dev):
     T = tg.zipf_tensor(43, (2000, 1000, 400, 20), 150_000, s=1.2)
     R, J = 24, 3000
