@@ -329,20 +329,28 @@ void do_mttkrp(cp_ctx *c, int mode) {
 template <typename T>
 void do_solve(cp_ctx *c, int mode) {
   const int64_t I = c->dims[mode];
+  T *U = static_cast<T *>(c->U[mode]);
   {
     PhaseScope ps(c, PH_SOLVE);
     const int nblk = solve_blocks(I);
     solve_rows<T>(static_cast<const T *>(c->M), I, c->R, c->Gfull, c->Gp, c->X,
                   c->partial, nblk, c->w.stats + 3, c->s);
-    finish_normalize<T>(c->X, I, c->R, c->partial, nblk, c->sigma,
-                        static_cast<T *>(c->U[mode]), c->d_err, c->s);
+    column_norms(c->partial, nblk, c->R, c->sigma, c->d_err, c->s);
   }
-  {
-    PhaseScope ps(c, PH_GRAM);
-    gram<T>(static_cast<const T *>(c->U[mode]), I, c->R, c->G[mode], c->tmp,
-            c->s);
+  // the pass that stages the new factor for its Gram (or for its tree's
+  // leaves) writes it, renormalised, on the way
+  if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, mode) &&
+      c->P2[mode] >= 2) {
+    PhaseScope ps(c, PH_SAMPLER_BUILD);  // the tree's root is the Gram
+    sts_build_scaled<T>(c->X, c->sigma, U, I, c->R, c->F, c->P2[mode],
+                        c->tree[mode], c->G[mode], c->s);
+  } else {
+    {
+      PhaseScope ps(c, PH_GRAM);
+      gram_scaled<T>(c->X, c->sigma, I, c->R, U, c->G[mode], c->tmp, c->s);
+    }
+    rebuild_sampler<T>(c, mode);
   }
-  rebuild_sampler<T>(c, mode);
   c->sampled_mode = -1;
   c->mttkrp_mode = -1;
 }
@@ -401,7 +409,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     if (c->ix[k].val) c->allocs.push_back(c->ix[k].val);
     if (c->ix[k].col_key) c->allocs.push_back(c->ix[k].col_key);
     if (c->ix[k].col_ptr) c->allocs.push_back(c->ix[k].col_ptr);
-    if (c->ix[k].top) c->allocs.push_back(c->ix[k].top);
+    if (c->ix[k].hash) c->allocs.push_back(c->ix[k].hash);
     if (!e.empty())
       throw Fail{e.find("63 bits") != std::string::npos ? CP_EUNSUPPORTED
                                                          : CP_ENOMEM, e};

@@ -57,17 +57,22 @@ struct ModeIndex {
   int64_t I = 0, n_cols = 0, max_col = 0;
   uint64_t *col_key = nullptr;  // n_cols sorted distinct column keys
   int64_t *col_ptr = nullptr;   // n_cols + 1 offsets
-  // first column whose key is >= v * top_stride, v = 0 .. n_top - 1, with
-  // top_stride chosen for about 4 columns per entry; top[n_top - 1] = n_cols
-  int64_t *top = nullptr;
-  uint64_t top_stride = 1;
-  int64_t n_top = 0;
+  // column lookup: open addressing with linear probing over 2^hbits entries
+  // of two words {key, column} (hash: 2 << hbits words), at most half full;
+  // key ~0 marks an empty entry (column keys have at most 63 bits)
+  uint64_t *hash = nullptr;
+  int hbits = 0;
   // sampled MTTKRP: record region start of each output-row bucket (set up
   // by cp_init for the sampling samplers)
   int64_t *bk_start = nullptr;
   int32_t *row = nullptr;       // nnz rows i_j
   void *val = nullptr;          // nnz values (float or double)
 };
+// home entry of a column key in a table of 2^hbits entries (multiplicative
+// hashing: the top hbits bits of key times 2^64 / golden ratio)
+__device__ __forceinline__ uint64_t col_hash(uint64_t key, int hbits) {
+  return (key * 0x9E3779B97F4A7C15ull) >> (64 - hbits);
+}
 // Returns an error message ("" on success).
 std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
                              int64_t nnz, int N, const int64_t *dims, int j,
@@ -85,12 +90,18 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
 
 // ---- dense R x R and tall-skinny kernels (k_dense.hip)
 // Gram of U (I x R): partial Grams per block (FP64 MFMA), then a fixed-order
-// reduction into G (R x R).  `scale` (R doubles or null) multiplies column r
-// by scale[r] before the product (used for renormalisation in place when
-// U_out is given: U_out = U * scale).
+// reduction into G (R x R).
 size_t gram_temp_bytes(int64_t I, int R);
 template <typename T>
 void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s);
+// The same after the solve: U = X / sigma written in the factor's precision
+// (zero columns stay zero) by the pass that stages it, G of the stored U.
+template <typename T>
+void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
+                 double *G, void *tmp, hipStream_t s);
+// sigma[r] = sqrt of the sum over the nblk partial rows of column r
+void column_norms(const double *partial, int nblk, int R, double *sigma,
+                  uint32_t *err, hipStream_t s);
 // Hadamard product of the Grams in `ml` (n entries), pseudo-inverse Gp;
 // for STS also the G_{>k} chain and <G^+, G> (ggt_out may be null).
 void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
@@ -138,6 +149,13 @@ int sts_packed(int R);  // doubles per tree node: packed upper triangle of sts_p
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
                hipStream_t s);
+// The same after the solve: the leaf pass writes U = X / sigma in the
+// factor's precision (zero columns stay zero) and builds on the stored
+// values; the root, which is U^T U, is written to G (R x R) when P2 >= 2.
+template <typename T>
+void sts_build_scaled(const double *X, const double *sigma, T *U, int64_t I,
+                      int R, int F, int64_t P2, double *tree, double *G,
+                      hipStream_t s);
 // per-slot record of the level-by-level tree descent (slots grouped by node)
 struct SlotBuf {
   int32_t *s;  // sample

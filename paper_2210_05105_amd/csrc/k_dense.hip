@@ -16,17 +16,21 @@ namespace {
 // padded to a multiple of 16) and its four waves accumulate the upper-
 // triangular 16x16 output tiles with v_mfma_f64_16x16x4f64.  Per-block
 // partial Grams are summed in a fixed order by a second kernel, so the
-// result is deterministic.
+// result is deterministic.  SCALE: the staging reads the solve's FP64 rows
+// X instead and writes the factor U = X / sigma (zero columns stay zero) in
+// the factor's precision; the Gram is of the stored values.
 // ---------------------------------------------------------------------------
 constexpr int GR_THREADS = 256;
-constexpr int GR_ROWS = 64;
+constexpr int GR_ROWS = 64;      // row granularity of the block ranges
+constexpr int GR_ELEMS = 4096;   // staged entries per chunk (32 KiB of LDS)
 constexpr int GR_MAXBLK = 512;
 
-template <typename T, int TPW>
+template <typename T, int TPW, bool SCALE>
 __global__ void __launch_bounds__(GR_THREADS)
-k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
+k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
+               int64_t I, int R, int Rp, int64_t rows_per_blk,
                double *partial) {
-  extern __shared__ double lds[];  // GR_ROWS x Rp
+  extern __shared__ double lds[];  // RC x Rp <= GR_ELEMS
   const int w = threadIdx.x / WAVE, l = lane_id();
   const int nt = Rp / 16;
   const int ntri = nt * (nt + 1) / 2;
@@ -46,29 +50,47 @@ k_gram_partial(const T *U, int64_t I, int R, int Rp, int64_t rows_per_blk,
   }
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(I, r0 + rows_per_blk);
-  for (int64_t c0 = r0; c0 < r1; c0 += GR_ROWS) {
-    const int nrow = (int)std::min<int64_t>(GR_ROWS, r1 - c0);
+  // chunks of RC rows (RC Rp <= GR_ELEMS, RC a multiple of 4), one batch
+  // of PE clamped loads per thread each, masked when stored; the next
+  // chunk's batch is issued before the current chunk's MFMAs
+  const int RC = (GR_ELEMS / Rp) & ~3, NE = RC * Rp;
+  constexpr int PE = GR_ELEMS / GR_THREADS;
+  double v[PE];
+  auto load = [&](int64_t c0) {
+    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int e = q * GR_THREADS + threadIdx.x;
+      const int rr = e / Rp, cc = e - rr * Rp;
+      const int rc = rr < nrow ? rr : nrow - 1, ccc = cc < R ? cc : R - 1;
+      if constexpr (SCALE) v[q] = X[(c0 + rc) * R + ccc];
+      else v[q] = (double)U[(c0 + rc) * R + ccc];
+    }
+  };
+  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS per entry
+  if constexpr (SCALE)
+    for (int c = threadIdx.x; c < R; c += GR_THREADS) ssg[c] = sigma[c];
+  if (r0 < r1) load(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += RC) {
+    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
     __syncthreads();
-    // 8 clamped loads in flight per thread, masked when stored
-    constexpr int PE = 8;
-    for (int e0 = 0; e0 < GR_ROWS * Rp; e0 += PE * GR_THREADS) {
-      double v[PE];
 #pragma unroll
-      for (int q = 0; q < PE; ++q) {
-        const int e = e0 + q * GR_THREADS + threadIdx.x;
-        const int rr = e / Rp, cc = e - rr * Rp;
-        const int rc = rr < nrow ? rr : nrow - 1, ccc = cc < R ? cc : R - 1;
-        v[q] = (double)U[(c0 + rc) * R + ccc];
+    for (int q = 0; q < PE; ++q) {
+      const int e = q * GR_THREADS + threadIdx.x;
+      const int rr = e / Rp, cc = e - rr * Rp;
+      const bool in = rr < nrow && cc < R;
+      double x = v[q];
+      if constexpr (SCALE) {
+        const double sg = ssg[cc < R ? cc : R - 1];
+        const T u = (T)(sg > 0 ? x / sg : 0.0);
+        if (in) Uout[(c0 + rr) * R + cc] = u;
+        x = (double)u;
       }
-#pragma unroll
-      for (int q = 0; q < PE; ++q) {
-        const int e = e0 + q * GR_THREADS + threadIdx.x;
-        const int rr = e / Rp, cc = e - rr * Rp;
-        if (e < GR_ROWS * Rp) lds[e] = (rr < nrow && cc < R) ? v[q] : 0.0;
-      }
+      if (e < NE) lds[e] = in ? x : 0.0;
     }
     __syncthreads();
-    for (int k0 = 0; k0 < GR_ROWS; k0 += 4) {
+    if (c0 + RC < r1) load(c0 + RC);
+    for (int k0 = 0; k0 < RC; k0 += 4) {
       const double *rowp = lds + (k0 + l / 16) * Rp + (l % 16);
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
@@ -152,12 +174,13 @@ int gram_blocks(int64_t I, int64_t *rows_per_blk) {
   return nblk;
 }
 
-template <typename T, int TPW>
-void launch_gram(const T *U, int64_t I, int R, int Rp, double *partial,
-                 int nblk, int64_t rpb, hipStream_t s) {
-  hipLaunchKernelGGL((k_gram_partial<T, TPW>), dim3(nblk), dim3(GR_THREADS),
-                     GR_ROWS * Rp * sizeof(double), s, U, I, R, Rp, rpb,
-                     partial);
+template <typename T, int TPW, bool SCALE>
+void launch_gram(const T *U, const double *X, const double *sigma, T *Uout,
+                 int64_t I, int R, int Rp, double *partial, int nblk,
+                 int64_t rpb, hipStream_t s) {
+  hipLaunchKernelGGL((k_gram_partial<T, TPW, SCALE>), dim3(nblk),
+                     dim3(GR_THREADS), GR_ELEMS * sizeof(double), s, U, X,
+                     sigma, Uout, I, R, Rp, rpb, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,7 +537,7 @@ __device__ __forceinline__ double afrag(const double *A, int R, int t, int ks,
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(SV_THREADS)
-__attribute__((amdgpu_waves_per_eu(NT <= 2 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1)))
 k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         double *X, double *partial, int64_t *rows_out) {
   constexpr int KS = 4 * NT;          // k-steps
@@ -523,13 +546,25 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
   const int l = lane_id(), w = threadIdx.x / WAVE;
   __shared__ double sG[LDS ? 2 * RP * RP : 1];
   if (LDS) {
-    for (int e = threadIdx.x; e < RP * RP; e += SV_THREADS) {
+    constexpr int NS = (RP * RP + SV_THREADS - 1) / SV_THREADS;
+    double gp[NS], g[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {  // loads first, clamped
+      const int e = q * SV_THREADS + threadIdx.x;
       const int a = e / RP, b = e % RP;
-      const bool in = a < R && b < R;
-      const int ec = in ? a * R + b : 0;
-      const double gp = Gp[ec], g = G[ec];
-      sG[e] = in ? gp : 0.0;
-      sG[RP * RP + e] = in ? g : 0.0;
+      const int ec = (e < RP * RP && a < R && b < R) ? a * R + b : 0;
+      gp[q] = Gp[ec];
+      g[q] = G[ec];
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int e = q * SV_THREADS + threadIdx.x;
+      const int a = e / RP, b = e % RP;
+      const double m = (e < RP * RP && a < R && b < R) ? 1.0 : 0.0;
+      if (e < RP * RP) {
+        sG[e] = gp[q] * m;
+        sG[RP * RP + e] = g[q] * m;
+      }
     }
     __syncthreads();
   }
@@ -557,14 +592,22 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
     // registers
     if (LDS) asm volatile("" ::: "memory");
     // B fragments of M^T: M[row][4 ks + l / 16]
+    // all loads of the tile first (clamped), then masked by a product, not
+    // a select, so that no load is moved into a branch (branch-guarded loads
+    // wait one by one)
     double mf[KS];
     bool nz = false;
+    T raw[KS];
+    const T *mrow = M + rc * R;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + l / 16;
-      const int kc = k < R ? k : R - 1;
-      const double v = (double)M[rc * R + kc];
-      mf[ks] = (row < I && k < R) ? v : 0.0;
+      raw[ks] = mrow[k < R ? k : R - 1];
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + l / 16;
+      mf[ks] = (double)raw[ks] * ((row < I && k < R) ? 1.0 : 0.0);
       nz |= (mf[ks] != 0.0);
     }
     const uint64_t b = __ballot(nz);
@@ -712,29 +755,55 @@ size_t gram_temp_bytes(int64_t I, int R) {
   return (size_t)nblk * R * R * sizeof(double) + 256;
 }
 
-template <typename T>
-void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
+template <typename T, bool SCALE>
+void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
+              int64_t I, int R, double *G, void *tmp, hipStream_t s) {
   int64_t rpb;
   const int nblk = gram_blocks(I, &rpb);
   const int Rp = (R + 15) / 16 * 16;
   const int nt = Rp / 16, ntri = nt * (nt + 1) / 2;
   const int tpw = (ntri + 3) / 4;
   double *partial = static_cast<double *>(tmp);
+#define CPR_GRAM(K) \
+  launch_gram<T, K, SCALE>(U, X, sigma, Uout, I, R, Rp, partial, nblk, rpb, s)
   switch (tpw) {
-    case 1: launch_gram<T, 1>(U, I, R, Rp, partial, nblk, rpb, s); break;
-    case 2: launch_gram<T, 2>(U, I, R, Rp, partial, nblk, rpb, s); break;
-    case 3: launch_gram<T, 3>(U, I, R, Rp, partial, nblk, rpb, s); break;
-    case 4: launch_gram<T, 4>(U, I, R, Rp, partial, nblk, rpb, s); break;
-    case 6: case 5: launch_gram<T, 6>(U, I, R, Rp, partial, nblk, rpb, s); break;
-    default: launch_gram<T, 9>(U, I, R, Rp, partial, nblk, rpb, s); break;
+    case 1: CPR_GRAM(1); break;
+    case 2: CPR_GRAM(2); break;
+    case 3: CPR_GRAM(3); break;
+    case 4: CPR_GRAM(4); break;
+    case 6: case 5: CPR_GRAM(6); break;
+    default: CPR_GRAM(9); break;
   }
+#undef CPR_GRAM
   colsum(partial, nblk, R * R, G, 0, nullptr, s);
   CPR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
+  gram_any<T, false>(U, nullptr, nullptr, nullptr, I, R, G, tmp, s);
 }
 template void gram<float>(const float *, int64_t, int, double *, void *,
                           hipStream_t);
 template void gram<double>(const double *, int64_t, int, double *, void *,
                            hipStream_t);
+
+template <typename T>
+void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
+                 double *G, void *tmp, hipStream_t s) {
+  gram_any<T, true>(nullptr, X, sigma, U, I, R, G, tmp, s);
+}
+template void gram_scaled<float>(const double *, const double *, int64_t, int,
+                                 float *, double *, void *, hipStream_t);
+template void gram_scaled<double>(const double *, const double *, int64_t,
+                                  int, double *, double *, void *,
+                                  hipStream_t);
+
+void column_norms(const double *partial, int nblk, int R, double *sigma,
+                  uint32_t *err, hipStream_t s) {
+  colsum(partial, nblk, R, sigma, 1, err, s);
+  CPR_LAUNCH_CHECK();
+}
 
 void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
                    double *ggt_out, double *trace_out, double *scratch,

@@ -165,18 +165,24 @@ __global__ void k_cols(const uint64_t *hi, int64_t n, int lo_bits,
   col_ptr[cid[p]] = p;
 }
 
-// offsets of the slowest mode's values in the sorted column keys
-__global__ void k_top(const uint64_t *col_key, int64_t n_cols,
-                      uint64_t top_stride, int64_t n_top, int64_t *top) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n_top) return;
-  const uint64_t key = (uint64_t)v * top_stride;
-  int64_t lo = 0, hi = n_cols;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (col_key[mid] < key) lo = mid + 1; else hi = mid;
+// column lookup table: each column claims the first empty entry from its
+// key's home entry on (keys are distinct, so a claim never meets its own key)
+__global__ void k_hash_insert(const uint64_t *col_key, int64_t n_cols,
+                              int hbits, uint64_t *tab) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cols) return;
+  const uint64_t key = col_key[c], mask = (1ull << hbits) - 1;
+  uint64_t p = col_hash(key, hbits);
+  for (uint64_t n = 0; n <= mask; ++n) {
+    const unsigned long long old = atomicCAS(
+        reinterpret_cast<unsigned long long *>(tab + 2 * p), ~0ull,
+        (unsigned long long)key);
+    if (old == ~0ull) {
+      tab[2 * p + 1] = (uint64_t)c;
+      return;
+    }
+    p = (p + 1) & mask;
   }
-  top[v] = lo;
 }
 
 // longest column: grid-stride per thread, then wave and block maxima and
@@ -345,21 +351,17 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
       hipStreamSynchronize(s) != hipSuccess)
     return "hip error while building the mode index";
   out.max_col = (int64_t)mxh;
-  // offset table over the column-key space: entry v = first column with
-  // key >= v top_stride, the stride chosen for about 4 distinct columns per
-  // entry (a lookup then bisects a short range)
-  int last = -1;
-  for (int k = 0; k < N; ++k)
-    if (k != j) last = k;
-  const uint64_t key_space = stride[last] * (uint64_t)dims_h[last];
-  const uint64_t target = std::max<uint64_t>(1, (uint64_t)out.n_cols / 4);
-  out.top_stride = std::max<uint64_t>(1, (key_space + target - 1) / target);
-  out.n_top = (int64_t)((key_space + out.top_stride - 1) / out.top_stride) + 1;
-  if (hipMalloc((void **)&out.top, out.n_top * 8) != hipSuccess)
+  // column lookup table, at least twice as many entries as columns
+  int hbits = 4;
+  while (((int64_t)1 << hbits) < 2 * out.n_cols) ++hbits;
+  out.hbits = hbits;
+  const size_t hbytes = ((size_t)2 << hbits) * 8;
+  if (hipMalloc((void **)&out.hash, hbytes) != hipSuccess)
     return "out of device memory for the mode index";
-  hipLaunchKernelGGL(k_top, dim3(ceil_div(out.n_top, 256)), dim3(256), 0, s,
-                     out.col_key, out.n_cols, out.top_stride, out.n_top,
-                     out.top);
+  if (hipMemsetAsync(out.hash, 0xff, hbytes, s) != hipSuccess)
+    return "hip error while building the mode index";
+  hipLaunchKernelGGL(k_hash_insert, dim3(ceil_div(out.n_cols, 256)), dim3(256),
+                     0, s, out.col_key, out.n_cols, hbits, out.hash);
   CPR_LAUNCH_CHECK();
   return "";
 }

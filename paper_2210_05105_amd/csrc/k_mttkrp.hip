@@ -44,34 +44,65 @@ __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
   h[e] = (T)v;
 }
 
-// Column of each draw: its key, then a binary search inside the short range
-// of columns given by the offset table (key / top_stride).  The first draw of a column
-// claims it with atomicMin (read first: most later draws see a smaller
-// owner and skip the atomic).
+// Column of each draw: its key, probed in the mode's hash table from the
+// key's home entry (one 16-byte load per entry) until the key or an empty
+// entry.  The first draw of a column claims it with atomicMin on its owner
+// word, once per block and column: the block's draws of a column meet in an
+// LDS table first (a heavily drawn column would otherwise take one global
+// atomic per draw, all on one address).
+constexpr int LK_HASH = 2 * LK_THREADS;
+
 __global__ void __launch_bounds__(LK_THREADS)
-k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *col_key,
-         const int64_t *top, uint64_t top_stride, int64_t n_top,
-         int32_t *col_id, int32_t *owner) {
+k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *tab,
+         int hbits, int32_t *col_id, int32_t *owner) {
+  __shared__ int32_t hk[LK_HASH], hm[LK_HASH];
+  for (int e = threadIdx.x; e < LK_HASH; e += LK_THREADS) {
+    hk[e] = -1;
+    hm[e] = INT32_MAX;
+  }
   const int64_t s = (int64_t)blockIdx.x * LK_THREADS + threadIdx.x;
-  if (s >= J) return;
-  uint64_t key = 0;
-  bool ok = true;
-  for (int q = 0; q < ml.n; ++q) {
-    int32_t i = sidx[s * ml.n + q];
-    ok &= (i >= 0 && i < ml.I[q]);
-    key += (uint64_t)i * ml.stride[q];
+  int32_t cid = -1;
+  if (s < J) {
+    uint64_t key = 0;
+    bool ok = true;
+    for (int q = 0; q < ml.n; ++q) {
+      int32_t i = sidx[s * ml.n + q];
+      ok &= (i >= 0 && i < ml.I[q]);
+      key += (uint64_t)i * ml.stride[q];
+    }
+    if (ok) {
+      const uint64_t mask = (1ull << hbits) - 1;
+      uint64_t p = col_hash(key, hbits);
+      for (uint64_t n = 0; n <= mask; ++n) {
+        const ulonglong2 e =
+            *reinterpret_cast<const ulonglong2 *>(tab + 2 * p);
+        if (e.x == key) {
+          cid = (int32_t)e.y;
+          break;
+        }
+        if (e.x == ~0ull) break;
+        p = (p + 1) & mask;
+      }
+    }
+    col_id[s] = cid;
   }
-  uint64_t tv = key / top_stride;
-  if (!ok || tv >= (uint64_t)(n_top - 1)) tv = 0;
-  int64_t lo = top[tv], hi = top[tv + 1];
-  while (lo < hi) {  // first column key >= key
-    int64_t mid = (lo + hi) >> 1;
-    if (col_key[mid] < key) lo = mid + 1; else hi = mid;
+  __syncthreads();
+  if (cid >= 0) {  // at most LK_THREADS keys in 2 LK_THREADS entries
+    uint32_t e = ((uint32_t)cid * 2654435761u) % LK_HASH;
+    for (int probe = 0; probe < LK_HASH; ++probe) {
+      const int32_t prev = atomicCAS(&hk[e], -1, cid);
+      if (prev == -1 || prev == cid) {
+        atomicMin(&hm[e], (int32_t)s);
+        break;
+      }
+      e = (e + 1) % LK_HASH;
+    }
   }
-  const int64_t end = top[tv + 1];
-  int32_t cid = (ok && lo < end && col_key[lo] == key) ? (int32_t)lo : -1;
-  col_id[s] = cid;
-  if (cid >= 0 && owner[cid] > (int32_t)s) atomicMin(&owner[cid], (int32_t)s);
+  __syncthreads();
+  for (int e = threadIdx.x; e < LK_HASH; e += LK_THREADS) {
+    const int32_t c = hk[e];
+    if (c >= 0 && owner[c] > hm[e]) atomicMin(&owner[c], hm[e]);
+  }
 }
 
 // Merge in two launches.  Block b owns the contiguous draws
@@ -784,8 +815,8 @@ template void set_sample_rows<double>(const ModeList &, int64_t, int,
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
                     const ModeIndex &ix, SampleWork &w, hipStream_t s) {
   hipLaunchKernelGGL(k_lookup, dim3(ceil_div(J, LK_THREADS)), dim3(LK_THREADS),
-                     0, s, ml, J, sidx, ix.col_key, ix.top, ix.top_stride,
-                     ix.n_top, w.col_id, w.owner);
+                     0, s, ml, J, sidx, ix.hash, ix.hbits, w.col_id,
+                     w.owner);
   CPR_LAUNCH_CHECK();
 }
 

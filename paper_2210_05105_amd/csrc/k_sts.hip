@@ -73,7 +73,8 @@ __device__ __forceinline__ int packed_index(int a, int b, int R) {
 // ---------------------------------------------------------------------------
 template <int LBMAX>
 __device__ __forceinline__ void sum_up(double (&x)[LBMAX], int n, double *tree,
-                                       int64_t first, int P, int c) {
+                                       int64_t first, int P, int c, double *G,
+                                       int R, int RP) {
   // x[0..n) are entry c of consecutive nodes first .. first + n - 1 of one
   // level; write entry c of every ancestor up to their common root
   for (int m = n / 2; m >= 1; m /= 2) {
@@ -85,44 +86,95 @@ __device__ __forceinline__ void sum_up(double (&x)[LBMAX], int n, double *tree,
         tree[(first + i) * P + c] = x[i];
       }
   }
+  // the root is the Gram U^T U: entry c is (a, b) of the packed upper
+  // triangle, written to both halves of the R x R matrix
+  if (G && first == 1 && n > 1) {
+    int a = 0, rem = c;
+    while (rem >= RP - a) {
+      rem -= RP - a;
+      ++a;
+    }
+    const int b = a + rem;
+    if (b < R) {
+      G[a * R + b] = x[0];
+      G[b * R + a] = x[0];
+    }
+  }
 }
 
 constexpr int TB_LBMAX = 16;
 
-template <typename T, int NT>
+// SCALE: the leaf pass reads the solve's FP64 rows X and writes the factor
+// U = X / sigma (zero columns stay zero) in the factor's precision; the
+// Grams are of the stored values.  G (or null) receives the root as an
+// R x R matrix when this launch writes the root.
+template <typename T, int NT, bool SCALE>
 __global__ void __launch_bounds__(256)
-k_tree_build(const T *U, int64_t I, int R, int F, int64_t P2, int lb,
-             double *tree) {
+k_tree_build(const T *U, const double *X, const double *sigma, T *Uout,
+             int64_t I, int R, int F, int64_t P2, int lb, double *tree,
+             double *G) {
   constexpr int NTRI = NT * (NT + 1) / 2, RP = 16 * NT;
   constexpr int P = RP * (RP + 1) / 2;
   extern __shared__ double leaves[];  // LB x P
   const int LB = 1 << lb;
   const int w = threadIdx.x / WAVE, l = lane_id();
   const int64_t leaf0 = (int64_t)blockIdx.x * LB;
+  double sg[NT];
+  if constexpr (SCALE) {
+#pragma unroll
+    for (int ta = 0; ta < NT; ++ta) {
+      const int ca = ta * 16 + (l % 16);
+      sg[ta] = sigma[ca < R ? ca : R - 1];
+    }
+  }
   for (int lf = w; lf < LB; lf += 4) {
     const int64_t leaf = leaf0 + lf;
     const int64_t rbase = leaf * F;
     double4_t acc[NTRI];
 #pragma unroll
     for (int i = 0; i < NTRI; ++i) acc[i] = double4_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < F; k0 += 4) {
-      const int64_t r = rbase + k0 + l / 16;
-      const double rm = r < I ? 1.0 : 0.0;
-      const T *ur = U + (r < I ? r : I - 1) * R;
-      double col[NT];
+    // 16 rows (four k-steps) at a time: their loads issued together, then
+    // the renormalised values stored (F is a multiple of 16)
+    for (int k0 = 0; k0 < F; k0 += 16) {
+      double col[4][NT];
 #pragma unroll
-      for (int ta = 0; ta < NT; ++ta) {
-        const int ca = ta * 16 + (l % 16);
-        col[ta] = (double)ur[ca < R ? ca : R - 1] * (ca < R ? rm : 0.0);
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = rbase + k0 + 4 * q + l / 16;
+        const int64_t ro = (r < I ? r : I - 1) * R;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta) {
+          const int ca = ta * 16 + (l % 16);
+          const int cc = ca < R ? ca : R - 1;
+          if constexpr (SCALE) col[q][ta] = X[ro + cc];
+          else col[q][ta] = (double)U[ro + cc];
+        }
       }
 #pragma unroll
-      for (int ta = 0; ta < NT; ++ta)
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = rbase + k0 + 4 * q + l / 16;
+        const double rm = r < I ? 1.0 : 0.0;
 #pragma unroll
-        for (int tb = ta; tb < NT; ++tb) {
-          const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
-          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(col[ta], col[tb],
-                                                        acc[i], 0, 0, 0);
+        for (int ta = 0; ta < NT; ++ta) {
+          const int ca = ta * 16 + (l % 16);
+          double x = col[q][ta];
+          if constexpr (SCALE) {
+            const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
+            if (r < I && ca < R) Uout[r * R + ca] = u;
+            x = (double)u;
+          }
+          col[q][ta] = x * (ca < R ? rm : 0.0);
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = ta; tb < NT; ++tb) {
+            const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                col[q][ta], col[q][tb], acc[i], 0, 0, 0);
+          }
     }
     // tile (ta, tb), lane l, element v -> (ta*16 + l/16 + 4v, tb*16 + l%16);
     // entries beyond R are exact zeros (zero columns)
@@ -151,7 +203,7 @@ k_tree_build(const T *U, int64_t I, int R, int F, int64_t P2, int lb,
     double x[TB_LBMAX];
 #pragma unroll
     for (int i = 0; i < TB_LBMAX; ++i) x[i] = i < LB ? leaves[i * P + c] : 0.0;
-    sum_up<TB_LBMAX>(x, LB, tree, P2 + leaf0, P, c);
+    sum_up<TB_LBMAX>(x, LB, tree, P2 + leaf0, P, c, G, R, RP);
   }
 }
 
@@ -159,7 +211,8 @@ k_tree_build(const T *U, int64_t I, int R, int F, int64_t P2, int lb,
 // ancestor up to the group's common root
 constexpr int TU_MAX = 16;
 __global__ void __launch_bounds__(256)
-k_tree_up(double *tree, int64_t first, int G, int P) {
+k_tree_up(double *tree, int64_t first, int G, int P, double *Gm, int R,
+          int RP) {
   const int64_t f = first + (int64_t)blockIdx.x * G;
   for (int c = threadIdx.x; c < P; c += 256) {
     double x[TU_MAX];
@@ -168,7 +221,7 @@ k_tree_up(double *tree, int64_t first, int G, int P) {
       const double y = tree[(f + (i < G ? i : G - 1)) * P + c];
       x[i] = i < G ? y : 0.0;
     }
-    sum_up<TU_MAX>(x, G, tree, f, P, c);
+    sum_up<TU_MAX>(x, G, tree, f, P, c, Gm, R, RP);
   }
 }
 
@@ -193,11 +246,19 @@ constexpr int ST = 256;
 // a barrier must follow)
 template <int RP>
 __device__ __forceinline__ void stage_pad(double *dst, const double *A, int R) {
-  for (int e = threadIdx.x; e < RP * RP; e += ST) {
+  constexpr int NS = (RP * RP + ST - 1) / ST;
+  double x[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {  // all loads first (clamped), then masked
+    const int e = q * ST + threadIdx.x;
     const int a = e / RP, b = e % RP;
-    const int ac = a < R ? a : R - 1, bc = b < R ? b : R - 1;
-    const double x = A[ac * R + bc];  // unconditional load, then mask
-    dst[e] = (a < R && b < R) ? x : 0.0;
+    x[q] = A[(a < R ? a : R - 1) * R + (b < R ? b : R - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int e = q * ST + threadIdx.x;
+    const int a = e / RP, b = e % RP;
+    if (e < RP * RP) dst[e] = x[q] * ((a < R && b < R) ? 1.0 : 0.0);
   }
 }
 
@@ -467,14 +528,31 @@ k_sts_first(const T *U, int64_t I, int R, const double *lev, const double *sub,
   if (lo >= I) lo = I - 1;
   if (act) sidx[s * nq] = (int32_t)lo;
   // h = U[lo] for the wave's samples, the rows read and written coalesced
+  // (WAVE samples x RP entries, WAVE per pass, eight passes' loads issued
+  // together; a full wave stores without a condition, so that no load is
+  // moved into a branch)
   const int nw = J - sw0 < WAVE ? (int)(J - sw0) : WAVE;
-#pragma unroll 8
-  for (int it = 0; it < RP; ++it) {  // WAVE samples x RP entries, WAVE per pass
-    const int e = it * WAVE + l, k = e / RP, a = e % RP;
-    const int64_t ik = __shfl(lo, k, WAVE);
-    if (k < nw) {
-      const double x = (double)U[ik * R + (a < R ? a : R - 1)];
-      hbuf[(sw0 + k) * RP + a] = a < R ? x : 0.0;
+#pragma unroll
+  for (int it0 = 0; it0 < RP; it0 += 8) {
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = (it0 + j) * WAVE + l, k = e / RP, a = e % RP;
+      const int64_t ik = __shfl(lo, k, WAVE);
+      x[j] = (double)U[ik * R + (a < R ? a : R - 1)] * (a < R ? 1.0 : 0.0);
+    }
+    if (nw == WAVE) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = (it0 + j) * WAVE + l;
+        hbuf[(sw0 + e / RP) * RP + e % RP] = x[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = (it0 + j) * WAVE + l;
+        if (e / RP < nw) hbuf[(sw0 + e / RP) * RP + e % RP] = x[j];
+      }
     }
   }
 }
@@ -985,13 +1063,16 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
   if (l < n) prob[p0 + l] = mass / *trace;
   // the 16 rows of h in the path precision, coalesced
   const int ne = n * R;
+  double hv[RP / 4];  // ne <= 16 R <= 64 (RP / 4); loads first (clamped)
 #pragma unroll
-  for (int it = 0; it < RP / 4; ++it) {  // ne <= 16 R <= 64 (RP / 4)
+  for (int it = 0; it < RP / 4; ++it) {
+    const int e = it * WAVE + l < ne ? it * WAVE + l : ne - 1;
+    hv[it] = hbuf[(p0 + e / R) * RP + e % R];
+  }
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {
     const int e = it * WAVE + l;
-    if (e < ne) {
-      const int r = e / R, c = e % R;
-      h_out[(p0 + r) * R + c] = (T)hbuf[(p0 + r) * RP + c];
-    }
+    if (e < ne) h_out[(p0 + e / R) * R + e % R] = (T)hv[it];
   }
 }
 
@@ -1071,31 +1152,52 @@ int tree_leaf_shift(int R, int64_t P2) {
   return lb;
 }
 
-template <typename T>
-void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
-               hipStream_t s) {
+template <typename T, bool SCALE>
+void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
+                int64_t I, int R, int F, int64_t P2, double *tree, double *G,
+                hipStream_t s) {
   const int lb = tree_leaf_shift(R, P2);
   const size_t lds = ((size_t)1 << lb) * sts_packed(R) * 8;
   const dim3 g((unsigned)(P2 >> lb)), b(256);
   switch ((R + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_tree_build<T, 1>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
-    case 2: hipLaunchKernelGGL((k_tree_build<T, 2>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
-    case 3: hipLaunchKernelGGL((k_tree_build<T, 3>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
-    default: hipLaunchKernelGGL((k_tree_build<T, 4>), g, b, lds, s, U, I, R, F, P2, lb, tree); break;
+    case 1: hipLaunchKernelGGL((k_tree_build<T, 1, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 2: hipLaunchKernelGGL((k_tree_build<T, 2, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 3: hipLaunchKernelGGL((k_tree_build<T, 3, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    default: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
   }
   CPR_LAUNCH_CHECK();
   // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1
-  const int P = sts_packed(R);
+  const int P = sts_packed(R), RP = sts_pad(R);
   for (int64_t n = P2 >> lb; n > 1;) {
     int gs = 0;  // up to four levels (TU_MAX nodes) per launch
     while ((2 << gs) <= TU_MAX && (int64_t(2) << gs) <= n) ++gs;
-    const int G = 1 << gs;
-    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(n / G)), dim3(256), 0, s,
-                       tree, n, G, P);
+    const int G1 = 1 << gs;
+    hipLaunchKernelGGL(k_tree_up, dim3((unsigned)(n / G1)), dim3(256), 0, s,
+                       tree, n, G1, P, G, R, RP);
     CPR_LAUNCH_CHECK();
-    n /= G;
+    n /= G1;
   }
 }
+
+template <typename T>
+void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
+               hipStream_t s) {
+  tree_build<T, false>(U, nullptr, nullptr, nullptr, I, R, F, P2, tree,
+                       nullptr, s);
+}
+
+template <typename T>
+void sts_build_scaled(const double *X, const double *sigma, T *U, int64_t I,
+                      int R, int F, int64_t P2, double *tree, double *G,
+                      hipStream_t s) {
+  tree_build<T, true>(nullptr, X, sigma, U, I, R, F, P2, tree, P2 >= 2 ? G : nullptr, s);
+}
+template void sts_build_scaled<float>(const double *, const double *, float *,
+                                      int64_t, int, int, int64_t, double *,
+                                      double *, hipStream_t);
+template void sts_build_scaled<double>(const double *, const double *,
+                                       double *, int64_t, int, int, int64_t,
+                                       double *, double *, hipStream_t);
 template void sts_build<float>(const float *, int64_t, int, int, int64_t,
                                double *, hipStream_t);
 template void sts_build<double>(const double *, int64_t, int, int, int64_t,
