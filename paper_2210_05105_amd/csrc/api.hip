@@ -456,7 +456,7 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     dalloc(c, &c->sw.rc, sts_counters(mP2) * 4);
     dalloc(c, &c->sw.sbeg, 2 * mP2 * 4);
     dalloc(c, &c->sw.send, 2 * mP2 * 4);
-    dalloc(c, &c->sw.topc, (size_t)STS_TOPC * MAXN * 4);
+    dalloc(c, &c->sw.tcnt, (size_t)sts_top_counts(Js) * 4);
   }
   dalloc(c, &c->sigma, R * 8);
   dalloc(c, &c->Gfull, R * R * 8);

@@ -142,7 +142,7 @@ void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
 // ---- STS-CP (k_sts.hip)
 int sts_pad(int R);     // rank padded to the draw width (row stride of StsWork::h)
 int64_t sts_counters(int64_t P2);
-constexpr int STS_TOPC = 32;
+int64_t sts_top_counts(int64_t J);
 int64_t sts_first_rows(int64_t I);
 int64_t sts_first_sums(int64_t I);  // entries of StsWork::lc and ::rc
 int sts_packed(int R);  // doubles per tree node: packed upper triangle of sts_pad(R)
@@ -170,7 +170,8 @@ struct StsWork {
   SlotBuf slot[2];       // J records, double-buffered across levels
   int32_t *lc, *rc;      // sts_counters(P2): samples sent left / right
   int32_t *sbeg, *send;  // 2 P2: slot range of a node
-  int32_t *topc;         // STS_TOPC per drawn factor: top-stage counters
+  int32_t *tcnt;         // sts_top_counts(J): samples per top node, per
+                         // top-stage block
 };
 template <typename T>
 void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,

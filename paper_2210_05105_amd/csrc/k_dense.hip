@@ -424,39 +424,33 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   double tr = 0, dmax = 0;
   bool bad = false;
   // Hadamard product of the other modes' Grams, 4 entries per thread at a
-  // time with the loads of one Gram issued together (clamped, then masked)
+  // time, the loads of all Grams issued together (clamped, then masked)
   const int RR = R * R;
+  constexpr int QM = MAXN - 1;  // at most N - 1 Grams
   for (int e0 = 0; e0 < RR; e0 += 4 * PV_THREADS) {
-    double hv[4] = {1.0, 1.0, 1.0, 1.0};
-    for (int i = ml.n - 1; i >= 0; --i) {
-      // STS: ggt[i] = Hadamard product of the Grams after i (times G^+ below)
-      if (ggt)
+    double x[QM][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = e0 + t + q * PV_THREADS;
-          if (e < RR) ggt[(int64_t)i * RR + e] = hv[q];
-        }
-      const double *Gi = ml.G[i];
-      double x[4];
+    for (int i = 0; i < QM; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = e0 + t + q * PV_THREADS;
-        x[q] = Gi[e < RR ? e : RR - 1];
+        x[i][q] = ml.G[i < ml.n ? i : 0][e < RR ? e : RR - 1];
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) hv[q] *= x[q];
-    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = e0 + t + q * PV_THREADS;
-      if (e >= RR) break;
-      const double v = hv[q];
-      A[e] = v;
-      Gfull[e] = v;
-      if (!isfinite(v)) bad = true;
-      if (e / R == e % R) {
-        tr += v;
-        dmax = fmax(dmax, v);
+      double v = 1.0;
+#pragma unroll
+      for (int i = QM - 1; i >= 0; --i)
+        if (i < ml.n) v *= x[i][q];
+      if (e < RR) {
+        A[e] = v;
+        Gfull[e] = v;
+        if (!isfinite(v)) bad = true;
+        if (e / R == e % R) {
+          tr += v;
+          dmax = fmax(dmax, v);
+        }
       }
     }
   }
@@ -501,12 +495,35 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
     }
     gps = A + RR;
   }
-  // <G^+, G> and, for STS, G_{>k} = G^+ (*) Hadamard of later Grams
+  // <G^+, G> and, for STS, G_{>k} = G^+ (*) Hadamard of the Grams after
+  // position k (the suffix products of the same Gram loads, issued together)
   double ip = 0;
-  for (int e = t; e < RR; e += PV_THREADS) {
-    const double gp = gps[e];
-    ip += gp * Gfull[e];
-    for (int q = 0; q < (ggt ? ml.n : 0); ++q) ggt[(int64_t)q * RR + e] *= gp;
+  for (int e0 = 0; e0 < RR; e0 += 4 * PV_THREADS) {
+    double x[QM][4], gp[4], gf[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + t + q * PV_THREADS, ec = e < RR ? e : RR - 1;
+      gp[q] = gps[ec];
+      gf[q] = Gfull[ec];
+#pragma unroll
+      for (int i = 0; i < QM; ++i)
+        x[i][q] = ggt ? ml.G[i < ml.n ? i : 0][ec] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + t + q * PV_THREADS;
+      if (e >= RR) continue;
+      ip += gp[q] * gf[q];
+      if (ggt) {
+        double h = 1.0;
+#pragma unroll
+        for (int i = QM - 1; i >= 0; --i)
+          if (i < ml.n) {
+            ggt[(int64_t)i * RR + e] = h * gp[q];
+            h *= x[i][q];
+          }
+      }
+    }
   }
   ip = block_sum(ip, red);
   if (trace_out && t == 0) *trace_out = ip;

@@ -262,6 +262,60 @@ __device__ __forceinline__ void stage_pad(double *dst, const double *A, int R) {
   }
 }
 
+// B fragments of a symmetric R x R matrix for tile_mass_t, staged in LDS in
+// fragment order: entry f WAVE + lane holds fragment f = 2 t (t + 1) + ks
+// (tile t, k-step ks <= 4 t + 3) of that lane, the off-diagonal blocks
+// doubled, zeros beyond R.  Each wave then reads a fragment with one
+// conflict-free LDS load.  Block-wide; a barrier must follow.
+template <int NT>
+constexpr int bfrag_count() { return 2 * NT * (NT + 1); }
+
+template <int NT>
+__device__ __forceinline__ void bfrag_entry(int f, int ln, int &k, int &c,
+                                            bool &off) {
+  int t = 0;
+  while (f >= 2 * (t + 1) * (t + 2)) ++t;
+  const int ks = f - 2 * t * (t + 1);
+  k = 4 * ks + ln / 16;
+  c = 16 * t + (ln % 16);
+  off = ks / 4 < t;
+}
+
+template <int NT>
+__device__ __forceinline__ void stage_bfrag(double *dst, const double *A,
+                                            int R) {
+  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + ST - 1) / ST;
+  double x[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {  // all loads first (clamped), then masked
+    const int e = q * ST + threadIdx.x;
+    int k, c;
+    bool off;
+    bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+    x[q] = A[(k < R ? k : R - 1) * R + (c < R ? c : R - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    const int e = q * ST + threadIdx.x;
+    int k, c;
+    bool off;
+    bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+    if (e < NE)
+      dst[e] = (off ? 2.0 : 1.0) * x[q] * ((k < R && c < R) ? 1.0 : 0.0);
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void lds_bfrag_f(const double *sF,
+                                            double (&f)[NT][4 * NT]) {
+  const int l = lane_id();
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int ks = 0; ks < 4 * (t + 1); ++ks)
+      f[t][ks] = sF[(2 * t * (t + 1) + ks) * WAVE + l];
+}
+
 // Fragments of a zero-padded symmetric RP x RP matrix held in LDS, for
 // tile_mass_t: block (tile t, k-tile) is used only for k-tile <= t, the
 // blocks off the diagonal doubled
@@ -362,16 +416,13 @@ __device__ __forceinline__ void load_hfrag_lds(const double *hb, int32_t s,
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(4)))
 k_sts_mass(const T *U, int64_t I, int R, const double *Gg, int gshift,
-           double *lev, double *sub, double *grp, int32_t *topc, int ntopc,
-           uint32_t *err) {
-  if (blockIdx.x == 0)  // counters of the tree factors' top stages
-    for (int i = threadIdx.x; i < ntopc; i += ST) topc[i] = 0;
+           double *lev, double *sub, double *grp, uint32_t *err) {
   constexpr int RP = 16 * NT, KS = 4 * NT, RS = tile_stride<NT>();
   static_assert(FIRST_SUB == 16 * (ST / WAVE), "one row tile per wave");
-  __shared__ double sG[RP * RP];
+  __shared__ double sG[bfrag_count<NT>() * WAVE];
   __shared__ double sH[ST / WAVE][16 * RS];
   __shared__ double wsum[ST / WAVE];
-  stage_pad<RP>(sG, Gg, R);
+  stage_bfrag<NT>(sG, Gg, R);
   __syncthreads();
   const int l = lane_id(), wv = threadIdx.x / WAVE;
   double *buf = sH[wv];
@@ -398,7 +449,7 @@ k_sts_mass(const T *U, int64_t I, int R, const double *Gg, int gshift,
     wave_lds_sync();
     asm volatile("" ::: "memory");
     double gB[NT][KS], xA[KS];
-    lds_bfrag<NT>(sG, gB);
+    lds_bfrag_f<NT>(sG, gB);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) xA[ks] = buf[(l % 16) * RS + 4 * ks + l / 16];
     double m = tile_mass_t<NT>(xA, gB);  // lanes 0..15: row row0 + l
@@ -622,49 +673,91 @@ template <int NT>
 __global__ void __launch_bounds__(TOP_ST)
 k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
           const double *uni, int q, int nq, int64_t J, StsWork w,
-          SlotBuf out, int32_t *topc, uint32_t *err) {
+          SlotBuf out, int32_t *tcnt, uint32_t *err) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2, KS = 4 * NT;
-  __shared__ double sN[TOP_N * P];  // node Grams TOP_N .., packed
+  // B fragments of the TOP_N products 2^[off-diagonal block] G_{>k} (*) G^v,
+  // fragment f = 2 t (t + 1) + ks of tile t, k-step ks, one double per lane:
+  // built once per block, then read by every wave without bank conflicts.
+  // The same LDS first holds each wave's 16 h rows.
+  constexpr int NQ = 2 * NT * (NT + 1);
+  constexpr int QE = TOP_N * NQ * WAVE;
+  constexpr int HE = (TOP_ST / WAVE) * 16 * tile_stride<NT>();
+  static_assert(QE == NQ * TOP_ST, "fragment entries per thread");
+  __shared__ double sQ[QE > HE ? QE : HE];
   __shared__ double sG[RP * RP];    // G_{>k}, zeros beyond R
-  __shared__ double sH[TOP_ST / WAVE][16 * tile_stride<NT>()];
   __shared__ int32_t scnt[TOP_N];
+  const int l = lane_id();
   const int64_t g0 = (int64_t)blockIdx.x * TOP_ST + threadIdx.x;
+  // this lane's uniform (if it has a sample), issued before the staging
+  const int64_t gu = ((int64_t)blockIdx.x * (TOP_ST / WAVE) + threadIdx.x / WAVE) * 16 +
+                     l % 16;
+  const double u0 = uni[(gu < J ? gu : J - 1) * nq + q];
   for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * TOP_ST) {
     w.lc[i] = 0;
     w.rc[i] = 0;
   }
   if (threadIdx.x < TOP_N) scnt[threadIdx.x] = 0;
-  {  // nodes TOP_N .. 2 TOP_N - 1 are contiguous in the tree
-    const double *src = tree + (int64_t)TOP_N * P;
-    for (int e = threadIdx.x; e < TOP_N * P; e += TOP_ST) sN[e] = src[e];
-    for (int e = threadIdx.x; e < RP * RP; e += TOP_ST) {
-      const int a = e / RP, b = e % RP;
-      const bool in = a < R && b < R;
-      const double x = Gg[in ? a * R + b : 0];
-      sG[e] = in ? x : 0.0;
-    }
+  // every staging load first: G_{>k} (clamped, masked when stored) and this
+  // thread's NQ node entries (nodes TOP_N .. 2 TOP_N - 1)
+  constexpr int NG = (RP * RP + TOP_ST - 1) / TOP_ST;
+  double z[NG], y[NQ];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+    const int e = j * TOP_ST + threadIdx.x, a = e / RP, b = e % RP;
+    z[j] = Gg[(a < R ? a : R - 1) * R + (b < R ? b : R - 1)];
   }
-  __syncthreads();
-  const int l = lane_id();
+  auto entry = [&](int j, int &v, int &k, int &c, bool &off) {
+    const int idx = j * TOP_ST + threadIdx.x;  // lane of the entry: l
+    v = idx / (NQ * WAVE);
+    const int f = (idx / WAVE) % NQ;
+    int tt = 0;
+    while (f >= 2 * (tt + 1) * (tt + 2)) ++tt;
+    const int ks = f - 2 * tt * (tt + 1);
+    k = 4 * ks + l / 16;
+    c = 16 * tt + (l % 16);
+    off = ks / 4 < tt;
+  };
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    int v, k, c;
+    bool off;
+    entry(j, v, k, c, off);
+    y[j] = tree[(int64_t)(TOP_N + v) * P +
+                (k <= c ? packed_index(k, c, RP) : packed_index(c, k, RP))];
+  }
   const int64_t p0 = ((int64_t)blockIdx.x * (TOP_ST / WAVE) + threadIdx.x / WAVE) * 16;
   const int64_t g = p0 + l;
   const bool act = p0 < J && l < 16 && g < J;
+  double xA[KS], xD[NT][4];
   if (p0 < J) {
     const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
-    double xA[KS], xD[NT][4], mm[TOP_N];
-    load_hfrag_lds<NT>(w.h, s, sH[threadIdx.x / WAVE], xA, xD);
+    load_hfrag_lds<NT>(w.h, s, sQ + (threadIdx.x / WAVE) * 16 * tile_stride<NT>(),
+                       xA, xD);
+  }
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+    const int e = j * TOP_ST + threadIdx.x, a = e / RP, b = e % RP;
+    if (e < RP * RP) sG[e] = z[j] * ((a < R && b < R) ? 1.0 : 0.0);
+  }
+  __syncthreads();  // h tiles read, G_{>k} staged
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    int v, k, c;
+    bool off;
+    entry(j, v, k, c, off);
+    sQ[j * TOP_ST + threadIdx.x] = (off ? 2.0 : 1.0) * sG[k * RP + c] * y[j];
+  }
+  __syncthreads();
+  if (p0 < J) {
+    double mm[TOP_N];
 #pragma unroll 1
     for (int v = 0; v < TOP_N; ++v) {
-      const double *nv = sN + v * P;
       double qB[NT][KS];
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-        for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
-          const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
-          qB[tt][ks] = (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j] *
-                       nv[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
-        }
+        for (int ks = 0; ks < 4 * (tt + 1); ++ks)
+          qB[tt][ks] = sQ[(v * NQ + 2 * tt * (tt + 1) + ks) * WAVE + l];
       const double x = tile_mass_t<NT>(xA, qB);  // lanes 0..15: sample l
 #pragma unroll
       for (int i = 0; i < TOP_N; ++i)
@@ -674,7 +767,7 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
 #pragma unroll
     for (int i = 0; i < TOP_N; ++i) Z += mm[i] > 0 ? mm[i] : 0.0;
     if (act) {
-      double u = uni[g * nq + q];
+      double u = u0;  // g == gu for active lanes
       if (!(u >= 0.0 && u < 1.0)) {
         atomicOr(err, ERR_UNIFORM);
         u = 0.0;
@@ -712,28 +805,77 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
     }
   }
   __syncthreads();
-  if (threadIdx.x < TOP_N && scnt[threadIdx.x])
-    atomicAdd(&topc[threadIdx.x], scnt[threadIdx.x]);
+  if (threadIdx.x < TOP_N)  // this block's count per node (no atomics)
+    tcnt[(int64_t)blockIdx.x * TOP_N + threadIdx.x] = scnt[threadIdx.x];
 }
 
 // Place the samples of the top stage in their node's slot range (nodes in
 // order, ranges contiguous); sets the ranges and left counts of the nodes
 // one level up so that the next level finds them as it does below a level.
-// A block places ST consecutive samples: per-node counts and ranks in LDS,
-// one atomic per block and node (issued together) for the block's base.
+// A block places ST consecutive samples, which are those of top-stage blocks
+// 2b and 2b + 1: from the per-block counts it forms the node totals (range
+// starts) and its own offsets inside each range (the samples of the
+// earlier blocks), with no global atomics; ranks inside the block come from
+// LDS counters.
+constexpr int TOP_SPB = 16 * (TOP_ST / WAVE);  // samples per top-stage block
+static_assert(ST == 2 * TOP_SPB, "two top-stage blocks per placement block");
+
 __global__ void __launch_bounds__(ST)
 k_sts_top_place(int64_t J, StsWork w, SlotBuf in, SlotBuf out,
-                const int32_t *topc_cnt, int32_t *topc_fill) {
+                const int32_t *tcnt, int ntb) {
   __shared__ int32_t start[TOP_N + 1], bcnt[TOP_N], bbase[TOP_N];
+  __shared__ int32_t red[ST / WAVE][2 * TOP_N];
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  // this thread's record first (clamped; its loads overlap the count sums)
+  const int64_t g = (int64_t)blockIdx.x * ST + threadIdx.x;
+  const bool a = g < J;
+  const int64_t gc = a ? g : J - 1;
+  const int32_t s = in.s[gc], v = in.v[gc];
+  const double t = in.t[gc], m = in.m[gc];
+  int32_t tot[TOP_N], pre[TOP_N];
+#pragma unroll
+  for (int i = 0; i < TOP_N; ++i) tot[i] = pre[i] = 0;
+  for (int tb = threadIdx.x; tb < ntb; tb += ST) {
+    const int4 *row = reinterpret_cast<const int4 *>(tcnt + (int64_t)tb * TOP_N);
+    const int4 c0 = row[0], c1 = row[1];
+    const int32_t c[TOP_N] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    const bool before = tb < 2 * (int)blockIdx.x;
+#pragma unroll
+    for (int i = 0; i < TOP_N; ++i) {
+      tot[i] += c[i];
+      pre[i] += before ? c[i] : 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TOP_N; ++i)
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      tot[i] += __shfl_xor(tot[i], o, WAVE);
+      pre[i] += __shfl_xor(pre[i], o, WAVE);
+    }
+  if (l == 0)
+#pragma unroll
+    for (int i = 0; i < TOP_N; ++i) {
+      red[wv][i] = tot[i];
+      red[wv][TOP_N + i] = pre[i];
+    }
+  if (threadIdx.x < TOP_N) bcnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (threadIdx.x < 2 * TOP_N) {
+    int32_t x = 0;
+    for (int q = 0; q < ST / WAVE; ++q) x += red[q][threadIdx.x];
+    if (threadIdx.x >= TOP_N) bbase[threadIdx.x - TOP_N] = x;
+    else red[0][threadIdx.x] = x;  // read back by thread 0 after a barrier
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     int32_t a = 0;
     for (int i = 0; i < TOP_N; ++i) {
       start[i] = a;
-      a += topc_cnt[i];
+      a += red[0][i];
     }
     start[TOP_N] = a;
   }
-  if (threadIdx.x < TOP_N) bcnt[threadIdx.x] = 0;
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x < TOP_N / 2) {  // parents TOP_N/2 ..
     const int p = TOP_N / 2 + threadIdx.x, i = 2 * threadIdx.x;
@@ -741,21 +883,8 @@ k_sts_top_place(int64_t J, StsWork w, SlotBuf in, SlotBuf out,
     w.send[p] = start[i + 2];
     w.lc[cslot(p)] = start[i + 1] - start[i];
   }
-  const int64_t g = (int64_t)blockIdx.x * ST + threadIdx.x;
-  const bool a = g < J;
-  int32_t s = 0, v = 0;
-  double t = 0.0, m = 0.0;
   int32_t rank = 0;
-  if (a) {
-    s = in.s[g];
-    v = in.v[g];
-    t = in.t[g];
-    m = in.m[g];
-    rank = atomicAdd(&bcnt[v - TOP_N], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x < TOP_N && bcnt[threadIdx.x])
-    bbase[threadIdx.x] = atomicAdd(&topc_fill[threadIdx.x], bcnt[threadIdx.x]);
+  if (a) rank = atomicAdd(&bcnt[v - TOP_N], 1);
   __syncthreads();
   if (a) {
     const int32_t pos = start[v - TOP_N] + bbase[v - TOP_N] + rank;
@@ -780,7 +909,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   __shared__ int32_t sh_s[64], sh_v[64], sh_beg[64], sh_end[64];
   __shared__ double sh_t[64], sh_m[64];
   __shared__ int32_t sh_r[64];
-  __shared__ double sG[RP * RP];  // G_{>k}, zeros beyond R
+  __shared__ double sG[bfrag_count<NT>() * WAVE];  // G_{>k}, zeros beyond R
   __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
   const int64_t pb = (int64_t)blockIdx.x * 64;
   if (pb >= J) return;
@@ -793,7 +922,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   const int32_t s = in.s[pc];
   const int32_t v = in.v[pc];
   double t = in.t[pc], m = in.m[pc];
-  stage_pad<RP>(sG, Gg, R);
+  stage_bfrag<NT>(sG, Gg, R);
   // slot range of node v: the root's, or the parent's split at its left count
   const int32_t par = v > 1 ? v >> 1 : 1;
   const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
@@ -832,10 +961,8 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-      for (int ks = 0; ks < 4 * (tt + 1); ++ks) {
-        const int k = 4 * ks + l / 16, j = 16 * tt + (l % 16);
-        nv[tt][ks] *= (ks / 4 < tt ? 2.0 : 1.0) * sG[k * RP + j];
-      }
+      for (int ks = 0; ks < 4 * (tt + 1); ++ks)
+        nv[tt][ks] *= sG[(2 * tt * (tt + 1) + ks) * WAVE + l];
     const double x = tile_mass_t<NT>(xA, nv);
     if ((grp >> l) & 1ull) mL = x;
     rem &= ~grp;
@@ -924,10 +1051,10 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
   constexpr int HB = 16 * tile_stride<NT>() * 8;     // h staging bytes
   constexpr int UB = PB * 16 * RSU * (int)sizeof(T);
   constexpr int WB = (HB > UB ? HB : UB) / 8;        // doubles per wave
-  __shared__ double sG[RP * RP];
+  __shared__ double sG[bfrag_count<NT>() * WAVE];
   __shared__ double sW[ST / WAVE][WB];
   __shared__ int64_t sR0[ST / WAVE][16];  // first leaf row of each slot
-  stage_pad<RP>(sG, Gg, R);
+  stage_bfrag<NT>(sG, Gg, R);
   __syncthreads();
   const int l = lane_id();
   const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
@@ -1005,7 +1132,7 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
       // held in registers
       asm volatile("" ::: "memory");
       double gB[NT][KS], xA[KS];
-      lds_bfrag<NT>(sG, gB);
+      lds_bfrag_f<NT>(sG, gB);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
         xA[ks] = (double)sp[(l % 16) * RSU + 4 * ks + l / 16] * hA[ks];
@@ -1047,9 +1174,9 @@ __global__ void __launch_bounds__(ST)
 k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
             const double *trace, double *prob, T *h_out) {
   constexpr int RP = 16 * NT;
-  __shared__ double sP[RP * RP];
+  __shared__ double sP[bfrag_count<NT>() * WAVE];
   __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
-  stage_pad<RP>(sP, Gp, R);
+  stage_bfrag<NT>(sP, Gp, R);
   __syncthreads();
   const int l = lane_id();
   const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
@@ -1057,7 +1184,7 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
   const int n = J - p0 < 16 ? (int)(J - p0) : 16;
   const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
   double qB[NT][4 * NT], xA[4 * NT], xD[NT][4];
-  lds_bfrag<NT>(sP, qB);
+  lds_bfrag_f<NT>(sP, qB);
   load_hfrag_lds<NT>(hbuf, s, sH[threadIdx.x / WAVE], xA, xD);
   const double mass = tile_mass_t<NT>(xA, qB);
   if (l < n) prob[p0 + l] = mass / *trace;
@@ -1088,7 +1215,7 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
   double *grp = w.sub + first_nsub(I0);
   hipLaunchKernelGGL((k_sts_mass<T, NT>), dim3((unsigned)first_ngroups(I0)), b,
                      0, st, static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0],
-                     gs, w.lev, w.sub, grp, w.topc, STS_TOPC * nq, err);
+                     gs, w.lev, w.sub, grp, err);
   CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
                      static_cast<const T *>(ml.U[0]), I0, R, w.lev, w.sub, grp,
@@ -1102,13 +1229,13 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
     bool top = false;
     if constexpr (NT <= 3) {  // the packed node products fit LDS
       if (P2 >= 2 * TOP_N) {  // top stage: nodes TOP_N .. 2 TOP_N - 1
-        int32_t *tc = w.topc + STS_TOPC * q;
-        hipLaunchKernelGGL((k_sts_top<NT>), dim3(ceil_div(J, 16 * (TOP_ST / WAVE))),
-                           dim3(TOP_ST), 0, st, tree, Gg, P2, R, uni, q, nq, J,
-                           w, w.slot[1], tc, err);
+        const int ntb = (int)ceil_div(J, TOP_SPB);
+        hipLaunchKernelGGL((k_sts_top<NT>), dim3(ntb), dim3(TOP_ST), 0, st,
+                           tree, Gg, P2, R, uni, q, nq, J, w, w.slot[1],
+                           w.tcnt, err);
         CPR_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sts_top_place, g, b, 0, st, J, w, w.slot[1],
-                           w.slot[0], tc, tc + TOP_N);
+                           w.slot[0], w.tcnt, ntb);
         CPR_LAUNCH_CHECK();
         n0 = TOP_N;
         top = true;
@@ -1141,6 +1268,10 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
 }
 
 }  // namespace
+
+int64_t sts_top_counts(int64_t J) {
+  return (J + TOP_SPB - 1) / TOP_SPB * TOP_N;
+}
 
 // leaves per block of the build: LB x P doubles in at most 48 KiB of LDS
 int tree_leaf_shift(int R, int64_t P2) {
