@@ -750,8 +750,8 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
   __syncthreads();
   if (p0 < J) {
     double mm[TOP_N];
-#pragma unroll 1
-    for (int v = 0; v < TOP_N; ++v) {
+#pragma unroll 2
+    for (int v = 0; v < TOP_N; ++v) {  // two nodes' MFMA chains interleaved
       double qB[NT][KS];
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
@@ -1124,19 +1124,27 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
     }
     load_batch(bt + 1 < nb ? bt + 1 : bt);
     wave_lds_sync();
-#pragma unroll 1
-    for (int pp = 0; pp < PB; ++pp) {
-      const int r = bt * PB + pp;
-      const T *sp = stg + pp * 16 * RSU;
-      // G_{>k} fragments are read from LDS again in every pass rather than
-      // held in registers
-      asm volatile("" ::: "memory");
-      double gB[NT][KS], xA[KS];
+    // the PB rows' masses as independent MFMA chains; G_{>k} fragments are
+    // read from LDS again in every batch rather than held in registers
+    asm volatile("" ::: "memory");
+    double mr[PB];
+    {
+      double gB[NT][KS], xA[PB][KS];
       lds_bfrag_f<NT>(sG, gB);
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        xA[ks] = (double)sp[(l % 16) * RSU + 4 * ks + l / 16] * hA[ks];
-      const double m = tile_mass_t<NT>(xA, gB);  // lanes 0..15: row r of slot l
+      for (int pp = 0; pp < PB; ++pp)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          xA[pp][ks] = (double)stg[(pp * 16 + l % 16) * RSU + 4 * ks + l / 16] *
+                       hA[ks];
+#pragma unroll
+      for (int pp = 0; pp < PB; ++pp)
+        mr[pp] = tile_mass_t<NT>(xA[pp], gB);  // lanes 0..15: row of slot l
+    }
+#pragma unroll
+    for (int pp = 0; pp < PB; ++pp) {
+      const int r = bt * PB + pp;
+      const double m = mr[pp];
       if (pick < 0 && row0 + r < I && m > 0) {
         pre += m;
         lastpos = r;
