@@ -540,7 +540,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
 // zero row of X.
 // ---------------------------------------------------------------------------
 constexpr int SV_THREADS = 256;
-constexpr int SV_MAXBLK = 1024;
+constexpr int SV_RESBLK = 512;  // blocks resident at once (2 waves per SIMD)
 
 template <int NT>
 __device__ __forceinline__ double afrag(const double *A, int R, int t, int ks,
@@ -601,30 +601,38 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
     for (int v = 0; v < 4; ++v) ss[t][v] = 0.0;
   int nrows = 0;
   const int64_t ntiles = (I + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
-       tile < ntiles; tile += (int64_t)gridDim.x * (SV_THREADS / WAVE)) {
-    const int64_t row = tile * 16 + (l % 16);
-    const int64_t rc = row < I ? row : I - 1;
-    // G, G^+ fragments are read from LDS in every tile rather than held in
-    // registers
-    if (LDS) asm volatile("" ::: "memory");
-    // B fragments of M^T: M[row][4 ks + l / 16]
-    // all loads of the tile first (clamped), then masked by a product, not
-    // a select, so that no load is moved into a branch (branch-guarded loads
-    // wait one by one)
-    double mf[KS];
-    bool nz = false;
-    T raw[KS];
-    const T *mrow = M + rc * R;
+  const int64_t tstep = (int64_t)gridDim.x * (SV_THREADS / WAVE);
+  // B fragments of M^T: M[row][4 ks + l / 16], all loads of a tile issued
+  // together (clamped), the next tile's before the current tile's products;
+  // masked by a product, not a select, so that no load is moved into a
+  // branch (branch-guarded loads wait one by one)
+  T raw[KS];
+  auto load_tile = [&](int64_t tl) {
+    const int64_t rr = tl * 16 + (l % 16);
+    const T *mrow = M + (rr < I ? rr : I - 1) * R;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + l / 16;
       raw[ks] = mrow[k < R ? k : R - 1];
     }
+  };
+  int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
+  if (tile < ntiles) load_tile(tile);
+  for (; tile < ntiles; tile += tstep) {
+    const int64_t row = tile * 16 + (l % 16);
+    T cur[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) cur[ks] = raw[ks];
+    if (tile + tstep < ntiles) load_tile(tile + tstep);
+    // G, G^+ fragments are read from LDS in every tile rather than held in
+    // registers
+    if (LDS) asm volatile("" ::: "memory");
+    double mf[KS];
+    bool nz = false;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k = 4 * ks + l / 16;
-      mf[ks] = (double)raw[ks] * ((row < I && k < R) ? 1.0 : 0.0);
+      mf[ks] = (double)cur[ks] * ((row < I && k < R) ? 1.0 : 0.0);
       nz |= (mf[ks] != 0.0);
     }
     const uint64_t b = __ballot(nz);
@@ -840,8 +848,9 @@ void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
 }
 
 int solve_blocks(int64_t I) {
-  // about four 16-row tiles per block (one per wave) or more
-  return (int)std::min<int64_t>(SV_MAXBLK, std::max<int64_t>(1, (I + 63) / 64));
+  // four 16-row tiles per block (one per wave) or more: every block is
+  // resident, and a wave prefetches its next tile
+  return (int)std::min<int64_t>(SV_RESBLK, std::max<int64_t>(1, (I + 63) / 64));
 }
 
 template <typename T>
