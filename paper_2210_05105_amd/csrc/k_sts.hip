@@ -991,31 +991,32 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   __syncthreads();
   if (wv != 0) return;
   // placement of the block's 64 slots (lane i = slot pb + i): left children
-  // fill a node's range from the front, right children from the back
-  const bool a2 = pb + l < J;
+  // fill a node's range from the front, right children from the back.  The
+  // slots of one node are consecutive, so each node's first lane leads its
+  // group, and all groups reserve their slots with one atomic instruction
+  // per side (the leaders' lanes), waited for once.
+  const bool a2 = pb + l < J;  // the active lanes are a prefix
   const int32_t v2 = sh_v[l], b2 = sh_beg[l], e2 = sh_end[l];
   const bool r2 = sh_r[l] != 0;
-  uint64_t todo = __ballot(a2);
+  const int32_t vp = __shfl_up(v2, 1, WAVE);
+  const bool lead = a2 && (l == 0 || vp != v2);
+  const uint64_t leads = __ballot(lead), am = __ballot(a2);
   const uint64_t rm = __ballot(a2 && r2);
-  const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
-  int32_t pos = 0;
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    const int32_t v0 = __shfl(v2, leader, WAVE);
-    const uint64_t grp = __ballot(a2 && v2 == v0) & todo;
-    const uint64_t gl = grp & ~rm, gr = grp & rm;
-    int32_t bl = 0, br = 0;
-    if (l == leader) {
-      if (gl) bl = atomicAdd(&w.lc[cslot(v0)], (int32_t)__popcll(gl));
-      if (gr) br = atomicAdd(&w.rc[cslot(v0)], (int32_t)__popcll(gr));
-    }
-    bl = __shfl(bl, leader, WAVE);
-    br = __shfl(br, leader, WAVE);
-    if ((grp >> l) & 1ull)
-      pos = r2 ? e2 - 1 - (br + (int32_t)__popcll(gr & below))
-               : b2 + bl + (int32_t)__popcll(gl & below);
-    todo &= ~grp;
-  }
+  const uint64_t upto = (2ull << l) - 1;  // lanes 0 .. l
+  const uint64_t below = upto >> 1;       // lanes 0 .. l - 1
+  const uint64_t ldb = leads & upto;
+  const int myld = ldb ? 63 - __clzll((long long)ldb) : 0;
+  const uint64_t nxt = leads & ~upto;
+  const uint64_t gend = nxt ? ((1ull << __ffsll((long long)nxt) - 1) - 1) : ~0ull;
+  const uint64_t grp = am & gend & ~((1ull << myld) - 1);
+  const uint64_t gL = grp & ~rm, gR = grp & rm;
+  int32_t bl = 0, br = 0;
+  if (lead && gL) bl = atomicAdd(&w.lc[cslot(v2)], (int32_t)__popcll(gL));
+  if (lead && gR) br = atomicAdd(&w.rc[cslot(v2)], (int32_t)__popcll(gR));
+  bl = __shfl(bl, myld, WAVE);
+  br = __shfl(br, myld, WAVE);
+  const int32_t pos = r2 ? e2 - 1 - (br + (int32_t)__popcll(gR & below))
+                         : b2 + bl + (int32_t)__popcll(gL & below);
   if (a2) {
     out.s[pos] = sh_s[l];
     out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
