@@ -133,7 +133,9 @@ cp_status cp_sample(cp_ctx *ctx, int32_t mode, int64_t J,
 /*
  * cp_set_samples - use given draws instead of drawing (teacher forcing):
  * idx (device, J x (N-1) int32) and prob (device, J doubles, > 0).  Then
- * proceeds as cp_sample after its draws.
+ * proceeds as cp_sample after its draws.  An index out of range or a
+ * probability that is not finite and positive is a data error (CP_EINVAL
+ * from the next synchronising call).
  */
 cp_status cp_set_samples(cp_ctx *ctx, int32_t mode, int64_t J,
                          const int32_t *idx, const double *prob);

@@ -25,6 +25,7 @@ struct ProfEv {
 
 struct cp_ctx {
   int N = 0, R = 0, sampler = 0, precision = 0, F = 16;
+  int gram_mode = GRAM_F64;  // MFMA form of the factor Grams
   bool f64 = true;
   int64_t nnz = 0, max_J = 0;
   int64_t dims[MAXN] = {};
@@ -180,10 +181,14 @@ cp_status read_errors(cp_ctx *c) {
   if (e & ERR_NONFINITE) m += " non-finite value;";
   if (e & ERR_PINV) m += " pseudo-inverse did not converge;";
   if (e & ERR_CAPACITY) m += " capacity exceeded;";
+  if (e & ERR_PROB) m += " draw probability not finite and positive;";
+  // a non-finite value also empties the masses it feeds: the numeric cause
+  // is reported over the zero mass; bad input data over both
   cp_status st = CP_EINVAL;
-  if (e & (ERR_NONFINITE | ERR_PINV)) st = CP_ENUMERIC;
   if (e & ERR_ZERO_MASS) st = CP_EDEGENERATE;
-  if (e & (ERR_INDEX | ERR_DUP | ERR_UNIFORM | ERR_CAPACITY)) st = CP_EINVAL;
+  if (e & (ERR_NONFINITE | ERR_PINV)) st = CP_ENUMERIC;
+  if (e & (ERR_INDEX | ERR_DUP | ERR_UNIFORM | ERR_CAPACITY | ERR_PROB))
+    st = CP_EINVAL;
   throw Fail{st, m};
 }
 
@@ -246,7 +251,8 @@ void do_set_factor(cp_ctx *c, int mode, const double *Uin) {
                         c->d_err, c->s);
   {
     PhaseScope ps(c, PH_GRAM);
-    gram<T>(static_cast<T *>(c->U[mode]), I, c->R, c->G[mode], c->tmp, c->s);
+    gram<T>(static_cast<T *>(c->U[mode]), I, c->R, c->G[mode], c->tmp,
+            c->gram_mode, c->s);
   }
   rebuild_sampler<T>(c, mode);
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(MAXR), 0, c->s, c->sigma,
@@ -295,8 +301,8 @@ void do_set_samples(cp_ctx *c, int mode, int64_t J, const int32_t *idx,
                         hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
   hip_ok(hipMemcpyAsync(c->prob, prob, J * 8, hipMemcpyDeviceToDevice, c->s),
          "hipMemcpyAsync");
-  set_sample_rows<T>(ml, J, c->R, c->sidx, static_cast<T *>(c->h), c->d_err,
-                     c->s);
+  set_sample_rows<T>(ml, J, c->R, c->sidx, c->prob, static_cast<T *>(c->h),
+                     c->d_err, c->s);
   {
     PhaseScope ps(c, PH_DEDUP);
     lookup_columns(ml, J, c->sidx, c->ix[mode], c->w, c->s);
@@ -347,7 +353,8 @@ void do_solve(cp_ctx *c, int mode) {
   } else {
     {
       PhaseScope ps(c, PH_GRAM);
-      gram_scaled<T>(c->X, c->sigma, I, c->R, U, c->G[mode], c->tmp, c->s);
+      gram_scaled<T>(c->X, c->sigma, I, c->R, U, c->G[mode], c->tmp,
+                     c->gram_mode, c->s);
     }
     rebuild_sampler<T>(c, mode);
   }
@@ -384,6 +391,9 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   c->precision = cfg->precision;
   c->F = cfg->sts_leaf ? cfg->sts_leaf : 16;
   c->f64 = (c->precision == CP_FP64);
+  c->gram_mode = c->precision == CP_FP64   ? GRAM_F64
+                 : c->precision == CP_FP32 ? GRAM_F32
+                                           : GRAM_BF16X3;
   c->nnz = t->nnz;
   c->max_J = cfg->max_J;
   const int N = c->N, R = c->R;
@@ -395,7 +405,11 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
          "hipMemcpyAsync");
   validate_coo(t->idx, t->val, t->val_is_fp64, t->nnz, N, c->d_dims, c->d_err,
                c->s);
-  read_errors(c);
+  try {  // any defect of the input tensor is a bad argument
+    read_errors(c);
+  } catch (const Fail &f) {
+    throw Fail{CP_EINVAL, "invalid tensor: " + f.msg};
+  }
   // COO copy for the fit, values in the path's precision
   dalloc(c, &c->coo_idx, (size_t)t->nnz * N * 4);
   hip_ok(hipMemcpyAsync(c->coo_idx, t->idx, (size_t)t->nnz * N * 4,
@@ -581,8 +595,6 @@ cp_status cp_init(const cp_tensor *t, const cp_config *cfg, void *stream,
   if (cfg->sts_leaf != 0 && cfg->sts_leaf != 16 && cfg->sts_leaf != 32 &&
       cfg->sts_leaf != 64)
     return CP_EINVAL;
-  if (cfg->precision == CP_MIXED) return CP_EUNSUPPORTED;
-  if (cfg->sampler == CP_SAMPLER_STS && cfg->R > 64) return CP_EUNSUPPORTED;
   cp_ctx *c = new (std::nothrow) cp_ctx;
   if (!c) return CP_ENOMEM;
   c->s = static_cast<hipStream_t>(stream);

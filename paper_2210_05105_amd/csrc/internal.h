@@ -26,6 +26,7 @@ enum : uint32_t {
   ERR_NONFINITE = 16u, // NaN/Inf in a factor or value
   ERR_PINV = 32u,      // Jacobi eigen solver did not converge
   ERR_CAPACITY = 64u,  // a device-sized buffer would overflow
+  ERR_PROB = 128u,     // given draw probability not finite and > 0
 };
 
 // Profiling phases (order matches cp_phase_name).
@@ -91,14 +92,18 @@ void exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n,
 // ---- dense R x R and tall-skinny kernels (k_dense.hip)
 // Gram of U (I x R): partial Grams per block (FP64 MFMA), then a fixed-order
 // reduction into G (R x R).
+// mode: the MFMA form of the products for FP32 factors (FP64 factors always
+// use GRAM_F64): FP64, FP32, or BF16 hi/lo split with three products.
+enum GramMode { GRAM_F64 = 0, GRAM_F32 = 1, GRAM_BF16X3 = 2 };
 size_t gram_temp_bytes(int64_t I, int R);
 template <typename T>
-void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s);
+void gram(const T *U, int64_t I, int R, double *G, void *tmp, int mode,
+          hipStream_t s);
 // The same after the solve: U = X / sigma written in the factor's precision
 // (zero columns stay zero) by the pass that stages it, G of the stored U.
 template <typename T>
 void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
-                 double *G, void *tmp, hipStream_t s);
+                 double *G, void *tmp, int mode, hipStream_t s);
 // sigma[r] = sqrt of the sum over the nblk partial rows of column r
 void column_norms(const double *partial, int nblk, int R, double *sigma,
                   uint32_t *err, hipStream_t s);
@@ -211,7 +216,7 @@ int64_t bucket_tiles(int64_t rec_cap);
 size_t bucket_record_bytes(int tsize);
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
-                     T *h, uint32_t *err, hipStream_t s);
+                     const double *prob, T *h, uint32_t *err, hipStream_t s);
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
                     const ModeIndex &ix, SampleWork &w, hipStream_t s);
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,

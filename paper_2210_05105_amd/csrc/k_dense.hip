@@ -4,6 +4,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace cpr {
 
@@ -114,6 +115,160 @@ k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
       if (gi < R && gj < R) {
         out[gi * R + gj] = acc[i][v];
         out[gj * R + gi] = acc[i][v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram U^T U in reduced precision (FP32 factors).  The staged rows are FP32
+// in LDS; output tiles accumulate on FP32 MFMA in FP32, flushed into FP64
+// registers after every staged chunk (at most GL_ROWS rows of FP32
+// accumulation per flush), then per-block partials reduced in FP64 in a
+// fixed order as for the FP64 Gram.
+//   GRAM_F32:    v_mfma_f32_16x16x4f32 on the FP32 values.
+//   GRAM_BF16X3: each value split u = hi + lo into two BF16 numbers
+//                (round to nearest even); u_a u_b is taken as
+//                hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//                v_mfma_f32_16x16x16bf16 (products exact in FP32, relative
+//                error of the dropped lo_a lo_b term about 2^-16).
+// D layout of both FP32 MFMAs: lane l, element v holds D[4 (l / 16) + v]
+// [l % 16].
+// ---------------------------------------------------------------------------
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+constexpr int GL_ELEMS = 4096;  // staged FP32 entries per chunk (16 KiB)
+constexpr int GL_ROWS = 256;    // longest FP32 accumulation between flushes
+
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(short h) {
+  return __uint_as_float(((uint32_t)(uint16_t)h) << 16);
+}
+
+template <int MODE, int TPW, bool SCALE>
+__global__ void __launch_bounds__(GR_THREADS)
+k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
+          int64_t I, int R, int Rp, int64_t rows_per_blk, double *partial) {
+  extern __shared__ float ldsf[];  // RC x Rp
+  const int w = threadIdx.x / WAVE, l = lane_id();
+  const int nt = Rp / 16;
+  const int ntri = nt * (nt + 1) / 2;
+  int ta[TPW], tb[TPW];
+  float4_t acc[TPW];
+  double accd[TPW][4];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    int t = w + 4 * i;
+    ta[i] = tb[i] = -1;
+    acc[i] = float4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accd[i][v] = 0.0;
+    if (t < ntri) {
+      int a = 0, rem = t;
+      while (rem >= nt - a) { rem -= nt - a; ++a; }
+      ta[i] = a;
+      tb[i] = a + rem;
+    }
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = std::min<int64_t>(I, r0 + rows_per_blk);
+  // chunk rows: a multiple of 16 (the BF16 k-step), at most GL_ROWS
+  int RC = (GL_ELEMS / Rp) & ~15;
+  RC = RC < GL_ROWS ? RC : GL_ROWS;
+  const int NE = RC * Rp;
+  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS per entry
+  if constexpr (SCALE) {
+    for (int c = threadIdx.x; c < R; c += GR_THREADS) ssg[c] = sigma[c];
+    __syncthreads();
+  }
+  constexpr int PE = GL_ELEMS / GR_THREADS;
+  float v[PE];
+  auto load = [&](int64_t c0) {
+    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int e = q * GR_THREADS + threadIdx.x;
+      const int rr = e / Rp, cc = e - rr * Rp;
+      const int rc = rr < nrow ? rr : nrow - 1, ccc = cc < R ? cc : R - 1;
+      if constexpr (SCALE) {
+        const double x = X[(c0 + rc) * R + ccc];
+        const double sg = ssg[ccc];
+        v[q] = (float)(sg > 0 ? x / sg : 0.0);
+      } else {
+        v[q] = U[(c0 + rc) * R + ccc];
+      }
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += RC) {
+    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+      const int e = q * GR_THREADS + threadIdx.x;
+      const int rr = e / Rp, cc = e - rr * Rp;
+      const bool in = rr < nrow && cc < R;
+      if constexpr (SCALE)
+        if (in && e < NE) Uout[(c0 + rr) * R + cc] = v[q];
+      if (e < NE) ldsf[e] = in ? v[q] : 0.0f;
+    }
+    __syncthreads();
+    if (c0 + RC < r1) load(c0 + RC);
+    if constexpr (MODE == GRAM_F32) {
+      for (int k0 = 0; k0 < RC; k0 += 4) {
+        const float *rowp = ldsf + (k0 + l / 16) * Rp + (l % 16);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          if (ta[i] < 0) continue;
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              rowp[ta[i] * 16], rowp[tb[i] * 16], acc[i], 0, 0, 0);
+        }
+      }
+    } else {
+      for (int k0 = 0; k0 < RC; k0 += 16) {
+        const float *rowp = ldsf + (k0 + 4 * (l / 16)) * Rp + (l % 16);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          if (ta[i] < 0) continue;
+          short4_t ah, al, bh, bl;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float a = rowp[q * Rp + ta[i] * 16];
+            const float b = rowp[q * Rp + tb[i] * 16];
+            const short a1 = bf16_rne(a), b1 = bf16_rne(b);
+            ah[q] = a1;
+            bh[q] = b1;
+            al[q] = bf16_rne(a - bf16_val(a1));
+            bl[q] = bf16_rne(b - bf16_val(b1));
+          }
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[i], 0, 0, 0);
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[i], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {  // flush the chunk's FP32 sums
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) accd[i][vv] += (double)acc[i][vv];
+      acc[i] = float4_t{0, 0, 0, 0};
+    }
+  }
+  double *out = partial + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    if (ta[i] < 0) continue;
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) {
+      const int gi = ta[i] * 16 + 4 * (l / 16) + vv;
+      const int gj = tb[i] * 16 + (l % 16);
+      if (gi < R && gj < R) {
+        out[gi * R + gj] = accd[i][vv];
+        out[gj * R + gi] = accd[i][vv];
       }
     }
   }
@@ -782,13 +937,42 @@ size_t gram_temp_bytes(int64_t I, int R) {
 
 template <typename T, bool SCALE>
 void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
-              int64_t I, int R, double *G, void *tmp, hipStream_t s) {
+              int64_t I, int R, double *G, void *tmp, int mode,
+              hipStream_t s) {
   int64_t rpb;
   const int nblk = gram_blocks(I, &rpb);
   const int Rp = (R + 15) / 16 * 16;
   const int nt = Rp / 16, ntri = nt * (nt + 1) / 2;
   const int tpw = (ntri + 3) / 4;
   double *partial = static_cast<double *>(tmp);
+  if constexpr (std::is_same<T, float>::value) {
+    if (mode != GRAM_F64) {
+#define CPR_GRAM_LP(M, K)                                                    \
+  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE>), dim3(nblk), dim3(GR_THREADS), \
+                     GL_ELEMS * sizeof(float), s, U, X, sigma, Uout, I, R,   \
+                     Rp, rpb, partial)
+#define CPR_GRAM_LP_T(M)                        \
+  switch (tpw) {                                \
+    case 1: CPR_GRAM_LP(M, 1); break;           \
+    case 2: CPR_GRAM_LP(M, 2); break;           \
+    case 3: CPR_GRAM_LP(M, 3); break;           \
+    case 4: CPR_GRAM_LP(M, 4); break;           \
+    case 6: case 5: CPR_GRAM_LP(M, 6); break;   \
+    default: CPR_GRAM_LP(M, 9); break;          \
+  }
+      if (mode == GRAM_F32) {
+        CPR_GRAM_LP_T(GRAM_F32)
+      } else {
+        CPR_GRAM_LP_T(GRAM_BF16X3)
+      }
+#undef CPR_GRAM_LP_T
+#undef CPR_GRAM_LP
+      CPR_LAUNCH_CHECK();
+      colsum(partial, nblk, R * R, G, 0, nullptr, s);
+      CPR_LAUNCH_CHECK();
+      return;
+    }
+  }
 #define CPR_GRAM(K) \
   launch_gram<T, K, SCALE>(U, X, sigma, Uout, I, R, Rp, partial, nblk, rpb, s)
   switch (tpw) {
@@ -805,23 +989,24 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
 }
 
 template <typename T>
-void gram(const T *U, int64_t I, int R, double *G, void *tmp, hipStream_t s) {
-  gram_any<T, false>(U, nullptr, nullptr, nullptr, I, R, G, tmp, s);
+void gram(const T *U, int64_t I, int R, double *G, void *tmp, int mode,
+          hipStream_t s) {
+  gram_any<T, false>(U, nullptr, nullptr, nullptr, I, R, G, tmp, mode, s);
 }
-template void gram<float>(const float *, int64_t, int, double *, void *,
+template void gram<float>(const float *, int64_t, int, double *, void *, int,
                           hipStream_t);
 template void gram<double>(const double *, int64_t, int, double *, void *,
-                           hipStream_t);
+                           int, hipStream_t);
 
 template <typename T>
 void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
-                 double *G, void *tmp, hipStream_t s) {
-  gram_any<T, true>(nullptr, X, sigma, U, I, R, G, tmp, s);
+                 double *G, void *tmp, int mode, hipStream_t s) {
+  gram_any<T, true>(nullptr, X, sigma, U, I, R, G, tmp, mode, s);
 }
 template void gram_scaled<float>(const double *, const double *, int64_t, int,
-                                 float *, double *, void *, hipStream_t);
+                                 float *, double *, void *, int, hipStream_t);
 template void gram_scaled<double>(const double *, const double *, int64_t,
-                                  int, double *, double *, void *,
+                                  int, double *, double *, void *, int,
                                   hipStream_t);
 
 void column_norms(const double *partial, int nblk, int R, double *sigma,

@@ -27,11 +27,16 @@ constexpr int BK_TILE = 4096;  // positions per scatter tile
 
 template <typename T>
 __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
-                              const int32_t *sidx, T *h, uint32_t *err) {
+                              const int32_t *sidx, const double *prob, T *h,
+                              uint32_t *err) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= J * R) return;
   const int64_t s = e / R;
   const int r = (int)(e - s * R);
+  if (r == 0) {  // a draw's weight is count / (J p): p must be finite, > 0
+    const double p = prob[s];
+    if (!(p > 0.0 && p <= 1.7976931348623157e308)) atomicOr(err, ERR_PROB);
+  }
   double v = 1.0;
   for (int q = 0; q < ml.n; ++q) {
     int32_t i = sidx[s * ml.n + q];
@@ -800,17 +805,17 @@ int mttkrp_grid() { return 256 * 8; }
 
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
-                     T *h, uint32_t *err, hipStream_t s) {
+                     const double *prob, T *h, uint32_t *err, hipStream_t s) {
   hipLaunchKernelGGL((k_sample_rows<T>), dim3(ceil_div(J * R, 256)), dim3(256),
-                     0, s, ml, J, R, sidx, h, err);
+                     0, s, ml, J, R, sidx, prob, h, err);
   CPR_LAUNCH_CHECK();
 }
 template void set_sample_rows<float>(const ModeList &, int64_t, int,
-                                     const int32_t *, float *, uint32_t *,
-                                     hipStream_t);
+                                     const int32_t *, const double *, float *,
+                                     uint32_t *, hipStream_t);
 template void set_sample_rows<double>(const ModeList &, int64_t, int,
-                                      const int32_t *, double *, uint32_t *,
-                                      hipStream_t);
+                                      const int32_t *, const double *,
+                                      double *, uint32_t *, hipStream_t);
 
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
                     const ModeIndex &ix, SampleWork &w, hipStream_t s) {

@@ -1212,19 +1212,508 @@ k_sts_final(int R, int64_t J, const double *hbuf, const double *Gp,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide ranks (NT >= 5, R > 64).  The kernels above hold a whole symmetric
+// Q in MFMA fragments (NT (NT + 1) / 2 blocks of 4 k-steps per lane), which
+// past NT = 4 exceeds the register file.  Here the fragments are streamed
+// tile by tile: G_{>k} (or G^+) from LDS in fragment order, a node product
+// G_{>k} (*) G^node formed on the way from the tree's packed node and the
+// LDS fragment.  The 16-row X tiles (h rows, factor rows) are read from
+// global memory directly in A-fragment layout, so LDS holds only the
+// fragments (57 KiB at NT = 7, 74 KiB at NT = 8).
+// ---------------------------------------------------------------------------
+constexpr int WNT_MIN = 5;
+
+// x^T Q x of the 16 rows of X (lane l: row l % 16) for Q given by its
+// fragments in LDS (stage_bfrag layout): as tile_mass_t, one tile at a time.
+template <int NT>
+__device__ __forceinline__ double tile_mass_s(const double (&xA)[4 * NT],
+                                              const double *sF) {
+  const int l = lane_id();
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double4_t acc = double4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 4 * (t + 1); ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+          sF[(2 * t * (t + 1) + ks) * WAVE + l], xA[ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s = fma(acc[v], xA[4 * t + v], s);
+    // keep each tile's fragment loads next to its MFMAs (bounded registers)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  s += __shfl_xor(s, 16, WAVE);
+  s += __shfl_xor(s, 32, WAVE);
+  return s;
+}
+
+// The same for Q = G_{>k} (*) G^node with the node's packed upper triangle
+// nd (global) and the G_{>k} fragments sG (LDS, off-diagonal blocks doubled).
+// A lane id the compiler cannot see through: index arithmetic derived from
+// it stays inside the loop that uses it instead of being hoisted out as
+// loop-invariant registers (one per fragment).
+__device__ __forceinline__ int opaque_lane() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return lane_id() + z;
+}
+
+template <int NT>
+__device__ __forceinline__ double tile_mass_node(const double (&xA)[4 * NT],
+                                                 const double *nd,
+                                                 const double *sG) {
+  constexpr int RP = 16 * NT;
+  const int l = opaque_lane();
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double q[4 * NT];
+#pragma unroll
+    for (int ks = 0; ks < 4 * (t + 1); ++ks) {  // tile t's loads together
+      const int k = 4 * ks + l / 16, j = 16 * t + (l % 16);
+      q[ks] = nd[k <= j ? packed_index(k, j, RP) : packed_index(j, k, RP)];
+    }
+    double4_t acc = double4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 4 * (t + 1); ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+          q[ks] * sG[(2 * t * (t + 1) + ks) * WAVE + l], xA[ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) s = fma(acc[v], xA[4 * t + v], s);
+    __builtin_amdgcn_sched_barrier(0);  // one tile's node loads at a time
+  }
+  s += __shfl_xor(s, 16, WAVE);
+  s += __shfl_xor(s, 32, WAVE);
+  return s;
+}
+
+// A-fragment of the 16 h rows (FP64, row stride RP, zeros beyond R) of the
+// samples held by lanes 0..15 (s: this lane's sample; lane l takes row
+// l % 16): xA[ks] = h[sample of row l % 16][4 ks + l / 16].
+template <int NT>
+__device__ __forceinline__ void load_hfrag_direct(const double *hb, int32_t s,
+                                                  double (&xA)[4 * NT]) {
+  constexpr int RP = 16 * NT;
+  const int l = lane_id();
+  const int32_t sr = __shfl(s, l % 16, WAVE);
+  const double *row = hb + (int64_t)sr * RP + l / 16;
+#pragma unroll
+  for (int ks = 0; ks < 4 * NT; ++ks) xA[ks] = row[4 * ks];
+}
+
+// First factor, wide ranks: as k_sts_mass with each wave's 16 factor rows
+// read straight into A fragments.
+template <typename T, int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_mass_w(const T *U, int64_t I, int R, const double *Gg, int gshift,
+             double *lev, double *sub, double *grp, uint32_t *err) {
+  constexpr int KS = 4 * NT;
+  static_assert(FIRST_SUB == 16 * (ST / WAVE), "one row tile per wave");
+  __shared__ double sG[bfrag_count<NT>() * WAVE];
+  __shared__ double wsum[ST / WAVE];
+  stage_bfrag<NT>(sG, Gg, R);
+  __syncthreads();
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  const int64_t nsub = (I + FIRST_SUB - 1) / FIRST_SUB;
+  const int64_t sb0 = (int64_t)blockIdx.x << gshift;
+  const int64_t sb1 = sb0 + (int64_t(1) << gshift) < nsub
+                          ? sb0 + (int64_t(1) << gshift) : nsub;
+  double gs = 0.0;
+  for (int64_t sb = sb0; sb < sb1; ++sb) {
+    const int64_t row0 = sb * FIRST_SUB + 16 * wv;
+    const int64_t r = row0 + (l % 16);
+    const double rm = r < I ? 1.0 : 0.0;
+    const T *src = U + (r < I ? r : I - 1) * R;
+    T raw[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {  // clamped loads first, then masked
+      const int c = 4 * ks + l / 16;
+      raw[ks] = src[c < R ? c : R - 1];
+    }
+    double xA[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      xA[ks] = (4 * ks + l / 16 < R) ? (double)raw[ks] * rm : 0.0;
+    double m = tile_mass_s<NT>(xA, sG);  // lanes 0..15: row row0 + l
+    if (l < 16 && r < I && !isfinite(m)) atomicOr(err, ERR_NONFINITE);
+    m = (l < 16 && r < I && m > 0) ? m : 0.0;
+    if (l < 16) lev[row0 + l] = m;  // rows past I (up to the allocation) get 0
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) m += __shfl_xor(m, o, WAVE);
+    if (l == 0) wsum[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < ST / WAVE; ++q) x += wsum[q];
+      sub[sb] = x;
+      gs += x;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grp[blockIdx.x] = gs;
+}
+
+// Root of a tree factor, wide ranks (as k_sts_root).
+template <int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_root_w(const double *tree, const double *Gg, int64_t P2, int R,
+             const double *uni, int q, int nq, int64_t J, StsWork w,
+             SlotBuf out, uint32_t *err) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  __shared__ double sG[bfrag_count<NT>() * WAVE];
+  const int64_t g0 = (int64_t)blockIdx.x * ST + threadIdx.x;
+  for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * ST) {
+    w.lc[i] = 0;
+    w.rc[i] = 0;
+  }
+  if (g0 == 0) {
+    w.sbeg[1] = 0;
+    w.send[1] = (int32_t)J;
+  }
+  stage_bfrag<NT>(sG, Gg, R);
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
+  if (p0 >= J) return;
+  const int64_t g = p0 + l;
+  const bool act = l < 16 && g < J;
+  const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
+  double xA[4 * NT];
+  load_hfrag_direct<NT>(w.h, s, xA);
+  const double Z = tile_mass_node<NT>(xA, tree + P, sG);
+  if (!act) return;
+  double u = uni[g * nq + q];
+  if (!(u >= 0.0 && u < 1.0)) {
+    atomicOr(err, ERR_UNIFORM);
+    u = 0.0;
+  }
+  if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
+  out.s[g] = (int32_t)g;
+  out.v[g] = 1;
+  out.t[g] = u * Z;
+  out.m[g] = Z;
+}
+
+// One level, wide ranks (as k_sts_level; the mass of each distinct node's
+// left child streamed from the tree).
+template <int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
+              StsWork w, SlotBuf in, SlotBuf out) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  __shared__ int32_t sh_s[64], sh_v[64], sh_beg[64], sh_end[64];
+  __shared__ double sh_t[64], sh_m[64];
+  __shared__ int32_t sh_r[64];
+  __shared__ double sG[bfrag_count<NT>() * WAVE];  // G_{>k}, zeros beyond R
+  const int64_t pb = (int64_t)blockIdx.x * 64;
+  if (pb >= J) return;
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  const int64_t p = pb + 16 * wv + l;
+  const bool act = l < 16 && p < J;
+  const int64_t pc = p < J ? p : J - 1;
+  const int32_t s = in.s[pc];
+  const int32_t v = in.v[pc];
+  double t = in.t[pc], m = in.m[pc];
+  stage_bfrag<NT>(sG, Gg, R);
+  const int32_t par = v > 1 ? v >> 1 : 1;
+  const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
+  double xA[4 * NT];
+  load_hfrag_direct<NT>(w.h, s, xA);
+  __syncthreads();
+  const uint64_t actm = __ballot(act);
+  const int32_t beg = v == 1 ? pbg : (v & 1) ? pbg + nl : pbg;
+  const int32_t end = v == 1 ? pen : (v & 1) ? pen : pbg + nl;
+  if (act && p == beg) {
+    w.sbeg[v] = beg;
+    w.send[v] = end;
+  }
+  double mL = 0.0;
+  uint64_t rem = actm;
+  while (rem) {
+    const int32_t v0 = __shfl(v, __ffsll((long long)rem) - 1, WAVE);
+    const uint64_t grp = __ballot(v == v0) & rem;
+    // G_{>k} fragments are read from LDS in every pass, not hoisted into
+    // registers
+    asm volatile("" ::: "memory");
+    const double x = tile_mass_node<NT>(xA, tree + (int64_t)(2 * v0) * P, sG);
+    if ((grp >> l) & 1ull) mL = x;
+    rem &= ~grp;
+  }
+  const bool right = mL <= 0 || (t >= mL && m - mL > 0);
+  if (right) {
+    t -= (mL > 0 ? mL : 0.0);
+    m -= mL;
+  } else {
+    m = mL;
+  }
+  if (l < 16) {
+    const int i = 16 * wv + l;
+    sh_s[i] = s;
+    sh_v[i] = v;
+    sh_beg[i] = beg;
+    sh_end[i] = end;
+    sh_t[i] = t;
+    sh_m[i] = m;
+    sh_r[i] = right ? 1 : 0;
+  }
+  __syncthreads();
+  if (wv != 0) return;
+  // placement of the block's 64 slots, as in k_sts_level
+  const bool a2 = pb + l < J;
+  const int32_t v2 = sh_v[l], b2 = sh_beg[l], e2 = sh_end[l];
+  const bool r2 = sh_r[l] != 0;
+  const int32_t vp = __shfl_up(v2, 1, WAVE);
+  const bool lead = a2 && (l == 0 || vp != v2);
+  const uint64_t leads = __ballot(lead), am = __ballot(a2);
+  const uint64_t rm = __ballot(a2 && r2);
+  const uint64_t upto = (2ull << l) - 1;
+  const uint64_t below = upto >> 1;
+  const uint64_t ldb = leads & upto;
+  const int myld = ldb ? 63 - __clzll((long long)ldb) : 0;
+  const uint64_t nxt = leads & ~upto;
+  const uint64_t gend = nxt ? ((1ull << __ffsll((long long)nxt) - 1) - 1) : ~0ull;
+  const uint64_t grp = am & gend & ~((1ull << myld) - 1);
+  const uint64_t gL = grp & ~rm, gR = grp & rm;
+  int32_t bl = 0, br = 0;
+  if (lead && gL) bl = atomicAdd(&w.lc[cslot(v2)], (int32_t)__popcll(gL));
+  if (lead && gR) br = atomicAdd(&w.rc[cslot(v2)], (int32_t)__popcll(gR));
+  bl = __shfl(bl, myld, WAVE);
+  br = __shfl(br, myld, WAVE);
+  const int32_t pos = r2 ? e2 - 1 - (br + (int32_t)__popcll(gR & below))
+                         : b2 + bl + (int32_t)__popcll(gL & below);
+  if (a2) {
+    out.s[pos] = sh_s[l];
+    out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
+    out.t[pos] = sh_t[l];
+    out.m[pos] = sh_m[l];
+  }
+}
+
+// Leaf, wide ranks (as k_sts_leaf): one wave per 16 slots, one leaf row of
+// every slot per pass, the next row's values in flight during the pass.
+template <typename T, int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_leaf_w(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
+             int64_t J, StsWork w, SlotBuf in, int q, int nq, int32_t *sidx,
+             uint32_t *err) {
+  constexpr int RP = 16 * NT, KS = 4 * NT;
+  __shared__ double sG[bfrag_count<NT>() * WAVE];
+  stage_bfrag<NT>(sG, Gg, R);
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
+  if (p0 >= J) return;
+  const int n = J - p0 < 16 ? (int)(J - p0) : 16;
+  const int64_t ps = p0 + ((l % 16) < n ? (l % 16) : 0);
+  const int32_t s = in.s[ps];
+  const int64_t row0 = (int64_t)(in.v[ps] - P2) * F;
+  const double t = in.t[ps];
+  double hA[KS];
+  load_hfrag_direct<NT>(w.h, s, hA);
+  // lane l reads row row0 + r of slot l % 16, columns 4 ks + l / 16
+  auto load_row = [&](int r, T (&x)[KS]) {
+    const int64_t row = row0 + r;
+    const T *src = U + (row < I ? row : I - 1) * R;
+    const int lz = opaque_lane();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + lz / 16;
+      x[ks] = src[c < R ? c : R - 1];
+    }
+  };
+  double pre = 0.0;
+  int pick = -1, lastpos = -1;
+  T nx[KS];
+  load_row(0, nx);
+  for (int r = 0; r < F; ++r) {
+    double xA[KS];
+    const double rm = row0 + r < I ? 1.0 : 0.0;
+    const int lz = opaque_lane();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      xA[ks] = (4 * ks + lz / 16 < R) ? (double)nx[ks] * hA[ks] * rm : 0.0;
+    load_row(r + 1 < F ? r + 1 : r, nx);
+    asm volatile("" ::: "memory");  // G_{>k} fragments re-read per row
+    const double mm = tile_mass_s<NT>(xA, sG);  // lanes 0..15: slot l
+    if (pick < 0 && row0 + r < I && mm > 0) {
+      pre += mm;
+      lastpos = r;
+      if (t < pre) pick = r;
+    }
+  }
+  const bool act = l < n;
+  if (pick < 0) {
+    pick = lastpos;
+    if (pick < 0) {
+      pick = 0;
+      if (act) atomicOr(err, ERR_ZERO_MASS);
+    }
+  }
+  int64_t idx = row0 + pick;
+  if (idx >= I) idx = I - 1;
+  if (act) sidx[(int64_t)s * nq + q] = (int32_t)idx;
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {  // 16 RP entries, 64 per pass
+    const int e = it * WAVE + l, k = e / RP, a = e % RP;
+    const int64_t sk = __shfl(s, k, WAVE), ik = __shfl(idx, k, WAVE);
+    if (k < n) {
+      const int ac = a < R ? a : R - 1;
+      const double x = w.h[sk * RP + a] * (double)U[ik * R + ac];
+      w.h[sk * RP + a] = a < R ? x : 0.0;
+    }
+  }
+}
+
+// Probabilities and h rows in the path precision, wide ranks (as k_sts_final).
+template <typename T, int NT>
+__global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_final_w(int R, int64_t J, const double *hbuf, const double *Gp,
+              const double *trace, double *prob, T *h_out) {
+  constexpr int RP = 16 * NT;
+  __shared__ double sP[bfrag_count<NT>() * WAVE];
+  stage_bfrag<NT>(sP, Gp, R);
+  __syncthreads();
+  const int l = lane_id();
+  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
+  if (p0 >= J) return;
+  const int n = J - p0 < 16 ? (int)(J - p0) : 16;
+  const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
+  double xA[4 * NT];
+  load_hfrag_direct<NT>(hbuf, s, xA);
+  const double mass = tile_mass_s<NT>(xA, sP);
+  if (l < n) prob[p0 + l] = mass / *trace;
+  const int ne = n * R;
+  double hv[RP / 4];
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {
+    const int e = it * WAVE + l < ne ? it * WAVE + l : ne - 1;
+    hv[it] = hbuf[(p0 + e / R) * RP + e % R];
+  }
+#pragma unroll
+  for (int it = 0; it < RP / 4; ++it) {
+    const int e = it * WAVE + l;
+    if (e < ne) h_out[(p0 + e / R) * R + e % R] = (T)hv[it];
+  }
+}
+
+// Tree leaves, wide ranks: one leaf per block, the NT (NT + 1) / 2 tiles of
+// its Gram split over the 4 waves (tile i to wave i % 4); every wave reads
+// the leaf's rows, wave 0 writes the renormalised factor (SCALE).  Internal
+// nodes come from k_tree_up.
+template <typename T, int NT, bool SCALE, int W>
+__device__ __forceinline__ void leaf_tiles(const T *U, const double *X,
+                                           const double (&sg)[NT], T *Uout,
+                                           int64_t I, int R, int F,
+                                           int64_t leaf, double *node) {
+  constexpr int NTRI = NT * (NT + 1) / 2, RP = 16 * NT;
+  constexpr int NMY = (NTRI - W + 3) / 4;  // tiles of this wave
+  const int l = lane_id();
+  double4_t acc[NMY > 0 ? NMY : 1];
+#pragma unroll
+  for (int i = 0; i < (NMY > 0 ? NMY : 1); ++i) acc[i] = double4_t{0, 0, 0, 0};
+  const int64_t rbase = leaf * F;
+  for (int k0 = 0; k0 < F; k0 += 16) {
+    double col[4][NT];
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int64_t r = rbase + k0 + 4 * qq + l / 16;
+      const int64_t ro = (r < I ? r : I - 1) * R;
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta) {
+        const int ca = ta * 16 + (l % 16);
+        const int cc = ca < R ? ca : R - 1;
+        if constexpr (SCALE) col[qq][ta] = X[ro + cc];
+        else col[qq][ta] = (double)U[ro + cc];
+      }
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int64_t r = rbase + k0 + 4 * qq + l / 16;
+      const double rm = r < I ? 1.0 : 0.0;
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta) {
+        const int ca = ta * 16 + (l % 16);
+        double x = col[qq][ta];
+        if constexpr (SCALE) {
+          const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
+          if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
+          x = (double)u;
+        }
+        col[qq][ta] = x * (ca < R ? rm : 0.0);
+      }
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < NT; ++tb) {
+          const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+          if (i % 4 == W)
+            acc[i / 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                col[qq][ta], col[qq][tb], acc[i / 4], 0, 0, 0);
+        }
+  }
+#pragma unroll
+  for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+    for (int tb = ta; tb < NT; ++tb) {
+      const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+      if (i % 4 == W) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ga = ta * 16 + (l / 16) + 4 * v;
+          const int gb = tb * 16 + (l % 16);
+          if (ga <= gb) node[packed_index(ga, gb, RP)] = acc[i / 4][v];
+        }
+      }
+    }
+}
+
+template <typename T, int NT, bool SCALE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_tree_build_w(const T *U, const double *X, const double *sigma, T *Uout,
+               int64_t I, int R, int F, int64_t P2, double *tree) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  const int l = lane_id();
+  double sg[NT];
+#pragma unroll
+  for (int ta = 0; ta < NT; ++ta) {
+    const int ca = ta * 16 + (l % 16);
+    sg[ta] = SCALE ? sigma[ca < R ? ca : R - 1] : 1.0;
+  }
+  const int64_t leaf = blockIdx.x;
+  double *node = tree + (P2 + leaf) * (int64_t)P;
+  switch (threadIdx.x / WAVE) {
+    case 0: leaf_tiles<T, NT, SCALE, 0>(U, X, sg, Uout, I, R, F, leaf, node); break;
+    case 1: leaf_tiles<T, NT, SCALE, 1>(U, X, sg, Uout, I, R, F, leaf, node); break;
+    case 2: leaf_tiles<T, NT, SCALE, 2>(U, X, sg, Uout, I, R, F, leaf, node); break;
+    default: leaf_tiles<T, NT, SCALE, 3>(U, X, sg, Uout, I, R, F, leaf, node); break;
+  }
+}
+
 template <typename T, int NT>
 void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
              const double *Gp, const double *trace, int32_t *sidx,
              double *prob, T *h, const StsWork &w, uint32_t *err,
              hipStream_t st) {
+  constexpr bool WIDE = NT >= WNT_MIN;
   const int nq = ml.n;
   const dim3 g(ceil_div(J, ST)), b(ST), gl(ceil_div(J, 16 * (ST / WAVE)));
   const int64_t I0 = ml.I[0];
   const int gs = first_gshift(I0);
   double *grp = w.sub + first_nsub(I0);
-  hipLaunchKernelGGL((k_sts_mass<T, NT>), dim3((unsigned)first_ngroups(I0)), b,
-                     0, st, static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0],
-                     gs, w.lev, w.sub, grp, err);
+  const dim3 gm((unsigned)first_ngroups(I0));
+  if constexpr (WIDE)
+    hipLaunchKernelGGL((k_sts_mass_w<T, NT>), gm, b, 0, st,
+                       static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0], gs,
+                       w.lev, w.sub, grp, err);
+  else
+    hipLaunchKernelGGL((k_sts_mass<T, NT>), gm, b, 0, st,
+                       static_cast<const T *>(ml.U[0]), I0, R, ml.Ggt[0], gs,
+                       w.lev, w.sub, grp, err);
   CPR_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_sts_first<T, NT>), g, b, 0, st,
                      static_cast<const T *>(ml.U[0]), I0, R, w.lev, w.sub, grp,
@@ -1251,28 +1740,46 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
       }
     }
     if (!top) {
-      hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R, uni,
-                         q, nq, J, w, w.slot[0], err);
+      if constexpr (WIDE)
+        hipLaunchKernelGGL((k_sts_root_w<NT>), gl, b, 0, st, tree, Gg, P2, R,
+                           uni, q, nq, J, w, w.slot[0], err);
+      else
+        hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R,
+                           uni, q, nq, J, w, w.slot[0], err);
       CPR_LAUNCH_CHECK();
     }
     for (int64_t n = n0; n < P2; n <<= 1) {
-      hipLaunchKernelGGL((k_sts_level<NT>), gl, b, 0, st, tree, Gg, R, J, w,
-                         w.slot[cur], w.slot[cur ^ 1]);
+      if constexpr (WIDE)
+        hipLaunchKernelGGL((k_sts_level_w<NT>), gl, b, 0, st, tree, Gg, R, J,
+                           w, w.slot[cur], w.slot[cur ^ 1]);
+      else
+        hipLaunchKernelGGL((k_sts_level<NT>), gl, b, 0, st, tree, Gg, R, J, w,
+                           w.slot[cur], w.slot[cur ^ 1]);
       CPR_LAUNCH_CHECK();
       cur ^= 1;
     }
-    if (R % (16 / (int)sizeof(T)) == 0)
-      hipLaunchKernelGGL((k_sts_leaf<T, NT, true>), gl, b, 0, st,
-                         static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2,
-                         Gg, J, w, w.slot[cur], q, nq, sidx, err);
-    else
-      hipLaunchKernelGGL((k_sts_leaf<T, NT, false>), gl, b, 0, st,
-                         static_cast<const T *>(ml.U[q]), ml.I[q], R, F, P2,
-                         Gg, J, w, w.slot[cur], q, nq, sidx, err);
+    const T *Uq = static_cast<const T *>(ml.U[q]);
+    if constexpr (WIDE) {
+      hipLaunchKernelGGL((k_sts_leaf_w<T, NT>), gl, b, 0, st, Uq, ml.I[q], R,
+                         F, P2, Gg, J, w, w.slot[cur], q, nq, sidx, err);
+    } else {
+      if (R % (16 / (int)sizeof(T)) == 0)
+        hipLaunchKernelGGL((k_sts_leaf<T, NT, true>), gl, b, 0, st, Uq,
+                           ml.I[q], R, F, P2, Gg, J, w, w.slot[cur], q, nq,
+                           sidx, err);
+      else
+        hipLaunchKernelGGL((k_sts_leaf<T, NT, false>), gl, b, 0, st, Uq,
+                           ml.I[q], R, F, P2, Gg, J, w, w.slot[cur], q, nq,
+                           sidx, err);
+    }
     CPR_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL((k_sts_final<T, NT>), gl, b, 0, st, R, J, w.h, Gp, trace,
-                     prob, h);
+  if constexpr (WIDE)
+    hipLaunchKernelGGL((k_sts_final_w<T, NT>), gl, b, 0, st, R, J, w.h, Gp,
+                       trace, prob, h);
+  else
+    hipLaunchKernelGGL((k_sts_final<T, NT>), gl, b, 0, st, R, J, w.h, Gp,
+                       trace, prob, h);
   CPR_LAUNCH_CHECK();
 }
 
@@ -1296,14 +1803,19 @@ template <typename T, bool SCALE>
 void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
                 int64_t I, int R, int F, int64_t P2, double *tree, double *G,
                 hipStream_t s) {
-  const int lb = tree_leaf_shift(R, P2);
+  const int nt = (R + 15) / 16;
+  const int lb = nt >= WNT_MIN ? 0 : tree_leaf_shift(R, P2);
   const size_t lds = ((size_t)1 << lb) * sts_packed(R) * 8;
   const dim3 g((unsigned)(P2 >> lb)), b(256);
-  switch ((R + 15) / 16) {
+  switch (nt) {
     case 1: hipLaunchKernelGGL((k_tree_build<T, 1, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
     case 2: hipLaunchKernelGGL((k_tree_build<T, 2, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
     case 3: hipLaunchKernelGGL((k_tree_build<T, 3, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
-    default: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 4: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 5: hipLaunchKernelGGL((k_tree_build_w<T, 5, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
+    case 6: hipLaunchKernelGGL((k_tree_build_w<T, 6, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
+    case 7: hipLaunchKernelGGL((k_tree_build_w<T, 7, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
+    default: hipLaunchKernelGGL((k_tree_build_w<T, 8, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
   }
   CPR_LAUNCH_CHECK();
   // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1
@@ -1352,7 +1864,11 @@ void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,
     case 1: draw_nt<T, 1>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
     case 2: draw_nt<T, 2>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
     case 3: draw_nt<T, 3>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    default: draw_nt<T, 4>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 4: draw_nt<T, 4>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 5: draw_nt<T, 5>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 6: draw_nt<T, 6>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 7: draw_nt<T, 7>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    default: draw_nt<T, 8>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
   }
 }
 template void sts_draw<float>(const ModeList &, int64_t, int, int,

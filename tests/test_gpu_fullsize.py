@@ -57,7 +57,8 @@ def test_fullsize_mode_solve(big):
     # (1) draws: a random subset against the exact conditional inverse CDF
     S = np.sort(rng.choice(J, 256, replace=False))
     oidx, oprob, _ = O.sts_sample(U, G, j, u[S], block=64)
-    compare_sts_indices(gidx[S], oidx, U, G, j, u[S])
+    n_acc = compare_sts_indices(gidx[S], oidx, U, G, j, u[S])
+    assert n_acc <= 2, n_acc  # in-band mismatches are rare: 256 draws
     same = np.all(gidx[S] == oidx, axis=1)
     others = [G[k] for k in range(len(dims)) if k != j]
     others.append(O.gram_hadamard(G, j))
