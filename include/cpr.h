@@ -239,6 +239,19 @@ const char *cp_phase_name(int32_t phase);
 cp_status cp_pinv(const double *G, int32_t R, double *Gp, void *stream);
 
 /*
+ * cp_pinv_noalloc - cp_pinv for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as cp_pinv (R > 128:
+ * CP_EINVAL), but no allocation: its scratch (the Hadamard copy, the
+ * eigen-solver work and the error word; 2 x 128 x 128 doubles + 256 bytes)
+ * is a static device array, one per GPU, held until the process ends.  All
+ * calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams, other host threads) race.  Synchronising.
+ */
+cp_status cp_pinv_noalloc(const double *G, int32_t R, double *Gp,
+                          void *stream);
+
+/*
  * cp_counters - cumulative work counters (host out, 4 int64): sampled mode
  * solves, distinct sampled columns, extracted nonzeros, nonzero rows of the
  * solved factors.  Synchronising; reset != 0 zeroes them afterwards.

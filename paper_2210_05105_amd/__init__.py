@@ -6,7 +6,7 @@ the HIP stream.  There is no CPU fallback: if the library is missing the
 import of `Context` fails.
 """
 from .binding import (CprError, Context, load_library, PHASES, SAMPLERS,
-                      PRECISIONS, declared_symbols, pinv)
+                      PRECISIONS, declared_symbols, pinv, pinv_noalloc)
 
 __all__ = ["CprError", "Context", "load_library", "PHASES", "SAMPLERS",
-           "PRECISIONS", "declared_symbols", "pinv"]
+           "PRECISIONS", "declared_symbols", "pinv", "pinv_noalloc"]

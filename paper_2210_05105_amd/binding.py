@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
         "cp_index_stats": [P, I32, C.POINTER(I64), C.POINTER(I64)],
         "cp_counters": [P, P, I32],
         "cp_pinv": [P, I32, P, P],
+        "cp_pinv_noalloc": [P, I32, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -120,6 +121,22 @@ def pinv(G, stream=None):
     st = lib.cp_pinv(_ptr(G), R, _ptr(out), C.c_void_p(s.cuda_stream))
     if st != 0:
         raise CprError(st, "cp_pinv failed")
+    return out
+
+
+def pinv_noalloc(G, out, stream=None):
+    """cp_pinv_noalloc: pseudo-inverse into the caller's `out` (same shape,
+    FP64 CUDA); the library allocates nothing."""
+    import torch
+    lib = load_library()
+    R = G.shape[0]
+    assert G.dtype == torch.float64 and G.is_contiguous() and G.is_cuda
+    assert out.dtype == torch.float64 and out.is_contiguous()
+    assert G.shape == (R, R) and out.shape == (R, R)
+    s = stream if stream is not None else torch.cuda.current_stream(G.device)
+    st = lib.cp_pinv_noalloc(_ptr(G), R, _ptr(out), C.c_void_p(s.cuda_stream))
+    if st != 0:
+        raise CprError(st, "cp_pinv_noalloc failed")
     return out
 
 

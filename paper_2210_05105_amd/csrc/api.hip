@@ -10,6 +10,7 @@
 #include <climits>
 #include <functional>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 using namespace cpr;
@@ -886,6 +887,70 @@ cp_status cp_pinv(const double *G, int32_t R, double *Gp, void *stream) {
   if (Gfull) (void)hipFree(Gfull);
   if (err) (void)hipFree(err);
   return st;
+}
+
+// Allocation-free pseudo-inverse: the scratch lives in a file-scope device
+// array (one copy per GPU, held until the process ends), resolved per device
+// with hipGetSymbolAddress on the first call there.  Layout: Hadamard copy
+// (MAXR^2 doubles), pseudo-inverse work (MAXR^2 doubles), error word.
+}  // extern "C"
+
+static __device__ __align__(256) double scratch[2 * MAXR * MAXR + 32];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+std::mutex g_noalloc_mu;
+
+__global__ void k_clear_word(uint32_t *w) { *w = 0u; }
+
+// Device address of `scratch` on the current device (resolved once).
+cp_status noalloc_scratch(double **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 ||
+      dev >= NOALLOC_MAX_DEVICES)
+    return CP_EHIP;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+      return CP_EHIP;
+    g_noalloc_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return CP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+cp_status cp_pinv_noalloc(const double *G, int32_t R, double *Gp,
+                          void *stream) {
+  if (!G || !Gp || R < 1 || R > MAXR) return CP_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *base = nullptr;
+  const cp_status st0 = noalloc_scratch(&base);
+  if (st0 != CP_OK) return st0;
+  double *Gfull = base;
+  double *work = base + MAXR * MAXR;
+  uint32_t *err = reinterpret_cast<uint32_t *>(base + 2 * MAXR * MAXR);
+  try {
+    ModeList ml;
+    std::memset(&ml, 0, sizeof(ml));
+    ml.n = 1;
+    ml.G[0] = G;
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, s, err);
+    CPR_LAUNCH_CHECK();
+    hadamard_pinv(ml, R, Gfull, Gp, nullptr, nullptr, work, err, s);
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return CP_EHIP;
+    if (e & (ERR_NONFINITE | ERR_PINV)) return CP_ENUMERIC;
+  } catch (const HipFail &) {
+    return CP_EHIP;
+  }
+  return CP_OK;
 }
 
 cp_status cp_counters(cp_ctx *c, int64_t *out, int32_t reset) {
