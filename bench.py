@@ -1,13 +1,17 @@
 """Benchmark: randomized CP-ALS sweeps/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload zipf3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload zipf3xl]
 
 A step is one ALS sweep (every mode solved once: pseudo-inverse, draws,
 merge, sampled MTTKRP, solve, renormalisation, Gram, sampler rebuild) over
-the resident synthetic tensor.  The default workload is the 3-way power-law
-tensor 100,000 x 80,000 x 60,000 with 50M nonzeros (Zipf(1.1) indices,
-lognormal FP32 values), R = 32, J = 65,536 draws per mode solve, STS-CP,
-FP32 MTTKRP with FP64 Grams / sampler / solve.  Prints one JSON line.
+the resident synthetic tensor.  The default workload is the largest
+single-GPU configuration: the 3-way power-law tensor 8,000,000 x 8,000,000 x
+200,000 with 1.5 billion nonzeros (Zipf(1.05) indices, lognormal FP32
+values), R = 100, J = 262,144 draws per mode solve, STS-CP, mixed precision
+(FP32 MTTKRP, split-BF16 MFMA factor Grams, FP64 sampler and refined
+solve), generated on the GPU.  Other workloads: zipf3 (100,000 x 80,000 x
+60,000, 50M nonzeros, R = 32), zipf4 (4-way, 200M nonzeros, R = 64,
+CP-ARLS-LEV), planted (200 x 150 x 100, R = 8).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,16 +32,34 @@ import tensorgen as tg  # noqa: E402
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 FP64_PEAK_TFS = 78.6      # MI355X FP64 vector / matrix
 
+# per workload: precision and STS leaf size when not given
+DEFAULTS = {"planted": ("fp64", 16), "zipf3": ("fp32", 16),
+            "zipf4": ("mixed", 16), "zipf3xl": ("mixed", 32),
+            "batch3": ("mixed", 16)}
+DEVICE_GENERATED = ("zipf4", "zipf3xl", "batch3")
+BATCH_RANKS = (8, 16, 32, 64, 128)   # batched restarts: ranks drawn from
+BATCH_B = 64                         # these, for 64 restarts
+
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="zipf3",
-                   choices=["zipf3", "planted"])
+    p.add_argument("--workload", default="zipf3xl",
+                   choices=["zipf3xl", "zipf4", "zipf3", "planted",
+                            "batch3"])
+    p.add_argument("--autotune", action="store_true",
+                   help="choose the leaf size / bucket rows (or streams) "
+                        "by timing candidates first (cached)")
+    p.add_argument("--nstreams", type=int, default=0,
+                   help="batch3: concurrent streams (0: 4)")
     p.add_argument("--precision", default=None)
     p.add_argument("--leaf", type=int, default=0)
+    p.add_argument("--compare", default=None, metavar="PRECISION",
+                   help="also run the same sweeps in this precision form "
+                        "(identical inputs and uniforms); report its rate "
+                        "and fit")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-profile", action="store_true")
     p.add_argument("--reduce-counters", nargs=3,
@@ -71,66 +93,123 @@ def sts_flops_per_solve(dims, j, R, J, F):
     return fl + J * (2 * R * R + R)
 
 
-def cpu_baseline(T, w, ctx, J, N, R, sampler):
-    """Time the FP64 oracle on a bounded sample of one mode solve."""
+def host_info():
+    """Cores this process may use, CPU model, RAM and BLAS threads."""
+    cores = len(os.sched_getaffinity(0))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return cores, model, ram
+
+
+def cpu_baseline(ctx, dims, nnz, idx_s, val_s, J, N, R, sampler, uni_j):
+    """Time the FP64 oracle on a bounded sample of one mode-0 solve.
+
+    Every piece runs on a sample and is scaled to the full solve: the
+    sampler structures on a prefix of each factor's rows (cost linear in
+    rows), a subset of the draws (each draw's cost does not depend on J),
+    the scan-filter extraction and the sampled MTTKRP on a uniform subset
+    of the nonzeros (idx_s, val_s), the solve and Gram at full size.
+    """
     import oracle as O
     import torch
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores, model, ram = host_info()
     j = 0
+    modes = [k for k in range(N) if k != j]
     U = [ctx.get_factor(k).cpu().numpy() for k in range(N)]
     G = [ctx.get_gram(k).cpu().numpy() for k in range(N)]
-    rng = np.random.default_rng(123)
-    Js = 512 if sampler == "sts" else J
-    u = rng.random((J, N - 1))
-    t0 = time.perf_counter()
-    if sampler == "sts":
-        pre = {k: O.sts_prefix_grams(U[k], 64) for k in range(N) if k != j}
-        t_pre = time.perf_counter() - t0
-        t1 = time.perf_counter()
-        O.sts_sample(U, G, j, u[:Js], 64, prefix=pre)
-        t_draw = (time.perf_counter() - t1) * (J / Js)
-    else:
-        st = {k: O.arls_build(U[k], G[k]) for k in range(N) if k != j}
-        t_pre = time.perf_counter() - t0
-        t1 = time.perf_counter()
-        O.arls_sample(U, st, j, u)
-        t_draw = time.perf_counter() - t1
-    # merge, extraction (scan over all nonzeros), MTTKRP and solve for the
-    # GPU's full draw set of this mode
-    gidx, gprob = ctx.sample(j, torch.from_numpy(u))
-    sidx, prob = gidx.cpu().numpy().astype(np.int64), gprob.cpu().numpy()
-    t2 = time.perf_counter()
-    h = np.ones((J, R))
-    for q, k in enumerate([k for k in range(N) if k != j]):
-        h = h * U[k][sidx[:, q]]
-    keys, rep, cnt, wts = O.dedup(sidx, prob, T.dims, j, J)
-    ck, rows, vals, slot = O.extract(T.idx, T.val, T.dims, j, keys)
-    M = O.sampled_mttkrp(T.dims[j], rows, vals, slot, wts, h[rep])
-    Uj, sig = O.solve(M, O.pinv_psd(O.gram_hadamard(G, j)))
-    Gj = O.gram(Uj)
-    t_rest = time.perf_counter() - t2
-    t3 = time.perf_counter()
-    if sampler == "sts":
-        O.sts_prefix_grams(Uj, 64)
-    else:
-        O.arls_build(Uj, Gj)
-    t_build = time.perf_counter() - t3
-    per_solve = t_pre / (N - 1) + t_draw + t_rest + t_build
+    with threadpool_limits(limits=cores):
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        ROWS = 100_000
+        blk = 64  # oracle prefix-Gram block (ROWS R^2 long doubles at most)
+        t_pre = 0.0
+        sub = {}
+        for k in modes:
+            rows = min(dims[k], ROWS)
+            t0 = time.perf_counter()
+            if sampler == "sts":
+                sub[k] = O.sts_prefix_grams(U[k][:rows], blk)
+            else:
+                sub[k] = O.arls_build(U[k][:rows], G[k])
+            t_pre += (time.perf_counter() - t0) * dims[k] / rows
+        # draws on the sampled factors: cost per draw, scaled to J
+        Us = [U[k][:min(dims[k], ROWS)] if k != j else U[k] for k in range(N)]
+        Js = min(J, 256 if sampler == "sts" else 8192)
+        u = uni_j[:Js]
+        t0 = time.perf_counter()
+        if sampler == "sts":
+            O.sts_sample(Us, G, j, u, block=blk,
+                         prefix={k: sub[k] for k in modes})
+        else:
+            O.arls_sample(Us, sub, j, u)
+        t_draw = (time.perf_counter() - t0) * (J / Js)
+        # merge, extraction and MTTKRP for the GPU's full draw set of mode 0,
+        # extraction scanning the sampled nonzeros
+        gidx, gprob = ctx.sample(j, torch.from_numpy(uni_j))
+        sidx = gidx.cpu().numpy().astype(np.int64)
+        prob = gprob.cpu().numpy()
+        t0 = time.perf_counter()
+        h = np.ones((J, R))
+        for q, k in enumerate(modes):
+            h = h * U[k][sidx[:, q]]
+        keys, rep, cnt, wts = O.dedup(sidx, prob, dims, j, J)
+        t_merge = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ck, rows, vals, slot = O.extract(idx_s, val_s, dims, j, keys)
+        M = O.sampled_mttkrp(dims[j], rows, vals, slot, wts, h[rep])
+        t_ext = (time.perf_counter() - t0) * nnz / idx_s.shape[0]
+        t0 = time.perf_counter()
+        Uj, sig = O.solve(M, O.pinv_psd(O.gram_hadamard(G, j)))
+        O.gram(Uj)
+        t_solve = time.perf_counter() - t0
+        rows_b = min(dims[j], ROWS)
+        t0 = time.perf_counter()
+        if sampler == "sts":
+            O.sts_prefix_grams(Uj[:rows_b], blk)
+        else:
+            O.arls_build(Uj[:rows_b], O.gram(Uj))
+        t_build = (time.perf_counter() - t0) * dims[j] / rows_b
+    per_solve = t_pre / (N - 1) + t_draw + t_merge + t_ext + t_solve + t_build
     per_sweep = N * per_solve
-    sample = (f"one mode solve of mode 0 at full size: sampler structures for "
-              f"the {N - 1} drawn factors ({t_pre:.1f} s, counted once per "
-              f"solve), {Js} of {J} draws ({t_draw * Js / J:.1f} s, scaled "
-              f"x{J // Js}), merge + scan-filter extraction over all "
-              f"{T.nnz} nonzeros + sampled MTTKRP + solve ({t_rest:.1f} s), "
-              f"sampler rebuild ({t_build:.1f} s); sweep = {N} x mode solve")
-    return dict(value=1.0 / per_sweep, unit="sweeps/s", cores=1,
-                kind="oracle", sample=sample,
+    sample = (f"one mode-0 solve, extrapolated to a sweep (x{N}): sampler "
+              f"structures on the first {ROWS} rows of each factor "
+              f"({t_pre:.1f} s scaled by rows, counted once per solve), "
+              f"{Js} of {J} draws ({t_draw * Js / J:.1f} s, scaled "
+              f"x{J / Js:.0f}), merge of the GPU's {J} draws "
+              f"({t_merge:.1f} s), scan-filter extraction + sampled MTTKRP "
+              f"over {idx_s.shape[0]} of {nnz} nonzeros ({t_ext * idx_s.shape[0] / nnz:.1f} s, "
+              f"scaled x{nnz / idx_s.shape[0]:.0f}), solve + Gram at full "
+              f"size ({t_solve:.1f} s), sampler rebuild ({t_build:.1f} s "
+              f"scaled); NumPy outside BLAS runs on one thread")
+    return dict(value=1.0 / per_sweep, unit="sweeps/s", cores=blas,
+                kind="oracle", sample=sample, host_cores=cores,
+                blas_threads=blas, cpu_model=model, host_ram_gib=ram,
                 seconds_per_sweep_extrapolated=per_sweep)
 
 
 # kernel sets whose HBM traffic is reported, and the sources they come from
 KERNEL_SETS = {"sts_draw": ("k_sts_", ["k_sts.hip"]),
                "sampled_mttkrp": ("k_bk_", ["k_mttkrp.hip"])}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_zipf3_sts_fp32.json")
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 
 
 def source_digest(files):
@@ -167,17 +246,188 @@ def reduce_counters(fetch_db, write_db, solves, calib_mib):
     return out
 
 
-def measured_traffic(kernel):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of a kernel set from the committed counter
     summary, or None if absent or taken on other sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(workload)) as fh:
             t = json.load(fh)[kernel]
     except (OSError, KeyError, ValueError):
         return None
     if t.get("source_digest") != source_digest(KERNEL_SETS[kernel][1]):
         return None
     return t["fetch_bytes_per_solve"] + t["write_bytes_per_solve"]
+
+
+def build_inputs(a, w, dev):
+    """Tensor (device COO), initial factors and uniforms of the workload."""
+    import torch
+    N = len(w["dims"])
+    t0 = time.time()
+    if a.workload in DEVICE_GENERATED:
+        dims, idx_d, val_d = tg.make_tensor_device(a.workload, dev, log=log)
+        base = 2210_5105 * 16 + int(w["tag"])
+        U0 = tg.init_factors_device(base + 11, dims, w["R"], dev) \
+            if "R" in w else None
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    else:
+        T = tg.make_tensor(a.workload)
+        dims = T.dims
+        idx_d = torch.from_numpy(T.idx).to(dev)
+        val_d = torch.from_numpy(T.val).to(dev)
+        _, _, rinit, _ = tg.streams(w["tag"])
+        U0 = [torch.from_numpy(u).to(dev) for u in
+              tg.init_factors(rinit, dims, w["R"], dtype=np.float32)]
+    log(f"generated {a.workload}: dims {dims} nnz {idx_d.shape[0]} in "
+        f"{time.time() - t0:.1f}s")
+    return dims, N, idx_d, val_d, U0
+
+
+def run_form(a, w, dims, N, idx_d, val_d, U0, uni, precision, leaf, timed,
+             bucket_rows=0):
+    """Build a context in one precision form and run warmup + timed sweeps.
+    Returns (ctx, seconds of the timed sweeps, init seconds, fit, counters,
+    per-phase times of the timed sweeps)."""
+    import torch
+    from paper_2210_05105_amd import Context
+    R, J, sampler = w["R"], w["J"], w["sampler"]
+    vdt = torch.float64 if precision == "fp64" else torch.float32
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx = Context(idx_d, val_d.to(vdt), dims, R, sampler, precision, max_J=J,
+                  sts_leaf=leaf, bucket_rows=bucket_rows)
+    torch.cuda.synchronize()
+    t_init = time.time() - t0
+    torch.cuda.empty_cache()
+    log(f"[{precision}] cp_init (per-mode index build) {t_init:.2f}s")
+    for k in range(N):
+        ctx.set_factor(k, U0[k])
+    if a.warmup:
+        ctx.sweep(a.warmup, J, uni[:a.warmup])
+    ctx.sync()
+    ctx.counters(reset=True)
+    if timed and not a.no_profile:
+        ctx.profile(True, phases=["sample", "mttkrp"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.sweep(a.steps, J, uni[a.warmup:a.warmup + a.steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.sync()
+    ph_timed = ctx.profile_read() if timed and not a.no_profile else {}
+    ctx.profile(False)
+    cnt = ctx.counters()
+    fit = ctx.fit()
+    log(f"[{precision}] timed {a.steps} sweeps in {dt:.4f}s; fit {fit:.6f}; "
+        f"counters {cnt}")
+    return ctx, dt, t_init, fit, cnt, ph_timed
+
+
+def bench_batch(a, w, dev, precision, leaf):
+    """Batched restarts: 64 decompositions of one tensor with ranks drawn
+    uniformly from {8, 16, 32, 64, 128}, every sweep one replay of a
+    captured HIP graph.  value = restart-sweeps per second.  The plain FP64
+    one-instance form is timed per rank class (one restart each, its own
+    context) and summed over the 64 restarts by class counts."""
+    import torch
+    from paper_2210_05105_amd import Batch, Context
+    J, sampler = w["J"], w["sampler"]
+    rng = np.random.default_rng(2210_5105 + 5)
+    ranks = [int(r) for r in rng.choice(BATCH_RANKS, size=BATCH_B)]
+    w = dict(w, R=max(ranks))
+    dims, N, idx_d, val_d, _ = build_inputs(a, w, dev)
+    nnz = int(idx_d.shape[0])
+    vdt = torch.float64 if precision == "fp64" else torch.float32
+    base = 2210_5105 * 16 + int(w["tag"])
+    nstreams = a.nstreams
+    tuned = None
+    if a.autotune:
+        from paper_2210_05105_amd.autotune import tune_batch
+        tuned = tune_batch(idx_d, val_d.to(vdt), dims, ranks, sampler,
+                           precision, J, log=log)
+        nstreams = tuned["nstreams"]
+        log(f"autotune: {tuned}")
+    t0 = time.time()
+    bt = Batch(idx_d, val_d.to(vdt), dims, ranks, sampler, precision, J=J,
+               sts_leaf=leaf, nstreams=nstreams)
+    torch.cuda.synchronize()
+    t_init = time.time() - t0
+    log(f"batch init (shared index, {BATCH_B} restarts) {t_init:.2f}s")
+    U0 = [tg.init_factors_device(base + 100 + b, dims, R, dev)
+          for b, R in enumerate(ranks)]
+    for b in range(BATCH_B):
+        for k in range(N):
+            bt.set_factor(b, k, U0[b][k])
+    nsw = a.warmup + a.steps
+    uni_all = tg.uniforms_device(base + 13, (nsw, BATCH_B, N, J, N - 1), dev)
+    ubuf = torch.empty_like(uni_all[0])
+    for t in range(a.warmup):
+        ubuf.copy_(uni_all[t])
+        bt.sweep(ubuf)
+    bt.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(a.warmup, nsw):
+        ubuf.copy_(uni_all[t])   # refill the captured buffer (a device copy)
+        bt.sweep(ubuf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bt.sync()
+    fits = bt.fit()
+    bt.close()
+    torch.cuda.empty_cache()
+    rate = BATCH_B * a.steps / dt
+    log(f"batch: {a.steps} sweeps of {BATCH_B} restarts in {dt:.3f}s "
+        f"({rate:.1f} restart-sweeps/s); mean fit {np.mean(fits):.5f}")
+    # plain FP64 one-instance reference: one restart per rank class
+    ref = {}
+    if a.compare:
+        vref = val_d.to(torch.float64 if a.compare == "fp64" else
+                        torch.float32)
+        for R in sorted(set(ranks)):
+            b = ranks.index(R)
+            c = Context(idx_d, vref, dims, R, sampler, a.compare, max_J=J,
+                        sts_leaf=leaf)
+            for k in range(N):
+                c.set_factor(k, U0[b][k])
+            c.sweep(a.warmup, J, uni_all[:a.warmup, b])
+            c.sync()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            c.sweep(a.steps, J, uni_all[a.warmup:, b])
+            torch.cuda.synchronize()
+            tr = (time.perf_counter() - t1) / a.steps
+            ref[R] = dict(count=ranks.count(R), s_per_sweep=tr, fit=c.fit(),
+                          batch_fit=fits[b])
+            c.close()
+            torch.cuda.empty_cache()
+            log(f"[{a.compare}] one instance R={R}: {tr * 1e3:.2f} ms/sweep, "
+                f"fit {ref[R]['fit']:.5f} (batch restart {fits[b]:.5f})")
+    compare = None
+    if ref:
+        tot = sum(v["count"] * v["s_per_sweep"] for v in ref.values())
+        compare = dict(precision=a.compare, form="one instance per restart",
+                       value=BATCH_B / tot,
+                       per_rank={str(k): v for k, v in ref.items()},
+                       max_abs_fit_difference=max(
+                           abs(v["fit"] - v["batch_fit"]) for v in ref.values()))
+    out = {
+        "metric": "ALS sweeps/sec and sampled-MTTKRP HBM GB/s (% of peak) at fixed fit",
+        "value": rate, "unit": "restart-sweeps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if precision != "fp64" else "f64", "data": "synthetic",
+        "config": {"workload": "batch3", "dims": list(dims), "nnz": nnz,
+                   "restarts": BATCH_B, "ranks": ranks, "J": J,
+                   "sampler": sampler, "precision": precision,
+                   "nstreams": nstreams or 4, "sts_leaf": leaf,
+                   "parallelism": "single-gpu", "autotuned": tuned},
+        "fits": fits, "init_s": t_init, "compare": compare,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -192,7 +442,7 @@ def main():
               f"multi-GPU layout is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2210_05105_amd import Context, load_library
+    from paper_2210_05105_amd import load_library
     load_library()
     dev = torch.device("cuda:0")
     if a.copy_calibration:  # first copies of the process: known size
@@ -205,57 +455,47 @@ def main():
         log(f"copy calibration: 3 copies of {a.copy_calibration} MiB")
         del src_t, dst_t
     w = dict(tg.WORKLOADS[a.workload])
-    if a.workload == "zipf3":
-        R, J, sampler = w["R"], w["J"], w["sampler"]
-        precision = a.precision or "fp32"
-    else:
-        R, J, sampler = w["R"], w["J"], w["sampler"]
-        precision = a.precision or "fp64"
-    t0 = time.time()
-    T = tg.make_tensor(a.workload)
-    log(f"generated {a.workload}: dims {T.dims} nnz {T.nnz} in "
-        f"{time.time() - t0:.1f}s")
-    N = T.N
-    vdt = torch.float64 if precision == "fp64" else torch.float32
-    idx_d = torch.from_numpy(T.idx).to(dev)
-    val_d = torch.from_numpy(T.val).to(dev, vdt)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    ctx = Context(idx_d, val_d, T.dims, R, sampler, precision, max_J=J,
-                  sts_leaf=a.leaf)
-    torch.cuda.synchronize()
-    t_init = time.time() - t0
-    del idx_d, val_d
-    log(f"cp_init (per-mode index build) {t_init:.2f}s")
-    _, _, rinit, runi = tg.streams(w["tag"])
-    U0 = tg.init_factors(rinit, T.dims, R,
-                         dtype=np.float64 if precision == "fp64" else np.float32)
-    for k in range(N):
-        ctx.set_factor(k, torch.from_numpy(U0[k]))
+    prec0, leaf0 = DEFAULTS[a.workload]
+    precision = a.precision or prec0
+    leaf = a.leaf or leaf0
+    if a.workload == "batch3":
+        return bench_batch(a, w, dev, precision, leaf)
+    R, J, sampler = w["R"], w["J"], w["sampler"]
+    dims, N, idx_d, val_d, U0 = build_inputs(a, w, dev)
+    nnz = int(idx_d.shape[0])
+    tuned = None
+    if a.autotune:
+        from paper_2210_05105_amd.autotune import tune_context
+        tuned = tune_context(idx_d, val_d.to(torch.float64 if precision ==
+                                             "fp64" else torch.float32),
+                             dims, R, sampler, precision, J, log=log)
+        leaf = tuned["sts_leaf"] or leaf
+        log(f"autotune: {tuned}")
+    # a uniform sample of the nonzeros (the COO is in random order) for the
+    # oracle's bounded extraction, kept on the host
+    S = min(nnz, 8_000_000)
+    idx_s = idx_d[:S].cpu().numpy()
+    val_s = val_d[:S].double().cpu().numpy()
     # after the timed sweeps, a short pass with events on every phase gives
     # the breakdown (events cost the stream a few microseconds each, so the
     # timed sweeps record them only around the two phases the line reports)
-    extra = 0 if a.no_profile else min(a.steps, 5)
-    uni = torch.from_numpy(
-        tg.uniform_blocks(runi, a.warmup + a.steps + extra, J, N)).to(dev)
-    torch.cuda.synchronize()
-    per = J * N * (N - 1)
-    if a.warmup:
-        ctx.sweep(a.warmup, J, uni[:a.warmup])
-    ctx.sync()
-    ctx.counters(reset=True)
-    if not a.no_profile:
-        ctx.profile(True, phases=["sample", "mttkrp"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.sweep(a.steps, J, uni[a.warmup:a.warmup + a.steps])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.sync()
-    ph_timed = ctx.profile_read() if not a.no_profile else {}
-    ctx.profile(False)
-    cnt = ctx.counters()
-    fit = ctx.fit()
+    extra = 0 if a.no_profile else min(a.steps, 3)
+    nsw = a.warmup + a.steps + extra
+    uni = tg.uniforms_device(2210_5105 * 16 + int(w["tag"]) + 13,
+                             (nsw, N, J, N - 1), dev)
+    compare = None
+    if a.compare:
+        cctx, cdt, cinit, cfit, _, _ = run_form(
+            a, w, dims, N, idx_d, val_d, U0, uni, a.compare, leaf, False)
+        cctx.close()
+        torch.cuda.empty_cache()
+        compare = dict(precision=a.compare, value=a.steps / cdt,
+                       ms_per_step=cdt / a.steps * 1e3, fit=cfit)
+    ctx, dt, t_init, fit, cnt, ph_timed = run_form(
+        a, w, dims, N, idx_d, val_d, U0, uni, precision, leaf, True,
+        tuned["bucket_rows"] if tuned else 0)
+    del idx_d, val_d
+    torch.cuda.empty_cache()
     ph = {}
     if extra:
         ctx.profile(True)
@@ -263,7 +503,6 @@ def main():
         ctx.sync()
         ph = ctx.profile_read()
         ctx.profile(False)
-    log(f"timed {a.steps} sweeps in {dt:.4f}s; fit {fit:.6f}; counters {cnt}")
     sweeps_per_s = a.steps / dt
 
     # ---- roofline of the dominant kernel and the sampled MTTKRP
@@ -291,20 +530,20 @@ def main():
         dom = max(ph, key=lambda k: ph[k][0])
         ms_dom = per_launch(dom)
         if dom == "sample" and sampler == "sts":
-            F = a.leaf or 16
-            fl = np.mean([sts_flops_per_solve(T.dims, j, R, J, F)
+            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaf)
                           for j in range(N)])
             ach = fl / (ms_dom * 1e-3) / 1e12
             roof = dict(kernel="sts_draw", bound="mfma", achieved=ach,
                         peak=FP64_PEAK_TFS, unit="TFLOP/s",
                         frac=ach / FP64_PEAK_TFS,
-                        traffic=measured_traffic("sts_draw"),
+                        traffic=measured_traffic(a.workload, "sts_draw"),
                         flops_per_launch=fl, ms_per_launch=ms_dom)
         elif dom == "mttkrp":
             roof = dict(kernel="sampled_mttkrp", bound="hbm",
                         achieved=mttkrp["achieved_GBs"], peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=mttkrp["frac_of_peak"],
-                        traffic=measured_traffic("sampled_mttkrp"),
+                        traffic=measured_traffic(a.workload,
+                                                 "sampled_mttkrp"),
                         bytes_per_launch=mtt_bytes, ms_per_launch=ms_mtt)
         else:
             roof = dict(kernel=dom, bound="latency", achieved=None,
@@ -313,7 +552,8 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         log("timing the oracle on the host ...")
-        cpu = cpu_baseline(T, w, ctx, J, N, R, sampler)
+        cpu = cpu_baseline(ctx, dims, nnz, idx_s, val_s, J, N, R, sampler,
+                           uni[0, 0].cpu().numpy())
         log(f"oracle: {cpu['seconds_per_sweep_extrapolated']:.1f} s/sweep")
     out = {
         "metric": "ALS sweeps/sec and sampled-MTTKRP HBM GB/s (% of peak) at fixed fit",
@@ -323,11 +563,13 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precision != "fp64" else "f64",
         "data": "synthetic",
-        "config": {"workload": a.workload, "dims": list(T.dims),
-                   "nnz": T.nnz, "R": R, "J": J, "sampler": sampler,
+        "config": {"workload": a.workload, "dims": list(dims), "nnz": nnz,
+                   "R": R, "J": J, "sampler": sampler,
                    "precision": precision, "sweeps_timed": a.steps,
-                   "sts_leaf": a.leaf or 16, "parallelism": "single-gpu"},
+                   "sts_leaf": leaf, "parallelism": "single-gpu",
+                   "autotuned": tuned},
         "fit": fit, "init_s": t_init,
+        "compare": compare,
         "sampled_mttkrp": mttkrp, "phases": phases,
         "phases_sweeps": extra,
         "roofline": roof, "cpu_baseline": cpu,

@@ -85,7 +85,21 @@ typedef struct {
   int32_t sts_leaf;   /* STS-CP tree leaf size in rows (16, 32 or 64); 0: 16  */
   int64_t max_J;      /* largest J any cp_sample will use, <= 2^24 (sizes    
                          workspaces); ignored by CP_SAMPLER_EXACT             */
+  int32_t bucket_rows;  /* output rows per bucket of the sampled MTTKRP's
+                           row-ordered placement: 0 = automatic (128, fewer
+                           when 128 x R values exceed 32 KiB), else a power
+                           of two in [16, 256]                             */
+  int32_t solve_gram;   /* cp_solve_gram: the R x R matrix G of the update
+                           U_j = M G^+                                     */
 } cp_config;
+
+typedef enum {
+  CP_GRAM_EXACT = 0,    /* Hadamard product of the factor Grams (Eq. 4-5)  */
+  CP_GRAM_SKETCHED = 1  /* G~ = (S U_{!=j})^T (S U_{!=j}) of the draws, the
+                           sketched least-squares problem of Fig. 3: every
+                           draw s adds h_s h_s^T / (J p_s); the draws still
+                           follow the exact leverage laws                   */
+} cp_solve_gram;
 
 /*
  * cp_init - build the per-mode column-sorted indices and allocate all state.
@@ -261,6 +275,49 @@ cp_status cp_counters(cp_ctx *ctx, int64_t *out, int32_t reset);
 /* Index statistics for mode (host outputs): nonempty columns, longest column. */
 cp_status cp_index_stats(cp_ctx *ctx, int32_t mode, int64_t *n_cols,
                          int64_t *max_col);
+
+/*
+ * Batched restarts: B independent decompositions of one tensor (Alg. 1 run
+ * as independent trials, as the paper's experiments average over trials),
+ * each with its own rank ranks[b] (1..128), factors, Grams, sigma and
+ * sampler; the same sampler, precision, leaf size and J (cfg->max_J, the J
+ * of every sweep; cfg->R is ignored) for all.  They share one copy of the
+ * per-mode indices.  The restarts are spread over `nstreams` streams (0:
+ * 4; by decreasing rank, round-robin): restarts of one stream run one after
+ * another and share one set of workspaces, different streams run
+ * concurrently.  The batch owns its streams and everything it allocates;
+ * cp_batch_init is synchronising, the tensor may be freed afterwards.
+ * Errors as for cp_init / cp_sweep; on failure *out still receives a batch
+ * that serves cp_batch_last_error and cp_batch_destroy.
+ */
+typedef struct cp_batch cp_batch;
+cp_status cp_batch_init(const cp_tensor *t, int32_t B, const int32_t *ranks,
+                        const cp_config *cfg, int32_t nstreams, void *stream,
+                        cp_batch **out);
+/* cp_set_factor for restart b (device U, I_mode x ranks[b], FP64). */
+cp_status cp_batch_set_factors(cp_batch *bt, int32_t b, int32_t mode,
+                               const double *U);
+/*
+ * cp_batch_sweep - one ALS sweep (Alg. 1, modes in order) of every
+ * restart.  uniforms: device, B x N x J x (N-1) doubles (restart b's block
+ * is as cp_sweep's for one sweep).  The whole sweep is captured once into a
+ * HIP graph and replayed with one graph launch per call; the graph reads
+ * `uniforms` at this address, so pass the same buffer (refilled) to reuse
+ * it (another address captures anew).  Asynchronous on the batch's stream.
+ */
+cp_status cp_batch_sweep(cp_batch *bt, const double *uniforms);
+/* cp_fit of every restart into fits (host, B doubles); synchronising. */
+cp_status cp_batch_fit(cp_batch *bt, double *fits);
+/* wait for the batch's work and return pending device errors */
+cp_status cp_batch_sync(cp_batch *bt);
+/* copies of restart b's factor (device, I_mode x ranks[b] FP64) / sigma */
+cp_status cp_batch_get_factor(cp_batch *bt, int32_t b, int32_t mode,
+                              double *U_out);
+cp_status cp_batch_get_sigma(cp_batch *bt, int32_t b, double *sigma_out);
+/* the stream index restart b runs on (-1 if out of range) */
+int32_t cp_batch_stream_of(const cp_batch *bt, int32_t b);
+void cp_batch_destroy(cp_batch *bt);
+const char *cp_batch_last_error(const cp_batch *bt);
 
 void cp_destroy(cp_ctx *ctx);
 const char *cp_last_error(const cp_ctx *ctx);

@@ -16,7 +16,7 @@ __all__ = [
     "sts_law_bruteforce", "arls_law_bruteforce", "dedup", "extract",
     "sampled_mttkrp", "mttkrp_exact", "mttkrp_dense", "solve", "fit",
     "fit_dense", "als", "arls_boundary_gap", "sts_boundary_gap",
-    "sts_conditional_cdf",
+    "sts_conditional_cdf", "sketched_gram",
 ]
 
 LD = np.longdouble
@@ -483,6 +483,14 @@ def mttkrp_dense(idx, val, dims, U, j):
     return matricize_dense(idx, val, dims, j) @ design_matrix(U, j)
 
 
+def sketched_gram(h, prob, J):
+    """G~ = (S U_{!=j})^T (S U_{!=j}) of the sketched least-squares problem
+    (Fig. 3): every draw s adds h_s h_s^T / (J p_s), h_s its Khatri-Rao row
+    (a row of S carries 1/sqrt(J p_s)).  Duplicates add up as S^T S does."""
+    wt = 1.0 / (J * np.asarray(prob, dtype=np.float64))
+    return (h * wt[:, None]).T @ h
+
+
 def solve(M, Gp):
     """U_j = M G^+ (Eq. 4), then sigma and renormalisation (Alg. 1)."""
     return normalize_columns(M @ Gp)
@@ -526,12 +534,14 @@ def fit_dense(idx, val, dims, sigma, U):
 
 
 def als(idx, val, dims, R, sampler, U0, uniforms=None, sweeps=1, J=None,
-        block=64, record_fit=False):
+        block=64, record_fit=False, sketched=False):
     """Randomized CP-ALS (Alg. 1 with the three steps of Section 4 per mode).
 
     sampler: "arls", "sts" or "exact" (every nonempty column at weight 1).
     U0: initial factors (float64); they are column-normalised and sigma = 1.
     uniforms[t, j] holds the J x (N-1) uniforms of mode j in sweep t.
+    sketched: solve with the sketched Gram G~ of the draws (Fig. 3) instead
+    of the exact Hadamard Gram G (Eq. 5); the draws still follow G.
     Returns (U, sigma, fits) where fits is per sweep if record_fit.
     """
     N = len(dims)
@@ -557,6 +567,8 @@ def als(idx, val, dims, R, sampler, U0, uniforms=None, sweeps=1, J=None,
                 keys, rep, counts, w = dedup(sidx, prob, dims, j, J)
                 ck, rows, vals, slot = extract(idx, val, dims, j, keys)
                 M = sampled_mttkrp(dims[j], rows, vals, slot, w, h[rep])
+                if sketched:
+                    Gp = pinv_psd(sketched_gram(h, prob, J))
             U[j], sigma = solve(M, Gp)
             G[j] = gram(U[j])
             if sampler == "arls":

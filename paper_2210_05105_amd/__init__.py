@@ -5,8 +5,8 @@ this package only marshals arguments.  PyTorch supplies device memory and
 the HIP stream.  There is no CPU fallback: if the library is missing the
 import of `Context` fails.
 """
-from .binding import (CprError, Context, load_library, PHASES, SAMPLERS,
+from .binding import (Batch, CprError, Context, load_library, PHASES, SAMPLERS,
                       PRECISIONS, declared_symbols, pinv, pinv_noalloc)
 
-__all__ = ["CprError", "Context", "load_library", "PHASES", "SAMPLERS",
+__all__ = ["Batch", "CprError", "Context", "load_library", "PHASES", "SAMPLERS",
            "PRECISIONS", "declared_symbols", "pinv", "pinv_noalloc"]

@@ -40,7 +40,8 @@ class _Tensor(C.Structure):
 class _Config(C.Structure):
     _fields_ = [("R", C.c_int32), ("sampler", C.c_int32),
                 ("precision", C.c_int32), ("sts_leaf", C.c_int32),
-                ("max_J", C.c_int64)]
+                ("max_J", C.c_int64), ("bucket_rows", C.c_int32),
+                ("solve_gram", C.c_int32)]
 
 
 _lib = None
@@ -87,6 +88,14 @@ def load_library(path=LIB_PATH):
         "cp_index_stats": [P, I32, C.POINTER(I64), C.POINTER(I64)],
         "cp_counters": [P, P, I32],
         "cp_pinv": [P, I32, P, P],
+        "cp_batch_init": [C.POINTER(_Tensor), I32, P, C.POINTER(_Config),
+                          I32, P, C.POINTER(P)],
+        "cp_batch_set_factors": [P, I32, I32, P],
+        "cp_batch_sweep": [P, P],
+        "cp_batch_fit": [P, P],
+        "cp_batch_sync": [P],
+        "cp_batch_get_factor": [P, I32, I32, P],
+        "cp_batch_get_sigma": [P, I32, P],
         "cp_pinv_noalloc": [P, I32, P, P],
     }
     for name, args in sig.items():
@@ -101,6 +110,12 @@ def load_library(path=LIB_PATH):
     lib.cp_status_string.restype = C.c_char_p
     lib.cp_phase_name.argtypes = [I32]
     lib.cp_phase_name.restype = C.c_char_p
+    lib.cp_batch_destroy.argtypes = [P]
+    lib.cp_batch_destroy.restype = None
+    lib.cp_batch_last_error.argtypes = [P]
+    lib.cp_batch_last_error.restype = C.c_char_p
+    lib.cp_batch_stream_of.argtypes = [P, I32]
+    lib.cp_batch_stream_of.restype = I32
     _lib = lib
     return lib
 
@@ -148,7 +163,8 @@ class Context:
     """
 
     def __init__(self, idx, val, dims, R, sampler="arls", precision="fp64",
-                 max_J=1, sts_leaf=0, stream=None):
+                 max_J=1, sts_leaf=0, stream=None, bucket_rows=0,
+                 sketched=False):
         import torch
         self._torch = torch
         lib = load_library()
@@ -168,7 +184,8 @@ class Context:
         t = _Tensor(self.N, d, int(val.shape[0]), idx.data_ptr(),
                     val.data_ptr(), int(val.dtype == torch.float64))
         cfg = _Config(self.R, SAMPLERS[sampler], PRECISIONS[precision],
-                      int(sts_leaf), int(max_J))
+                      int(sts_leaf), int(max_J), int(bucket_rows),
+                      int(bool(sketched)))
         h = C.c_void_p()
         st = lib.cp_init(C.byref(t), C.byref(cfg),
                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -322,3 +339,98 @@ class Context:
         self._check(self.lib.cp_index_stats(self._h, mode, C.byref(a),
                                             C.byref(b)))
         return a.value, b.value
+
+
+class Batch:
+    """Batched restarts of one tensor (cp_batch_*): ranks[b] per restart,
+    a shared index, one captured HIP graph per sweep."""
+
+    def __init__(self, idx, val, dims, ranks, sampler="arls",
+                 precision="fp64", J=1, sts_leaf=0, nstreams=0, stream=None,
+                 bucket_rows=0):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self.lib = lib
+        self.N = len(dims)
+        self.dims = [int(d) for d in dims]
+        self.ranks = [int(r) for r in ranks]
+        self.B = len(self.ranks)
+        self.J = int(J)
+        self.device = idx.device
+        assert idx.dtype == torch.int32 and idx.is_contiguous()
+        assert idx.shape == (val.shape[0], self.N) and val.is_contiguous()
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(self.device)
+        d = (C.c_int64 * self.N)(*self.dims)
+        t = _Tensor(self.N, d, int(val.shape[0]), idx.data_ptr(),
+                    val.data_ptr(), int(val.dtype == torch.float64))
+        cfg = _Config(0, SAMPLERS[sampler], PRECISIONS[precision],
+                      int(sts_leaf), self.J, int(bucket_rows), 0)
+        rk = (C.c_int32 * self.B)(*self.ranks)
+        h = C.c_void_p()
+        st = lib.cp_batch_init(C.byref(t), self.B, rk, C.byref(cfg),
+                               int(nstreams),
+                               C.c_void_p(self.stream.cuda_stream),
+                               C.byref(h))
+        self._h = h
+        if st != 0:
+            msg = lib.cp_batch_last_error(h).decode() if h else "invalid arguments"
+            if h:
+                lib.cp_batch_destroy(h)
+            self._h = None
+            raise CprError(st, msg)
+        self._uni = None
+
+    def _check(self, st):
+        if st != 0:
+            raise CprError(st, self.lib.cp_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.cp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_factor(self, b, mode, U):
+        U = U.to(device=self.device, dtype=self._torch.float64).contiguous()
+        assert U.shape == (self.dims[mode], self.ranks[b])
+        self._keep = U
+        self._check(self.lib.cp_batch_set_factors(self._h, b, mode, _ptr(U)))
+
+    def sweep(self, uniforms):
+        """uniforms: [B, N, J, N-1] FP64; kept by the batch (the captured
+        graph reads this buffer at every replay)."""
+        u = uniforms
+        assert u.dtype == self._torch.float64 and u.is_contiguous()
+        assert tuple(u.shape) == (self.B, self.N, self.J, self.N - 1)
+        self._uni = u
+        self._check(self.lib.cp_batch_sweep(self._h, _ptr(u)))
+
+    def fit(self):
+        out = (C.c_double * self.B)()
+        self._check(self.lib.cp_batch_fit(self._h, out))
+        return list(out)
+
+    def sync(self):
+        self._check(self.lib.cp_batch_sync(self._h))
+
+    def get_factor(self, b, mode):
+        out = self._torch.empty((self.dims[mode], self.ranks[b]),
+                                dtype=self._torch.float64, device=self.device)
+        self._check(self.lib.cp_batch_get_factor(self._h, b, mode, _ptr(out)))
+        return out
+
+    def get_sigma(self, b):
+        out = self._torch.empty((self.ranks[b],), dtype=self._torch.float64,
+                                device=self.device)
+        self._check(self.lib.cp_batch_get_sigma(self._h, b, _ptr(out)))
+        return out
+
+    def stream_of(self, b):
+        return self.lib.cp_batch_stream_of(self._h, b)

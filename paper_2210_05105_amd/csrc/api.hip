@@ -34,14 +34,12 @@ struct cp_ctx {
   std::string msg;
   uint32_t *d_err = nullptr;
   int64_t *d_dims = nullptr;
-  int32_t *coo_idx = nullptr;
-  void *coo_val = nullptr;
   double normT2 = 0;
   ModeIndex ix[MAXN];
   void *U[MAXN] = {};
   double *G[MAXN] = {};
   double *sigma = nullptr;
-  double *lev[MAXN] = {}, *cdf[MAXN] = {}, *Zd[MAXN] = {};
+  double *lev[MAXN] = {}, *cdf[MAXN] = {}, *coarse[MAXN] = {}, *Zd[MAXN] = {};
   int64_t *last[MAXN] = {};
   double *tree[MAXN] = {};
   int64_t P2[MAXN] = {};
@@ -57,6 +55,18 @@ struct cp_ctx {
   void *tmp = nullptr;
   double *d_fit = nullptr, *fit_partial = nullptr;
   int64_t max_I = 0, max_cols = 0;
+  bool index_owner = false;  // the per-mode indices are this context's
+  int ws_R = 0;              // largest rank the workspaces serve
+  int bb_fixed = -1;         // bucket shift set by the caller (-1: by rank)
+  int bb = 7;                // bucket shift of this context's rank
+  bool sketched = false;     // solve with the sketched Gram of the draws
+  double *hs = nullptr;      // J x R: draws scaled by 1 / sqrt(J p)
+  double *Gs = nullptr;      // R x R: their Gram
+  // bucket shift of the sampled MTTKRP for rank r
+  int bshift(int r) const {
+    return bb_fixed >= 0 ? bb_fixed : bucket_shift(r, (int)tsize());
+  }
+  int64_t *bk_start_bb[8][MAXN] = {};  // bucket regions per bucket shift
   int sampled_mode = -1, mttkrp_mode = -1;
   int64_t cur_J = 0;
   bool factor_set[MAXN] = {};
@@ -142,6 +152,7 @@ ModeList make_ml(cp_ctx *c, int j) {
     st *= (uint64_t)c->dims[k];
     ml.lev[q] = c->lev[k];
     ml.cdf[q] = c->cdf[k];
+    ml.coarse[q] = c->coarse[k];
     ml.Z[q] = c->Zd[k];
     ml.last[q] = c->last[k];
     ml.tree[q] = c->tree[k];
@@ -213,6 +224,10 @@ cp_status guard(cp_ctx *c, F &&fn) {
   }
 }
 
+bool valid_bucket_rows(int32_t b) {
+  return b == 0 || b == 16 || b == 32 || b == 64 || b == 128 || b == 256;
+}
+
 void check_mode(cp_ctx *c, int mode) {
   require(mode >= 0 && mode < c->N, CP_EINVAL, "mode out of range");
 }
@@ -238,8 +253,8 @@ void rebuild_sampler(cp_ctx *c, int k) {
     m1.G[0] = c->G[k];
     hadamard_pinv(m1, c->R, c->Gfull1, c->Gp1, nullptr, nullptr, c->pv_scratch,
                   c->d_err, c->s);
-    arls_build<T>(U, c->dims[k], c->R, c->Gp1, c->lev[k], c->cdf[k], c->Zd[k],
-                  c->last[k], c->tmp, c->d_err, c->s);
+    arls_build<T>(U, c->dims[k], c->R, c->Gp1, c->lev[k], c->cdf[k],
+                  c->coarse[k], c->Zd[k], c->last[k], c->tmp, c->d_err, c->s);
   } else if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, k)) {
     sts_build<T>(U, c->dims[k], c->R, c->F, c->P2[k], c->tree[k], c->s);
   }
@@ -327,8 +342,8 @@ void do_mttkrp(cp_ctx *c, int mode) {
                     static_cast<const T *>(ix.val), c->R, M, c->s);
   } else {
     sampled_mttkrp<T>(c->w, c->dims[mode], ix.col_ptr, ix.row,
-                      static_cast<const T *>(ix.val), ix.bk_start, c->R, M,
-                      c->s);
+                      static_cast<const T *>(ix.val), ix.bk_start, c->R,
+                      c->bb, M, c->s);
   }
   c->mttkrp_mode = mode;
 }
@@ -339,8 +354,22 @@ void do_solve(cp_ctx *c, int mode) {
   T *U = static_cast<T *>(c->U[mode]);
   {
     PhaseScope ps(c, PH_SOLVE);
+    const double *Gf = c->Gfull, *Gp = c->Gp;
+    if (c->sketched && c->sampler != CP_SAMPLER_EXACT) {
+      // G~ of this solve's draws (Fig. 3) and its pseudo-inverse
+      sketched_gram<T>(static_cast<const T *>(c->h), c->prob, c->cur_J,
+                       c->R, c->hs, c->Gs, c->tmp, c->s);
+      ModeList m1;
+      std::memset(&m1, 0, sizeof(m1));
+      m1.n = 1;
+      m1.G[0] = c->Gs;
+      hadamard_pinv(m1, c->R, c->Gfull1, c->Gp1, nullptr, nullptr,
+                    c->pv_scratch, c->d_err, c->s);
+      Gf = c->Gfull1;
+      Gp = c->Gp1;
+    }
     const int nblk = solve_blocks(I);
-    solve_rows<T>(static_cast<const T *>(c->M), I, c->R, c->Gfull, c->Gp, c->X,
+    solve_rows<T>(static_cast<const T *>(c->M), I, c->R, Gf, Gp, c->X,
                   c->partial, nblk, c->w.stats + 3, c->s);
     column_norms(c->partial, nblk, c->R, c->sigma, c->d_err, c->s);
   }
@@ -366,11 +395,15 @@ void do_solve(cp_ctx *c, int mode) {
 template <typename T>
 void do_fit(cp_ctx *c, double *fit) {
   const ModeList ml = make_ml_all(c);
+  const ModeList m0 = make_ml(c, 0);
+  const ModeIndex &ix = c->ix[0];
   const int nb = fit_blocks(c->nnz);
   {
     PhaseScope ps(c, PH_FIT);
-    fit_inner<T>(c->coo_idx, static_cast<const T *>(c->coo_val), c->nnz, c->N,
-                 ml, c->sigma, c->R, c->fit_partial, nb, c->s);
+    fit_inner_index<T>(ix.col_ptr, ix.col_key, ix.n_cols, ix.row,
+                       static_cast<const T *>(ix.val), c->nnz,
+                       static_cast<const T *>(c->U[0]), m0, c->sigma, c->R,
+                       c->fit_partial, nb, c->s);
     fit_finish(ml, c->N, c->R, c->sigma, c->fit_partial, nb, c->normT2,
                c->d_fit, c->s);
   }
@@ -385,8 +418,8 @@ int64_t next_pow2(int64_t x) {
   return p;
 }
 
-void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
-  c->N = t->N;
+void set_config(cp_ctx *c, int N, const int64_t *dims, const cp_config *cfg) {
+  c->N = N;
   c->R = cfg->R;
   c->sampler = cfg->sampler;
   c->precision = cfg->precision;
@@ -395,10 +428,21 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   c->gram_mode = c->precision == CP_FP64   ? GRAM_F64
                  : c->precision == CP_FP32 ? GRAM_F32
                                            : GRAM_BF16X3;
-  c->nnz = t->nnz;
   c->max_J = cfg->max_J;
-  const int N = c->N, R = c->R;
-  for (int k = 0; k < N; ++k) c->dims[k] = t->dims[k];
+  c->sketched = cfg->solve_gram == CP_GRAM_SKETCHED &&
+                cfg->sampler != CP_SAMPLER_EXACT;
+  c->bb_fixed = -1;
+  for (int b = 4; b <= 8; ++b)
+    if (cfg->bucket_rows == (1 << b)) c->bb_fixed = b;
+  for (int k = 0; k < N; ++k) c->dims[k] = dims[k];
+  c->max_I = 0;
+  for (int k = 0; k < N; ++k) c->max_I = std::max(c->max_I, dims[k]);
+}
+
+// Validated per-mode column-sorted indices (Section 4.3) and ||T||^2.
+void init_index(cp_ctx *c, const cp_tensor *t) {
+  const int N = c->N;
+  c->nnz = t->nnz;
   dalloc(c, &c->d_err, 4);
   dalloc(c, &c->d_dims, N * 8);
   hip_ok(hipMemsetAsync(c->d_err, 0, 4, c->s), "hipMemsetAsync");
@@ -411,11 +455,6 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   } catch (const Fail &f) {
     throw Fail{CP_EINVAL, "invalid tensor: " + f.msg};
   }
-  // COO copy for the fit, values in the path's precision
-  dalloc(c, &c->coo_idx, (size_t)t->nnz * N * 4);
-  hip_ok(hipMemcpyAsync(c->coo_idx, t->idx, (size_t)t->nnz * N * 4,
-                        hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
-  dalloc(c, &c->coo_val, (size_t)t->nnz * c->tsize());
   for (int k = 0; k < N; ++k) {
     std::string e = build_mode_index(t->idx, t->val, t->val_is_fp64, t->nnz, N,
                                      c->dims, k, c->f64, c->ix[k], c->d_err,
@@ -430,14 +469,34 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
                                                          : CP_ENOMEM, e};
     read_errors(c);
     c->max_cols = std::max(c->max_cols, c->ix[k].n_cols);
-    c->max_I = std::max(c->max_I, c->dims[k]);
   }
-  // values of the COO copy, in the path's precision
-  convert_values(t->val, t->val_is_fp64, c->coo_val, c->f64, t->nnz, c->s);
-  c->normT2 = sum_squares(c->coo_val, c->f64, c->nnz, c->s);
+  // ||T||^2 of the values in the path's precision (mode 0's copy)
+  c->normT2 = sum_squares(c->ix[0].val, c->f64, c->nnz, c->s);
   require(c->normT2 > 0, CP_EINVAL, "tensor has zero norm");
+  c->index_owner = true;
+}
 
+// Record regions of the sampled MTTKRP's output-row buckets of 2^bb rows,
+// per mode (built once per bucket size by the context owning the index).
+void ensure_bucket_regions(cp_ctx *c, int bb, int64_t *scratch,
+                           void *scan_tmp) {
+  if (c->bk_start_bb[bb][0]) return;
+  for (int k = 0; k < c->N; ++k) {
+    const int64_t nbk_k = (c->dims[k] + (1 << bb) - 1) >> bb;
+    dalloc(c, &c->bk_start_bb[bb][k], (size_t)(nbk_k + 1) * 8);
+    bucket_regions(c->ix[k].row, c->nnz, c->dims[k], bb,
+                   c->bk_start_bb[bb][k], scratch, scan_tmp, c->s);
+  }
+}
+
+// Factors, Grams, sigma and the sampler structures of one decomposition.
+void init_state(cp_ctx *c) {
+  const int N = c->N, R = c->R;
   const size_t ts = c->tsize();
+  if (!c->d_err) {
+    dalloc(c, &c->d_err, 4);
+    hip_ok(hipMemsetAsync(c->d_err, 0, 4, c->s), "hipMemsetAsync");
+  }
   for (int k = 0; k < N; ++k) {
     const int64_t I = c->dims[k];
     dalloc(c, &c->U[k], (size_t)I * R * ts);
@@ -445,22 +504,38 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     if (c->sampler == CP_SAMPLER_ARLS_LEV) {
       dalloc(c, &c->lev[k], I * 8);
       dalloc(c, &c->cdf[k], I * 8);
+      dalloc(c, &c->coarse[k], ((I + ARLS_CHUNK - 1) / ARLS_CHUNK) * 8);
       dalloc(c, &c->Zd[k], 8);
       dalloc(c, &c->last[k], 8);
     } else if (c->sampler == CP_SAMPLER_STS) {
       c->P2[k] = next_pow2((I + c->F - 1) / c->F);
-      dalloc(c, &c->tree[k], (size_t)2 * c->P2[k] * sts_packed(R) * 8);
+      if (sts_tree_factor(N, k))
+        dalloc(c, &c->tree[k], (size_t)2 * c->P2[k] * sts_packed(R) * 8);
     }
   }
+  dalloc(c, &c->sigma, R * 8);
+  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(MAXR), 0, c->s, c->sigma,
+                     (int64_t)R, 1.0);
+  CPR_LAUNCH_CHECK();
+}
+
+// Workspaces of a mode solve for every rank up to Rws (shared by the
+// contexts of one stream in a batch; each solve leaves them ready for the
+// next one).  `own` holds the index (bucket regions are built there).
+void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
+  const int N = c->N;
+  const size_t ts = c->tsize();
+  c->ws_R = Rws;
   if (c->sampler == CP_SAMPLER_STS) {
-    int64_t mI = 0;
-    for (int k = 0; k < N; ++k) mI = std::max(mI, c->dims[k]);
+    int64_t mI = 0, mP2 = 1;
+    for (int k = 0; k < N; ++k) {
+      mI = std::max(mI, c->dims[k]);
+      mP2 = std::max(mP2, next_pow2((c->dims[k] + c->F - 1) / c->F));
+    }
     dalloc(c, &c->sw.lev, sts_first_rows(mI) * 8);
     dalloc(c, &c->sw.sub, sts_first_sums(mI) * 8);
-    int64_t mP2 = 1;
-    for (int k = 0; k < N; ++k) mP2 = std::max(mP2, c->P2[k]);
     const int64_t Js = std::max<int64_t>(c->max_J, 1);
-    dalloc(c, &c->sw.h, (size_t)Js * sts_pad(R) * 8);
+    dalloc(c, &c->sw.h, (size_t)Js * sts_pad(Rws) * 8);
     for (int b = 0; b < 2; ++b) {
       dalloc(c, &c->sw.slot[b].s, Js * 4);
       dalloc(c, &c->sw.slot[b].v, Js * 4);
@@ -473,22 +548,22 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
     dalloc(c, &c->sw.send, 2 * mP2 * 4);
     dalloc(c, &c->sw.tcnt, (size_t)sts_top_counts(Js) * 4);
   }
-  dalloc(c, &c->sigma, R * 8);
-  dalloc(c, &c->Gfull, R * R * 8);
-  dalloc(c, &c->Gp, R * R * 8);
-  dalloc(c, &c->Gfull1, R * R * 8);
-  dalloc(c, &c->Gp1, R * R * 8);
-  dalloc(c, &c->pv_scratch, R * R * 8);
-  dalloc(c, &c->ggt, (size_t)(N - 1) * R * R * 8);
+  const size_t RR = (size_t)Rws * Rws * 8;
+  dalloc(c, &c->Gfull, RR);
+  dalloc(c, &c->Gp, RR);
+  dalloc(c, &c->Gfull1, RR);
+  dalloc(c, &c->Gp1, RR);
+  dalloc(c, &c->pv_scratch, RR);
+  dalloc(c, &c->ggt, (size_t)(N - 1) * RR);
   dalloc(c, &c->trace, 8);
   const int64_t J = std::max<int64_t>(c->max_J, 1);
   dalloc(c, &c->sidx, (size_t)J * (N - 1) * 4);
   dalloc(c, &c->prob, J * 8);
-  dalloc(c, &c->h, (size_t)J * R * ts);
+  dalloc(c, &c->h, (size_t)J * Rws * ts);
   dalloc(c, &c->w.col_id, J * 4);
-  dalloc(c, &c->w.owner, c->max_cols * 4);
+  dalloc(c, &c->w.owner, own->max_cols * 4);
   dalloc(c, &c->w.dupcnt, J * 4);
-  dalloc(c, &c->w.hc, (size_t)J * R * ts);
+  dalloc(c, &c->w.hc, (size_t)J * Rws * ts);
   dalloc(c, &c->w.uq_s, J * 4);
   dalloc(c, &c->w.uq_cid, J * 4);
   dalloc(c, &c->w.uq_cnt, J * 4);
@@ -499,67 +574,108 @@ void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
   dalloc(c, &c->w.counts, 16);
   dalloc(c, &c->w.stats, 4 * 8);
   dalloc(c, &c->w.scratch, (size_t)4 * J * 8);
-  // output-row buckets of the sampled MTTKRP and the record capacity: at
-  // most J distinct columns are extracted, so the J longest columns of a
-  // mode bound the extracted nonzeros of any of its solves
-  const int bb = bucket_shift(R, (int)ts);
-  const int64_t nbk = (c->max_I + (1 << bb) - 1) >> bb;
+  // output-row buckets of the sampled MTTKRP: the smallest bucket (most
+  // buckets) and the largest B x R block over the ranks served
+  int bb_min = 30;
+  for (int r = 1; r <= Rws; ++r) bb_min = std::min(bb_min, c->bshift(r));
+  const int64_t nbk = (c->max_I + (1 << bb_min) - 1) >> bb_min;
   dalloc(c, &c->w.scan_tmp, std::max(scan_temp_bytes(J),
                                      scan_temp_bytes(nbk + 1)));
   dalloc(c, &c->w.bk, (size_t)5 * (nbk + 1) * 8);
   c->w.bk_max = nbk;
+  // record capacity: at most J distinct columns are extracted, so the J
+  // longest columns of a mode bound the extracted nonzeros of any solve
   int64_t cap = 1;
   if (c->sampler != CP_SAMPLER_EXACT) {
     for (int k = 0; k < N; ++k) {
-      const int64_t nc = c->ix[k].n_cols;
-      std::vector<int64_t> ptr(nc + 1);
-      hip_ok(hipMemcpyAsync(ptr.data(), c->ix[k].col_ptr, (nc + 1) * 8,
-                            hipMemcpyDeviceToHost, c->s), "hipMemcpyAsync");
-      hip_ok(hipStreamSynchronize(c->s), "hipStreamSynchronize");
-      std::vector<int64_t> len(nc);
-      for (int64_t i = 0; i < nc; ++i) len[i] = ptr[i + 1] - ptr[i];
-      int64_t top = 0;
-      if (J >= nc) {
-        top = c->nnz;
-      } else {
-        std::nth_element(len.begin(), len.begin() + J, len.end(),
-                         std::greater<int64_t>());
-        for (int64_t i = 0; i < J; ++i) top += len[i];
-      }
-      cap = std::max(cap, std::min(top, c->nnz));
+      const int64_t top = top_columns_total(own->ix[k].col_ptr,
+                                            own->ix[k].n_cols, own->nnz, J,
+                                            c->s);
+      require(top >= 0, CP_EHIP, "column length statistics failed");
+      cap = std::max(cap, top);
     }
   }
   c->w.rec_cap = cap;
   if (c->sampler != CP_SAMPLER_EXACT) {
     // records sit in each bucket's fixed region: nnz of them at most
     dalloc(c, &c->w.rec, (size_t)c->nnz * bucket_record_bytes((int)ts));
-    for (int k = 0; k < N; ++k) {
-      const int64_t nbk_k = (c->dims[k] + (1 << bb) - 1) >> bb;
-      dalloc(c, &c->ix[k].bk_start, (size_t)(nbk_k + 1) * 8);
-      bucket_regions(c->ix[k].row, c->nnz, c->dims[k], bb, c->ix[k].bk_start,
-                     c->w.bk, c->w.scan_tmp, c->s);
-    }
+    for (int r = 1; r <= Rws; ++r)
+      ensure_bucket_regions(own, c->bshift(r), c->w.bk,
+                            c->w.scan_tmp);
   }
   // bucket fill cursors start at zero; the accumulation plan clears them
   // again after every sampled MTTKRP
   zero_fill<int64_t>(c->w.bk, (size_t)5 * (nbk + 1), c->s);
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);
-  dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * (1 << bb) * R * ts);
+  size_t blk = 0;  // largest B x R block of a split bucket
+  for (int r = 1; r <= Rws; ++r)
+    blk = std::max(blk, ((size_t)1 << c->bshift(r)) * r * ts);
+  dalloc(c, &c->w.part, (size_t)bucket_max_items(cap, nbk) * blk);
   zero_fill<int64_t>(c->w.stats, 4, c->s);
-  dalloc(c, &c->M, (size_t)c->max_I * R * ts);
-  dalloc(c, &c->X, (size_t)c->max_I * R * 8);
-  dalloc(c, &c->partial, (size_t)(1024 + 2) * R * 8);
-  dalloc(c, &c->tmp, std::max(gram_temp_bytes(c->max_I, R),
+  dalloc(c, &c->M, (size_t)c->max_I * Rws * ts);
+  dalloc(c, &c->X, (size_t)c->max_I * Rws * 8);
+  dalloc(c, &c->partial, (size_t)(1024 + 2) * Rws * 8);
+  dalloc(c, &c->tmp, std::max(gram_temp_bytes(std::max(c->max_I, J), Rws),
                               256 + scan_temp_bytes(c->max_I)));
+  if (c->sketched) {
+    dalloc(c, &c->hs, (size_t)J * Rws * 8);
+    dalloc(c, &c->Gs, RR);
+  }
   dalloc(c, &c->d_fit, 4 * 8);
   dalloc(c, &c->fit_partial, fit_blocks(c->nnz) * 8);
-  hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(c->max_cols, 256)), dim3(256),
-                     0, c->s, c->w.owner, c->max_cols, INT_MAX);
+  hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div(own->max_cols, 256)), dim3(256),
+                     0, c->s, c->w.owner, own->max_cols, INT_MAX);
   zero_fill<int32_t>(c->w.dupcnt, J, c->s);
-  hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(MAXR), 0, c->s, c->sigma,
-                     (int64_t)R, 1.0);
   CPR_LAUNCH_CHECK();
+}
+
+// The index (and its bucket regions for this rank) of `own`, borrowed.
+void borrow_index(cp_ctx *c, const cp_ctx *own) {
+  c->nnz = own->nnz;
+  c->normT2 = own->normT2;
+  c->max_cols = own->max_cols;
+  for (int k = 0; k < c->N; ++k) c->ix[k] = own->ix[k];
+}
+
+// Workspace pointers of `ws` (sized for ranks up to ws->ws_R), borrowed.
+void borrow_workspace(cp_ctx *c, const cp_ctx *ws) {
+  c->ws_R = ws->ws_R;
+  c->sw = ws->sw;
+  c->Gfull = ws->Gfull;
+  c->Gp = ws->Gp;
+  c->Gfull1 = ws->Gfull1;
+  c->Gp1 = ws->Gp1;
+  c->pv_scratch = ws->pv_scratch;
+  c->ggt = ws->ggt;
+  c->trace = ws->trace;
+  c->sidx = ws->sidx;
+  c->prob = ws->prob;
+  c->h = ws->h;
+  c->w = ws->w;
+  c->M = ws->M;
+  c->X = ws->X;
+  c->partial = ws->partial;
+  c->tmp = ws->tmp;
+  c->d_fit = ws->d_fit;
+  c->fit_partial = ws->fit_partial;
+  c->hs = ws->hs;
+  c->Gs = ws->Gs;
+}
+
+// The bucket regions matching this context's rank.
+void select_bucket_regions(cp_ctx *c, const cp_ctx *own) {
+  const int bb = c->bshift(c->R);
+  c->bb = bb;
+  for (int k = 0; k < c->N; ++k) c->ix[k].bk_start = own->bk_start_bb[bb][k];
+}
+
+void init_ctx(cp_ctx *c, const cp_tensor *t, const cp_config *cfg) {
+  set_config(c, t->N, t->dims, cfg);
+  init_index(c, t);
+  init_state(c);
+  init_workspace(c, c, c->R);
+  select_bucket_regions(c, c);
   read_errors(c);
 }
 
@@ -572,6 +688,96 @@ void destroy_ctx(cp_ctx *c) {
     (void)hipEventDestroy(e.b);
   }
   delete c;
+}
+
+
+// Batched restarts: B decompositions of one tensor share its per-mode
+// indices (built once by `base`); restart b has its own factors, Grams,
+// sigma and sampler structures.  Restarts are spread over `st` streams
+// (decreasing rank, round-robin); the restarts of one stream run one after
+// another and share one set of workspaces, sized for the stream's largest
+// rank.  A sweep of all restarts is captured once into a HIP graph (fork
+// from the caller's stream into the branch streams, join back) and replayed
+// with one hipGraphLaunch per sweep.
+struct BatchState {
+  cp_ctx *base = nullptr;
+  std::vector<cp_ctx *> r;
+  std::vector<int> branch;
+  std::vector<hipStream_t> st;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipStream_t s = nullptr;   // the caller's stream (may be the null stream)
+  hipStream_t cs = nullptr;  // the batch's own stream the graph is captured on
+  int B = 0, N = 0;
+  int64_t J = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const double *cap_uni = nullptr;
+};
+
+template <typename T>
+void restart_sweep(cp_ctx *c, int64_t J, const double *uni) {
+  const int N = c->N;
+  for (int j = 0; j < N; ++j) {
+    do_sample<T>(c, j, J, uni + (int64_t)j * J * (N - 1));
+    do_mttkrp<T>(c, j);
+    do_solve<T>(c, j);
+  }
+}
+
+void drop_graph(BatchState &b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr;
+  b.graph = nullptr;
+  b.cap_uni = nullptr;
+}
+
+// Captured on the batch's own stream (capture is not possible on the null
+// stream); the graph is then launched on the caller's stream.
+void capture_sweep(BatchState &b, const double *uni) {
+  drop_graph(b);
+  hip_ok(hipStreamBeginCapture(b.cs, hipStreamCaptureModeThreadLocal),
+         "hipStreamBeginCapture");
+  try {
+    hip_ok(hipEventRecord(b.fork, b.cs), "hipEventRecord");
+    for (hipStream_t x : b.st)
+      hip_ok(hipStreamWaitEvent(x, b.fork, 0), "hipStreamWaitEvent");
+    const int64_t per = (int64_t)b.N * b.J * (b.N - 1);
+    for (int i = 0; i < b.B; ++i) {
+      cp_ctx *c = b.r[i];
+      c->s = b.st[b.branch[i]];
+      if (c->f64) restart_sweep<double>(c, b.J, uni + i * per);
+      else restart_sweep<float>(c, b.J, uni + i * per);
+      c->s = b.s;
+    }
+    for (size_t q = 0; q < b.st.size(); ++q) {
+      hip_ok(hipEventRecord(b.join[q], b.st[q]), "hipEventRecord");
+      hip_ok(hipStreamWaitEvent(b.cs, b.join[q], 0), "hipStreamWaitEvent");
+    }
+  } catch (...) {
+    for (cp_ctx *c : b.r) c->s = b.s;
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(b.cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_ok(hipStreamEndCapture(b.cs, &b.graph), "hipStreamEndCapture");
+  hip_ok(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0),
+         "hipGraphInstantiate");
+  b.cap_uni = uni;
+}
+
+void destroy_batch(BatchState *b) {
+  if (!b) return;
+  if (b->s) (void)hipStreamSynchronize(b->s);
+  drop_graph(*b);
+  for (cp_ctx *c : b->r) destroy_ctx(c);
+  destroy_ctx(b->base);
+  for (hipStream_t x : b->st) (void)hipStreamDestroy(x);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
 }
 
 }  // namespace
@@ -596,6 +802,8 @@ cp_status cp_init(const cp_tensor *t, const cp_config *cfg, void *stream,
   if (cfg->sts_leaf != 0 && cfg->sts_leaf != 16 && cfg->sts_leaf != 32 &&
       cfg->sts_leaf != 64)
     return CP_EINVAL;
+  if (!valid_bucket_rows(cfg->bucket_rows)) return CP_EINVAL;
+  if (cfg->solve_gram < 0 || cfg->solve_gram > 1) return CP_EINVAL;
   cp_ctx *c = new (std::nothrow) cp_ctx;
   if (!c) return CP_ENOMEM;
   c->s = static_cast<hipStream_t>(stream);
@@ -998,6 +1206,205 @@ const char *cp_status_string(cp_status s) {
     case CP_EUNSUPPORTED: return "CP_EUNSUPPORTED";
   }
   return "unknown";
+}
+
+
+// ---------------------------------------------------------------- batches
+
+}  // extern "C"
+
+struct cp_batch {
+  BatchState b;
+  std::string msg;
+};
+
+namespace {
+template <typename F>
+cp_status bguard(cp_batch *bt, F &&fn) {
+  try {
+    fn();
+    bt->msg.clear();
+    return CP_OK;
+  } catch (const Fail &f) {
+    bt->msg = f.msg;
+    return f.st;
+  } catch (const HipFail &h) {
+    bt->msg = std::string("HIP launch error: ") + hipGetErrorString(h.e) +
+              " at " + h.file + ":" + std::to_string(h.line);
+    return CP_EHIP;
+  } catch (const std::bad_alloc &) {
+    bt->msg = "host allocation failed";
+    return CP_ENOMEM;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+cp_status cp_batch_init(const cp_tensor *t, int32_t B, const int32_t *ranks,
+                        const cp_config *cfg, int32_t nstreams, void *stream,
+                        cp_batch **out) {
+  if (!out) return CP_EINVAL;
+  *out = nullptr;
+  if (!t || !cfg || !ranks || !t->dims || !t->idx || !t->val) return CP_EINVAL;
+  if (B < 1 || B > 4096 || nstreams < 0 || nstreams > 32) return CP_EINVAL;
+  if (t->N < 3 || t->N > MAXN || t->nnz < 1 || t->nnz >= (int64_t(1) << 32))
+    return CP_EINVAL;
+  for (int k = 0; k < t->N; ++k)
+    if (t->dims[k] < 1 || t->dims[k] >= (int64_t(1) << 31)) return CP_EINVAL;
+  int rmax = 0;
+  for (int i = 0; i < B; ++i) {
+    if (ranks[i] < 1 || ranks[i] > MAXR) return CP_EINVAL;
+    rmax = std::max(rmax, (int)ranks[i]);
+  }
+  if (cfg->sampler < 0 || cfg->sampler > 1) return CP_EINVAL;
+  if (cfg->precision < 0 || cfg->precision > 2) return CP_EINVAL;
+  if (cfg->max_J < 1 || cfg->max_J > (int64_t(1) << 24)) return CP_EINVAL;
+  if (cfg->sts_leaf != 0 && cfg->sts_leaf != 16 && cfg->sts_leaf != 32 &&
+      cfg->sts_leaf != 64)
+    return CP_EINVAL;
+  if (!valid_bucket_rows(cfg->bucket_rows)) return CP_EINVAL;
+  if (cfg->solve_gram < 0 || cfg->solve_gram > 1) return CP_EINVAL;
+  cp_batch *bt = new (std::nothrow) cp_batch;
+  if (!bt) return CP_ENOMEM;
+  *out = bt;
+  BatchState &b = bt->b;
+  b.s = static_cast<hipStream_t>(stream);
+  b.B = B;
+  b.N = t->N;
+  b.J = cfg->max_J;
+  return bguard(bt, [&] {
+    cp_config c0 = *cfg;
+    c0.R = rmax;
+    b.base = new cp_ctx;
+    b.base->s = b.s;
+    set_config(b.base, t->N, t->dims, &c0);
+    init_index(b.base, t);
+    const int ns = std::min<int>(nstreams ? nstreams : 4, B);
+    for (int q = 0; q < ns; ++q) {
+      hipStream_t x = nullptr;
+      hip_ok(hipStreamCreateWithFlags(&x, hipStreamNonBlocking),
+             "hipStreamCreateWithFlags");
+      b.st.push_back(x);
+      hipEvent_t e = nullptr;
+      hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming),
+             "hipEventCreate");
+      b.join.push_back(e);
+    }
+    hip_ok(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming),
+           "hipEventCreate");
+    hip_ok(hipStreamCreateWithFlags(&b.cs, hipStreamNonBlocking),
+           "hipStreamCreateWithFlags");
+    std::vector<int> order(B);
+    for (int i = 0; i < B; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return ranks[x] > ranks[y]; });
+    b.r.assign(B, nullptr);
+    b.branch.assign(B, 0);
+    std::vector<cp_ctx *> owner(ns, nullptr);
+    for (int o = 0; o < B; ++o) {
+      const int i = order[o], q = o % ns;
+      cp_config ci = *cfg;
+      ci.R = ranks[i];
+      cp_ctx *c = new cp_ctx;
+      b.r[i] = c;
+      b.branch[i] = q;
+      c->s = b.s;
+      set_config(c, t->N, t->dims, &ci);
+      borrow_index(c, b.base);
+      init_state(c);
+      if (!owner[q]) {  // the stream's largest rank: its workspaces
+        init_workspace(c, b.base, c->R);
+        owner[q] = c;
+      } else {
+        borrow_workspace(c, owner[q]);
+      }
+      select_bucket_regions(c, b.base);
+    }
+    read_errors(b.base);
+  });
+}
+
+cp_status cp_batch_set_factors(cp_batch *bt, int32_t b, int32_t mode,
+                               const double *U) {
+  if (!bt || !bt->b.base) return CP_EINVAL;
+  return bguard(bt, [&] {
+    require(b >= 0 && b < bt->b.B, CP_EINVAL, "restart out of range");
+    cp_ctx *c = bt->b.r[b];
+    check_mode(c, mode);
+    require(U != nullptr, CP_EINVAL, "null factor");
+    if (c->f64) do_set_factor<double>(c, mode, U);
+    else do_set_factor<float>(c, mode, U);
+    c->factor_set[mode] = true;
+    c->sampled_mode = c->mttkrp_mode = -1;
+  });
+}
+
+cp_status cp_batch_sweep(cp_batch *bt, const double *uni) {
+  if (!bt || !bt->b.base) return CP_EINVAL;
+  return bguard(bt, [&] {
+    BatchState &b = bt->b;
+    require(uni != nullptr, CP_EINVAL, "null uniforms");
+    for (cp_ctx *c : b.r) check_factors(c);
+    if (!b.exec || uni != b.cap_uni) capture_sweep(b, uni);
+    hip_ok(hipGraphLaunch(b.exec, b.s), "hipGraphLaunch");
+  });
+}
+
+cp_status cp_batch_fit(cp_batch *bt, double *fits) {
+  if (!bt || !bt->b.base || !fits) return CP_EINVAL;
+  return bguard(bt, [&] {
+    for (int i = 0; i < bt->b.B; ++i) {
+      cp_ctx *c = bt->b.r[i];
+      check_factors(c);
+      if (c->f64) do_fit<double>(c, &fits[i]);
+      else do_fit<float>(c, &fits[i]);
+    }
+  });
+}
+
+cp_status cp_batch_sync(cp_batch *bt) {
+  if (!bt || !bt->b.base) return CP_EINVAL;
+  return bguard(bt, [&] {
+    for (cp_ctx *c : bt->b.r) read_errors(c);
+    read_errors(bt->b.base);
+  });
+}
+
+cp_status cp_batch_get_factor(cp_batch *bt, int32_t b, int32_t mode,
+                              double *U_out) {
+  if (!bt || !bt->b.base || !U_out) return CP_EINVAL;
+  return bguard(bt, [&] {
+    require(b >= 0 && b < bt->b.B, CP_EINVAL, "restart out of range");
+    cp_ctx *c = bt->b.r[b];
+    check_mode(c, mode);
+    copy_to_f64(c->U[mode], c->f64, U_out, c->dims[mode] * c->R, c->s);
+  });
+}
+
+cp_status cp_batch_get_sigma(cp_batch *bt, int32_t b, double *sigma_out) {
+  if (!bt || !bt->b.base || !sigma_out) return CP_EINVAL;
+  return bguard(bt, [&] {
+    require(b >= 0 && b < bt->b.B, CP_EINVAL, "restart out of range");
+    cp_ctx *c = bt->b.r[b];
+    hip_ok(hipMemcpyAsync(sigma_out, c->sigma, c->R * 8,
+                          hipMemcpyDeviceToDevice, c->s), "hipMemcpyAsync");
+  });
+}
+
+int32_t cp_batch_stream_of(const cp_batch *bt, int32_t b) {
+  if (!bt || b < 0 || b >= bt->b.B) return -1;
+  return bt->b.branch[b];
+}
+
+void cp_batch_destroy(cp_batch *bt) {
+  if (!bt) return;
+  destroy_batch(&bt->b);
+  delete bt;
+}
+
+const char *cp_batch_last_error(const cp_batch *bt) {
+  return bt ? bt->msg.c_str() : "null batch";
 }
 
 }  // extern "C"

@@ -43,6 +43,7 @@ struct ModeList {
   uint64_t stride[MAXN];      // column-key stride of each mode for mode j
   const double *lev[MAXN];    // ARLS scores
   const double *cdf[MAXN];    // ARLS inclusive prefix sums
+  const double *coarse[MAXN]; // ARLS prefix sum at the end of each 64 rows
   const double *Z[MAXN];      // ARLS totals (device scalars)
   const int64_t *last[MAXN];  // ARLS last row of positive mass
   const double *tree[MAXN];   // STS trees
@@ -58,10 +59,11 @@ struct ModeIndex {
   int64_t I = 0, n_cols = 0, max_col = 0;
   uint64_t *col_key = nullptr;  // n_cols sorted distinct column keys
   int64_t *col_ptr = nullptr;   // n_cols + 1 offsets
-  // column lookup: open addressing with linear probing over 2^hbits entries
-  // of two words {key, column} (hash: 2 << hbits words), at most half full;
-  // key ~0 marks an empty entry (column keys have at most 63 bits)
-  uint64_t *hash = nullptr;
+  // column lookup: open addressing with linear probing over 2^hbits
+  // entries, each the 32-bit id of a column (its key is col_key[id]), at
+  // most half full; ~0 marks an empty entry.  4 bytes per entry: 8 to 16
+  // bytes per nonempty column.
+  uint32_t *hash = nullptr;
   int hbits = 0;
   // sampled MTTKRP: record region start of each output-row bucket (set up
   // by cp_init for the sampling samplers)
@@ -79,6 +81,11 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
                              int64_t nnz, int N, const int64_t *dims, int j,
                              int out_fp64, ModeIndex &out, uint32_t *err,
                              hipStream_t s);
+
+// Sum of the lengths of the J longest columns (nnz if J >= n_cols); -1 on
+// a HIP failure.
+int64_t top_columns_total(const int64_t *col_ptr, int64_t n_cols, int64_t nnz,
+                          int64_t J, hipStream_t s);
 
 // ---- scans (k_scan.hip): deterministic reduce-then-scan
 size_t scan_temp_bytes(int64_t n);
@@ -104,6 +111,11 @@ void gram(const T *U, int64_t I, int R, double *G, void *tmp, int mode,
 template <typename T>
 void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
                  double *G, void *tmp, int mode, hipStream_t s);
+// G~ = sum_s h_s h_s^T / (J p_s) over J draws (h: J x R, factor precision),
+// the sketched Gram of Fig. 3; hs: J x R FP64 scratch, tmp as for gram.
+template <typename T>
+void sketched_gram(const T *h, const double *prob, int64_t J, int R,
+                   double *hs, double *Gs, void *tmp, hipStream_t s);
 // sigma[r] = sqrt of the sum over the nblk partial rows of column r
 void column_norms(const double *partial, int nblk, int R, double *sigma,
                   uint32_t *err, hipStream_t s);
@@ -136,10 +148,11 @@ void convert_values(const void *src, int src_fp64, void *dst, int dst_fp64,
                     int64_t n, hipStream_t s);
 
 // ---- CP-ARLS-LEV (k_arls.hip)
+constexpr int ARLS_CHUNK = 64;  // rows per entry of the coarse CDF
 template <typename T>
 void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
-                double *cdf, double *Z, int64_t *last, void *tmp,
-                uint32_t *err, hipStream_t s);
+                double *cdf, double *coarse, double *Z, int64_t *last,
+                void *tmp, uint32_t *err, hipStream_t s);
 template <typename T>
 void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,
                int32_t *sidx, double *prob, T *h, uint32_t *err, hipStream_t s);
@@ -222,10 +235,12 @@ void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
 void merge_samples(int64_t J, const double *prob, const int64_t *col_ptr,
                    const void *h, int R, int tsize, SampleWork &w,
                    hipStream_t s);
+// bb: bucket shift (2^bb output rows per bucket, bb <= 8: a record keeps
+// the row inside its bucket in 8 bits)
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                     const int32_t *row, const T *val, const int64_t *bk_start,
-                    int R, T *M, hipStream_t s);
+                    int R, int bb, T *M, hipStream_t s);
 // Fixed record regions of a mode's output-row buckets of 2^bb rows:
 // starts[b] = nonzeros of the mode in buckets < b (nbk + 1 entries); cnt is
 // nbk + 1 int64 of scratch.
@@ -245,10 +260,13 @@ void debug_unique(const SampleWork &w, int64_t nu_host,
                   int32_t *cnt_out, double *w_out, int64_t cap, hipStream_t s);
 
 // ---- fit (k_fit.hip)
+// ml: the modes != 0 (make_ml for mode 0: strides of mode 0's column keys)
 template <typename T>
-void fit_inner(const int32_t *idx, const T *val, int64_t nnz, int N,
-               const ModeList &ml, const double *sigma, int R, double *partial,
-               int nblk, hipStream_t s);
+void fit_inner_index(const int64_t *col_ptr, const uint64_t *col_key,
+                     int64_t n_cols, const int32_t *row, const T *val,
+                     int64_t nnz, const T *U0, const ModeList &ml,
+                     const double *sigma, int R, double *partial, int nblk,
+                     hipStream_t s);
 int fit_blocks(int64_t nnz);
 void fit_finish(const ModeList &ml, int N, int R, const double *sigma,
                 const double *partial, int nblk, double normT2, double *out,

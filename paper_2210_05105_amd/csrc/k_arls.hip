@@ -106,38 +106,70 @@ __global__ void k_arls_tail(const double *cdf, int64_t I,
 
 constexpr int DR_THREADS = 256;
 
+// Coarse CDF: the inclusive prefix sum at the end of every 64-row chunk
+// (the last chunk ends at row I - 1).
+__global__ void k_arls_coarse(const double *cdf, int64_t I, double *coarse) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nb = (I + ARLS_CHUNK - 1) / ARLS_CHUNK;
+  if (b >= nb) return;
+  const int64_t e = (b + 1) * ARLS_CHUNK - 1;
+  coarse[b] = cdf[e < I ? e : I - 1];
+}
+
+// Draws: index = min{ i : u Z < F(i) } per (sample, factor).  Each lane
+// bisects the coarse CDF for its sample's 64-row chunk (a table 64 times
+// shorter than F, mostly cache resident); then the wave settles the 64
+// chunks of its 64 samples one after another, each with one coalesced
+// load of the chunk's 64 prefix sums and a ballot of u Z < F(i) (the first
+// set lane is the row).  The result is the first row whose prefix sum
+// exceeds the target, as a bisection of F would give.
 template <typename T>
 __global__ void __launch_bounds__(DR_THREADS)
 k_arls_draw(ModeList ml, int64_t J, int R, const double *uni, int32_t *sidx,
             double *prob, T *h, uint32_t *err) {
   __shared__ int32_t sh_idx[DR_THREADS * (MAXN - 1)];
   const int nq = ml.n;
+  const int l = lane_id();
   const int64_t s = (int64_t)blockIdx.x * DR_THREADS + threadIdx.x;
-  if (s < J) {
-    double p = 1.0;
-    for (int q = 0; q < nq; ++q) {
-      double u = uni[s * nq + q];
-      if (!(u >= 0.0 && u < 1.0)) {
-        atomicOr(err, ERR_UNIFORM);
-        u = 0.0;
-      }
-      const double Z = *ml.Z[q];
-      const double t = u * Z;
-      const double *cdf = ml.cdf[q];
-      int64_t lo = 0, hi = ml.I[q];
-      while (lo < hi) {  // first i with t < cdf[i]
-        int64_t mid = (lo + hi) >> 1;
-        if (t < cdf[mid]) hi = mid; else lo = mid + 1;
-      }
-      const int64_t last = *ml.last[q];
-      if (lo > last) lo = last;
-      if (lo < 0) lo = 0;
-      sidx[s * nq + q] = (int32_t)lo;
-      sh_idx[threadIdx.x * nq + q] = (int32_t)lo;
-      p = p * (ml.lev[q][lo] / Z);
+  const bool act = s < J;
+  const int64_t sc = act ? s : J - 1;  // lanes past J follow sample J - 1
+  double p = 1.0;
+  for (int q = 0; q < nq; ++q) {
+    double u = uni[sc * nq + q];
+    if (!(u >= 0.0 && u < 1.0)) {
+      if (act) atomicOr(err, ERR_UNIFORM);
+      u = 0.0;
     }
-    prob[s] = p;
+    const double Z = *ml.Z[q];
+    const double t = u * Z;
+    const int64_t I = ml.I[q];
+    const double *cdf = ml.cdf[q], *coarse = ml.coarse[q];
+    const int64_t nb = (I + ARLS_CHUNK - 1) / ARLS_CHUNK;
+    int64_t lo = 0, hi = nb - 1;  // first chunk whose end exceeds t
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (t < coarse[mid]) hi = mid; else lo = mid + 1;
+    }
+    const int64_t myb = lo;
+    int off = ARLS_CHUNK - 1;
+#pragma unroll 4
+    for (int i = 0; i < WAVE; ++i) {
+      const int64_t bi = __shfl(myb, i, WAVE);
+      const double ti = __shfl(t, i, WAVE);
+      const int64_t e = bi * ARLS_CHUNK + l;
+      const double v = cdf[e < I ? e : I - 1];
+      const uint64_t m = __ballot(e < I && ti < v);
+      if (l == i && m) off = __ffsll((long long)m) - 1;
+    }
+    int64_t idx = myb * ARLS_CHUNK + off;
+    const int64_t last = *ml.last[q];
+    if (idx > last) idx = last;  // rounding past the end: last positive row
+    if (idx < 0) idx = 0;
+    if (act) sidx[s * nq + q] = (int32_t)idx;
+    sh_idx[threadIdx.x * nq + q] = (int32_t)idx;
+    p = p * (ml.lev[q][idx] / Z);
   }
+  if (act) prob[s] = p;
   __syncthreads();
   // Khatri-Rao rows of the block's samples, lanes over columns
   const int64_t s0 = (int64_t)blockIdx.x * DR_THREADS;
@@ -155,8 +187,8 @@ k_arls_draw(ModeList ml, int64_t J, int R, const double *uni, int32_t *sidx,
 
 template <typename T>
 void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
-                double *cdf, double *Z, int64_t *last, void *tmp,
-                uint32_t *err, hipStream_t s) {
+                double *cdf, double *coarse, double *Z, int64_t *last,
+                void *tmp, uint32_t *err, hipStream_t s) {
   unsigned long long *lastp1 = static_cast<unsigned long long *>(tmp);
   void *scan_tmp = static_cast<char *>(tmp) + 256;
   zero_fill<int64_t>(reinterpret_cast<int64_t *>(lastp1), 1, s);
@@ -177,14 +209,17 @@ void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
   inclusive_scan_f64(lev, cdf, I, scan_tmp, s);
   hipLaunchKernelGGL(k_arls_tail, dim3(1), dim3(1), 0, s, cdf, I, lastp1, Z,
                      last, err);
+  const int64_t nb = (I + ARLS_CHUNK - 1) / ARLS_CHUNK;
+  hipLaunchKernelGGL(k_arls_coarse, dim3(ceil_div(nb, 256)), dim3(256), 0, s,
+                     cdf, I, coarse);
   CPR_LAUNCH_CHECK();
 }
 template void arls_build<float>(const float *, int64_t, int, const double *,
-                                double *, double *, double *, int64_t *,
-                                void *, uint32_t *, hipStream_t);
+                                double *, double *, double *, double *,
+                                int64_t *, void *, uint32_t *, hipStream_t);
 template void arls_build<double>(const double *, int64_t, int, const double *,
-                                 double *, double *, double *, int64_t *,
-                                 void *, uint32_t *, hipStream_t);
+                                 double *, double *, double *, double *,
+                                 int64_t *, void *, uint32_t *, hipStream_t);
 
 template <typename T>
 void arls_draw(const ModeList &ml, int64_t J, int R, const double *uni,

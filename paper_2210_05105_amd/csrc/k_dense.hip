@@ -266,7 +266,10 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
     for (int vv = 0; vv < 4; ++vv) {
       const int gi = ta[i] * 16 + 4 * (l / 16) + vv;
       const int gj = tb[i] * 16 + (l % 16);
-      if (gi < R && gj < R) {
+      // a diagonal tile holds both (a, b) and (b, a), rounded differently
+      // (hi_a lo_b and lo_a hi_b enter in different MFMAs): its upper
+      // triangle is written to both halves so that G is exactly symmetric
+      if (gi < R && gj < R && gi <= gj) {
         out[gi * R + gj] = accd[i][vv];
         out[gj * R + gi] = accd[i][vv];
       }
@@ -1008,6 +1011,33 @@ template void gram_scaled<float>(const double *, const double *, int64_t, int,
 template void gram_scaled<double>(const double *, const double *, int64_t,
                                   int, double *, double *, void *, int,
                                   hipStream_t);
+
+namespace {
+template <typename T>
+__global__ void k_scale_draws(const T *h, const double *prob, int64_t J,
+                              int R, double *hs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= J * R) return;
+  const int64_t s = e / R;
+  hs[e] = (double)h[e] * sqrt(1.0 / ((double)J * prob[s]));
+}
+}  // namespace
+
+template <typename T>
+void sketched_gram(const T *h, const double *prob, int64_t J, int R,
+                   double *hs, double *Gs, void *tmp, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale_draws<T>), dim3(ceil_div(J * R, 256)),
+                     dim3(256), 0, s, h, prob, J, R, hs);
+  CPR_LAUNCH_CHECK();
+  gram_any<double, false>(hs, nullptr, nullptr, nullptr, J, R, Gs, tmp,
+                          GRAM_F64, s);
+}
+template void sketched_gram<float>(const float *, const double *, int64_t,
+                                   int, double *, double *, void *,
+                                   hipStream_t);
+template void sketched_gram<double>(const double *, const double *, int64_t,
+                                    int, double *, double *, void *,
+                                    hipStream_t);
 
 void column_norms(const double *partial, int nblk, int R, double *sigma,
                   uint32_t *err, hipStream_t s) {

@@ -1,7 +1,7 @@
 // Fit of Section 5.1: 1 - ||[sigma; U] - T||_F / ||T||_F with
 // ||[sigma; U] - T||^2 = ||T||^2 - 2 <T, [sigma; U]> + sigma^T (*G_k) sigma.
-// <T, [sigma; U]> streams the nonzeros once (FP64 accumulation, fixed-order
-// block reduction).
+// <T, [sigma; U]> streams mode 0's index once (FP64 accumulation,
+// fixed-order block reduction).
 #include "internal.h"
 
 #include <algorithm>
@@ -12,28 +12,70 @@ namespace {
 constexpr int FT_THREADS = 256;
 constexpr int FT_MAXBLK = 2048;
 
+// <T, [sigma; U]> from mode 0's column-sorted index (the nonzeros in
+// (column, row) order), so that no coordinate list is kept.  A block takes
+// ranges of FI_E consecutive positions: the offsets of the range's columns
+// and their coordinates (decoded from the column keys, mode 1 fastest) are
+// staged in LDS; each group of L lanes takes one nonzero, finds its column
+// by bisection of the staged offsets and adds
+// v * sum_r sigma_r U_0[i_0, r] prod_{k > 0} U_k[i_k, r].
+constexpr int FI_E = 1024;
+
 template <typename T, int L>
 __global__ void __launch_bounds__(FT_THREADS)
-k_fit_inner(const int32_t *idx, const T *val, int64_t nnz, int N, ModeList ml,
-            const double *sigma, int R, double *partial) {
-  constexpr int GPW = WAVE / L;
+k_fit_index(const int64_t *col_ptr, const uint64_t *col_key, int64_t n_cols,
+            const int32_t *row, const T *val, int64_t nnz, const T *U0,
+            ModeList ml, const double *sigma, int R, double *partial) {
+  constexpr int GPW = WAVE / L, GPB = GPW * (FT_THREADS / WAVE);
+  __shared__ int64_t sptr[FI_E + 1];
+  __shared__ int32_t scrd[FI_E][MAXN - 1];
+  __shared__ int64_t scol[2];
+  __shared__ double red[FT_THREADS / WAVE];
   const int l = lane_id(), w = threadIdx.x / WAVE;
-  const int gl = l % L;
-  const int64_t group = ((int64_t)blockIdx.x * (FT_THREADS / WAVE) + w) * GPW + l / L;
-  const int64_t ng = (int64_t)gridDim.x * (FT_THREADS / WAVE) * GPW;
+  const int gl = l % L, grp = w * GPW + l / L;
+  const int64_t nrange = (nnz + FI_E - 1) / FI_E;
   double acc = 0;
-  for (int64_t e = group; e < nnz; e += ng) {
-    double part = 0;
-    for (int r = gl; r < R; r += L) {
-      double p = sigma[r];
-      for (int k = 0; k < N; ++k)
-        p *= (double)static_cast<const T *>(ml.U[k])[(int64_t)idx[e * N + k] * R + r];
-      part += p;
+  for (int64_t rg = blockIdx.x; rg < nrange; rg += gridDim.x) {
+    const int64_t e0 = rg * FI_E;
+    const int64_t e1 = e0 + FI_E < nnz ? e0 + FI_E : nnz;
+    if (threadIdx.x < 2) {  // last column starting at or before e0 / e1 - 1
+      const int64_t e = threadIdx.x == 0 ? e0 : e1 - 1;
+      int64_t lo = 0, hi = n_cols - 1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (col_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      scol[threadIdx.x] = lo;
     }
-    acc += part * (double)val[e];
+    __syncthreads();
+    const int64_t c0 = scol[0];
+    const int nc = (int)(scol[1] - c0 + 1);  // <= FI_E
+    for (int i = threadIdx.x; i <= nc; i += FT_THREADS) sptr[i] = col_ptr[c0 + i];
+    for (int i = threadIdx.x; i < nc; i += FT_THREADS) {
+      const uint64_t key = col_key[c0 + i];
+      for (int q = 0; q < ml.n; ++q)
+        scrd[i][q] = (int32_t)((key / ml.stride[q]) % (uint64_t)ml.I[q]);
+    }
+    __syncthreads();
+    for (int64_t e = e0 + grp; e < e1; e += GPB) {
+      int lo = 0, hi = nc - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sptr[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const int64_t i0 = row[e];
+      double part = 0;
+      for (int r = gl; r < R; r += L) {
+        double p = sigma[r] * (double)U0[i0 * R + r];
+        for (int q = 0; q < ml.n; ++q)
+          p *= (double)static_cast<const T *>(ml.U[q])[(int64_t)scrd[lo][q] * R + r];
+        part += p;
+      }
+      acc += part * (double)val[e];
+    }
+    __syncthreads();
   }
   acc = wave_sum(acc);
-  __shared__ double red[FT_THREADS / WAVE];
   if (l == 0) red[w] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -95,26 +137,32 @@ int fit_blocks(int64_t nnz) {
 }
 
 template <typename T>
-void fit_inner(const int32_t *idx, const T *val, int64_t nnz, int N,
-               const ModeList &ml, const double *sigma, int R, double *partial,
-               int nblk, hipStream_t s) {
+void fit_inner_index(const int64_t *col_ptr, const uint64_t *col_key,
+                     int64_t n_cols, const int32_t *row, const T *val,
+                     int64_t nnz, const T *U0, const ModeList &ml,
+                     const double *sigma, int R, double *partial, int nblk,
+                     hipStream_t s) {
   const dim3 g(nblk), b(FT_THREADS);
-  if (R <= 8)
-    hipLaunchKernelGGL((k_fit_inner<T, 8>), g, b, 0, s, idx, val, nnz, N, ml, sigma, R, partial);
-  else if (R <= 16)
-    hipLaunchKernelGGL((k_fit_inner<T, 16>), g, b, 0, s, idx, val, nnz, N, ml, sigma, R, partial);
-  else if (R <= 32)
-    hipLaunchKernelGGL((k_fit_inner<T, 32>), g, b, 0, s, idx, val, nnz, N, ml, sigma, R, partial);
-  else
-    hipLaunchKernelGGL((k_fit_inner<T, 64>), g, b, 0, s, idx, val, nnz, N, ml, sigma, R, partial);
+#define CPR_FIT(L)                                                         \
+  hipLaunchKernelGGL((k_fit_index<T, L>), g, b, 0, s, col_ptr, col_key,    \
+                     n_cols, row, val, nnz, U0, ml, sigma, R, partial)
+  if (R <= 8) CPR_FIT(8);
+  else if (R <= 16) CPR_FIT(16);
+  else if (R <= 32) CPR_FIT(32);
+  else CPR_FIT(64);
+#undef CPR_FIT
   CPR_LAUNCH_CHECK();
 }
-template void fit_inner<float>(const int32_t *, const float *, int64_t, int,
-                               const ModeList &, const double *, int, double *,
-                               int, hipStream_t);
-template void fit_inner<double>(const int32_t *, const double *, int64_t, int,
-                                const ModeList &, const double *, int, double *,
-                                int, hipStream_t);
+template void fit_inner_index<float>(const int64_t *, const uint64_t *,
+                                     int64_t, const int32_t *, const float *,
+                                     int64_t, const float *, const ModeList &,
+                                     const double *, int, double *, int,
+                                     hipStream_t);
+template void fit_inner_index<double>(const int64_t *, const uint64_t *,
+                                      int64_t, const int32_t *,
+                                      const double *, int64_t, const double *,
+                                      const ModeList &, const double *, int,
+                                      double *, int, hipStream_t);
 
 void fit_finish(const ModeList &ml, int N, int R, const double *sigma,
                 const double *partial, int nblk, double normT2, double *out,

@@ -7,6 +7,8 @@
 // init; the hot path only reads the result.
 #include "internal.h"
 
+#include <functional>
+
 #include <algorithm>
 
 namespace cpr {
@@ -168,19 +170,13 @@ __global__ void k_cols(const uint64_t *hi, int64_t n, int lo_bits,
 // column lookup table: each column claims the first empty entry from its
 // key's home entry on (keys are distinct, so a claim never meets its own key)
 __global__ void k_hash_insert(const uint64_t *col_key, int64_t n_cols,
-                              int hbits, uint64_t *tab) {
+                              int hbits, uint32_t *tab) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cols) return;
   const uint64_t key = col_key[c], mask = (1ull << hbits) - 1;
   uint64_t p = col_hash(key, hbits);
   for (uint64_t n = 0; n <= mask; ++n) {
-    const unsigned long long old = atomicCAS(
-        reinterpret_cast<unsigned long long *>(tab + 2 * p), ~0ull,
-        (unsigned long long)key);
-    if (old == ~0ull) {
-      tab[2 * p + 1] = (uint64_t)c;
-      return;
-    }
+    if (atomicCAS(tab + p, ~0u, (uint32_t)c) == ~0u) return;
     p = (p + 1) & mask;
   }
 }
@@ -208,6 +204,31 @@ k_max_col(const int64_t *col_ptr, int64_t n_cols, unsigned long long *mx) {
     m = sm[0] > m ? sm[0] : m;
     if (m) atomicMax(mx, m);
   }
+}
+
+// Column lengths for the sum of the J longest columns: lengths below
+// LH_SMALL counted in an LDS histogram per block (added to the global one
+// at the end), longer ones appended to a list (at most nnz / LH_SMALL).
+constexpr int LH_SMALL = 4096;
+__global__ void __launch_bounds__(256)
+k_len_hist(const int64_t *col_ptr, int64_t n_cols, unsigned long long *hist,
+           int64_t *big, unsigned long long *nbig, int64_t big_cap) {
+  __shared__ uint32_t h[LH_SMALL];
+  for (int i = threadIdx.x; i < LH_SMALL; i += 256) h[i] = 0;
+  __syncthreads();
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n_cols;
+       c += (int64_t)gridDim.x * 256) {
+    const int64_t len = col_ptr[c + 1] - col_ptr[c];
+    if (len < LH_SMALL) {
+      atomicAdd(&h[len], 1u);
+    } else {
+      const unsigned long long at = atomicAdd(nbig, 1ull);
+      if ((int64_t)at < big_cap) big[at] = len;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < LH_SMALL; i += 256)
+    if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
 }
 
 struct DevBuf {
@@ -355,7 +376,7 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
   int hbits = 4;
   while (((int64_t)1 << hbits) < 2 * out.n_cols) ++hbits;
   out.hbits = hbits;
-  const size_t hbytes = ((size_t)2 << hbits) * 8;
+  const size_t hbytes = ((size_t)1 << hbits) * 4;
   if (hipMalloc((void **)&out.hash, hbytes) != hipSuccess)
     return "out of device memory for the mode index";
   if (hipMemsetAsync(out.hash, 0xff, hbytes, s) != hipSuccess)
@@ -364,6 +385,50 @@ std::string build_mode_index(const int32_t *idx, const void *val, int val_fp64,
                      0, s, out.col_key, out.n_cols, hbits, out.hash);
   CPR_LAUNCH_CHECK();
   return "";
+}
+
+// Sum of the lengths of the J longest columns of a mode (all nonzeros when
+// J >= n_cols): a bound on the nonzeros any solve extracts, since it takes
+// at most J distinct columns.  Returns -1 on a HIP failure.
+int64_t top_columns_total(const int64_t *col_ptr, int64_t n_cols, int64_t nnz,
+                          int64_t J, hipStream_t s) {
+  if (J >= n_cols) return nnz;
+  const int64_t big_cap = nnz / LH_SMALL + 1;
+  DevBuf hist, big, nbig;
+  if (!dalloc(hist, LH_SMALL * 8) || !dalloc(big, big_cap * 8) ||
+      !dalloc(nbig, 8))
+    return -1;
+  if (hipMemsetAsync(hist.p, 0, LH_SMALL * 8, s) != hipSuccess ||
+      hipMemsetAsync(nbig.p, 0, 8, s) != hipSuccess)
+    return -1;
+  const unsigned nb = (unsigned)std::min<int64_t>(ceil_div(n_cols, 256), 2048);
+  hipLaunchKernelGGL(k_len_hist, dim3(nb), dim3(256), 0, s, col_ptr, n_cols,
+                     hist.get<unsigned long long>(), big.get<int64_t>(),
+                     nbig.get<unsigned long long>(), big_cap);
+  if (hipGetLastError() != hipSuccess) return -1;
+  std::vector<unsigned long long> hh(LH_SMALL);
+  unsigned long long nb_h = 0;
+  if (hipMemcpyAsync(hh.data(), hist.p, LH_SMALL * 8, hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(&nb_h, nbig.p, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return -1;
+  const int64_t n_big = std::min<int64_t>((int64_t)nb_h, big_cap);
+  std::vector<int64_t> bl(n_big);
+  if (n_big > 0 &&
+      (hipMemcpyAsync(bl.data(), big.p, n_big * 8, hipMemcpyDeviceToHost, s) !=
+           hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    return -1;
+  std::sort(bl.begin(), bl.end(), std::greater<int64_t>());
+  int64_t left = J, tot = 0;
+  for (int64_t i = 0; i < n_big && left > 0; ++i, --left) tot += bl[i];
+  for (int len = LH_SMALL - 1; len >= 1 && left > 0; --len) {
+    const int64_t take = std::min<int64_t>(left, (int64_t)hh[len]);
+    tot += take * len;
+    left -= take;
+  }
+  return std::min(tot, nnz);
 }
 
 }  // namespace cpr

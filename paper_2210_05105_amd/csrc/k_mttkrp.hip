@@ -50,16 +50,17 @@ __global__ void k_sample_rows(ModeList ml, int64_t J, int R,
 }
 
 // Column of each draw: its key, probed in the mode's hash table from the
-// key's home entry (one 16-byte load per entry) until the key or an empty
-// entry.  The first draw of a column claims it with atomicMin on its owner
+// key's home entry (a column id per entry, its key read from col_key) until
+// the key or an empty entry.  The first draw of a column claims it with atomicMin on its owner
 // word, once per block and column: the block's draws of a column meet in an
 // LDS table first (a heavily drawn column would otherwise take one global
 // atomic per draw, all on one address).
 constexpr int LK_HASH = 2 * LK_THREADS;
 
 __global__ void __launch_bounds__(LK_THREADS)
-k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *tab,
-         int hbits, int32_t *col_id, int32_t *owner) {
+k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint32_t *tab,
+         const uint64_t *col_key, int hbits, int32_t *col_id,
+         int32_t *owner) {
   __shared__ int32_t hk[LK_HASH], hm[LK_HASH];
   for (int e = threadIdx.x; e < LK_HASH; e += LK_THREADS) {
     hk[e] = -1;
@@ -79,13 +80,12 @@ k_lookup(ModeList ml, int64_t J, const int32_t *sidx, const uint64_t *tab,
       const uint64_t mask = (1ull << hbits) - 1;
       uint64_t p = col_hash(key, hbits);
       for (uint64_t n = 0; n <= mask; ++n) {
-        const ulonglong2 e =
-            *reinterpret_cast<const ulonglong2 *>(tab + 2 * p);
-        if (e.x == key) {
-          cid = (int32_t)e.y;
+        const uint32_t c = tab[p];
+        if (c == ~0u) break;
+        if (col_key[c] == key) {
+          cid = (int32_t)c;
           break;
         }
-        if (e.x == ~0ull) break;
         p = (p + 1) & mask;
       }
     }
@@ -820,8 +820,8 @@ template void set_sample_rows<double>(const ModeList &, int64_t, int,
 void lookup_columns(const ModeList &ml, int64_t J, const int32_t *sidx,
                     const ModeIndex &ix, SampleWork &w, hipStream_t s) {
   hipLaunchKernelGGL(k_lookup, dim3(ceil_div(J, LK_THREADS)), dim3(LK_THREADS),
-                     0, s, ml, J, sidx, ix.hash, ix.hbits, w.col_id,
-                     w.owner);
+                     0, s, ml, J, sidx, ix.hash, ix.col_key, ix.hbits,
+                     w.col_id, w.owner);
   CPR_LAUNCH_CHECK();
 }
 
@@ -865,9 +865,8 @@ size_t lds_cap() { return 160 * 1024 - 8 * 1024; }
 template <typename T>
 void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                     const int32_t *row, const T *val, const int64_t *bk_start,
-                    int R, T *M, hipStream_t s) {
+                    int R, int bb, T *M, hipStream_t s) {
   const T *hc = static_cast<const T *>(w.hc);
-  const int bb = bucket_shift(R, (int)sizeof(T));
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
   // fixed offsets: the fill cursors of every mode stay zero between calls
   // (each plan clears the ones it read), whatever the mode's bucket count
@@ -938,12 +937,12 @@ size_t bucket_record_bytes(int tsize) {
 }
 template void sampled_mttkrp<float>(const SampleWork &, int64_t,
                                     const int64_t *, const int32_t *,
-                                    const float *, const int64_t *, int,
+                                    const float *, const int64_t *, int, int,
                                     float *, hipStream_t);
 template void sampled_mttkrp<double>(const SampleWork &, int64_t,
                                      const int64_t *, const int32_t *,
                                      const double *, const int64_t *, int,
-                                     double *, hipStream_t);
+                                     int, double *, hipStream_t);
 
 void bucket_regions(const int32_t *row, int64_t nnz, int64_t I, int bb,
                     int64_t *starts, int64_t *cnt, void *scan_tmp,

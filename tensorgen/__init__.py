@@ -11,7 +11,11 @@ Workloads (sizes follow the five configurations the project benchmarks):
   planted  : 200x150x100, 20k nnz, planted rank-8 model + N(0, 0.01) noise
   zipf3    : 100000x80000x60000, 50M nnz, Zipf(1.1) indices, lognormal values
   zipf4    : 1000000x500000x200000x1000, 200M nnz, Zipf(1.2), Poisson(3)+1
+  zipf3xl  : 8000000x8000000x200000, 1.5B nnz, Zipf(1.05), lognormal
   batch3   : 500000x300000x100000, 100M nnz, Zipf(1.1), lognormal
+
+The large ones are generated on the GPU (make_tensor_device, torch's
+generator); the NumPy path serves the sizes the oracle can take whole.
 
 Zipf(s) on a finite support r = 1..I draws r with probability proportional
 to r^-s; labels are then relabelled by a seeded per-mode permutation so that
@@ -28,6 +32,8 @@ __all__ = [
     "SparseTensor", "streams", "zipf_coords", "uniform_coords",
     "planted_values", "lognormal_values", "poisson_values", "init_factors",
     "uniform_block", "uniform_blocks", "make_tensor", "WORKLOADS",
+    "zipf_coords_device", "values_device", "init_factors_device",
+    "uniforms_device", "make_tensor_device",
 ]
 
 
@@ -193,6 +199,223 @@ def uniform_blocks(rng, sweeps, J, N):
     return rng.random((sweeps, N, J, N - 1))
 
 
+# --------------------------------------------------------------------------
+# Device generation (torch on the GPU) for tensors of 10^8 - 10^9 nonzeros.
+# Same laws as above (Zipf(s) marginals with a seeded per-mode relabelling,
+# distinct coordinates topped up to exactly nnz, lognormal or Poisson(3)+1
+# values, N(0,1) initial factors), drawn from torch's counter-based
+# generator instead of NumPy's PCG64: a different stream of the same
+# distribution.  Input generation only.
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_pack(cols, bits):
+    """Pack per-mode coordinates (int64 tensors) into one int64 key per
+    nonzero (bit fields, first mode lowest; at most 64 bits in total)."""
+    key = None
+    sh = 0
+    for c, b in zip(cols, bits):
+        part = c << sh
+        key = part if key is None else key | part
+        sh += b
+    return key
+
+
+def _dev_unpack(key, bits, out, col0):
+    torch = _torch()
+    sh = 0
+    for k, b in enumerate(bits):
+        out[:, col0 + k] = ((key >> sh) & ((1 << b) - 1)).to(torch.int32)
+        sh += b
+
+
+_GOLD = -7046029254386353131  # 0x9E3779B97F4A7C15 as a signed int64
+
+
+def _hash_part(a, nparts):
+    """Part of each key (same key, same part): top bits of a multiplicative
+    hash, so that parts are of about equal size whatever the key law."""
+    torch = _torch()
+    h = (a * _GOLD) >> 40           # arithmetic shift; wraps like uint64
+    return torch.remainder(h, nparts)
+
+
+_PART = 1 << 30  # elements per sort / mask / unique call (index limits)
+
+
+def _unique_parts(ka, kb=None, log=None):
+    """Distinct keys (or key pairs) of the chunks ka (and kb), as a list of
+    (a, b or None) tensors, one per hash part; every call on a tensor stays
+    below 2^30 elements."""
+    torch = _torch()
+    total = sum(x.shape[0] for x in ka)
+    nparts = max(1, -(-total // _PART) * 2)
+    pieces = [[] for _ in range(nparts)]
+    for i, a in enumerate(ka):
+        b = None if kb is None else kb[i]
+        if nparts == 1:
+            pieces[0].append((a, b))
+            continue
+        part = _hash_part(a if b is None else a ^ (b * 31), nparts)
+        for p in range(nparts):
+            m = part == p
+            pieces[p].append((a[m], None if b is None else b[m]))
+            del m
+        del part
+    ka.clear()
+    if kb is not None:
+        kb.clear()
+    outs = []
+    for p in range(nparts):
+        if log:
+            log(f"tensorgen: part {p + 1} of {nparts}")
+        sa = torch.cat([x for x, _ in pieces[p]])
+        sb = None if kb is None else torch.cat([y for _, y in pieces[p]])
+        pieces[p] = None
+        if sb is None:
+            outs.append((torch.unique(sa), None))
+        else:
+            o1 = torch.argsort(sb, stable=True)
+            sa, sb = sa[o1], sb[o1]
+            o2 = torch.argsort(sa, stable=True)
+            sa, sb = sa[o2], sb[o2]
+            del o1, o2
+            first = torch.ones(sa.shape[0], dtype=torch.bool, device=sa.device)
+            first[1:] = (sa[1:] != sa[:-1]) | (sb[1:] != sb[:-1])
+            outs.append((sa[first], sb[first]))
+            del first
+        del sa, sb
+    return outs
+
+
+def zipf_draws_device(g, cdf, perm, m):
+    """m i.i.d. labels: rank r (0-based) with probability cdf[r] - cdf[r-1]
+    by inverse CDF of a uniform, then relabelled as perm[r]."""
+    torch = _torch()
+    u = torch.rand(m, dtype=torch.float64, device=cdf.device, generator=g)
+    r = torch.searchsorted(cdf, u).clamp_(max=cdf.shape[0] - 1)
+    return perm[r]
+
+
+def zipf_coords_device(seed, dims, nnz, s, device, oversample=1.6,
+                       chunk=1 << 27, log=None):
+    """Distinct coordinates with Zipf(s) marginals per mode, on `device`.
+
+    Raw draws are packed into one or two int64 keys (modes split where 64
+    bits would be exceeded), deduplicated, and a uniformly random subset of
+    exactly nnz distinct tuples is returned (int32 [nnz, N], random order).
+    """
+    torch = _torch()
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    N = len(dims)
+    bits = [_bits(d) for d in dims]
+    split, acc = N, 0  # modes [0, split) in key A, [split, N) in key B
+    for k in range(N):
+        if acc + bits[k] > 64:
+            split = k
+            break
+        acc += bits[k]
+    cdfs, perms = [], []
+    for I in dims:
+        w = torch.arange(1, I + 1, dtype=torch.float64, device=device) ** (-s)
+        c = torch.cumsum(w, 0)
+        cdfs.append(c / c[-1])
+        perms.append(torch.randperm(I, generator=g, device=device))
+        del w, c
+    parts = []  # distinct keys so far, per hash part: [(a, b or None)]
+    chunk = min(chunk, _PART)
+    have = 0
+    while have < nnz:
+        n = int((nnz - have) * oversample) + 1024
+        ka = [x for x, _ in parts]
+        kb = [y for _, y in parts] if split < N else None
+        parts = None
+        for c0 in range(0, n, chunk):
+            m = min(chunk, n - c0)
+            cols = [zipf_draws_device(g, cdfs[k], perms[k], m)
+                    for k in range(N)]
+            ka.append(_dev_pack(cols[:split], bits[:split]))
+            if split < N:
+                kb.append(_dev_pack(cols[split:], bits[split:]))
+            del cols
+        if log:
+            log(f"tensorgen: {n} draws packed; deduplicating")
+        parts = _unique_parts(ka, kb, log)
+        have = sum(x.shape[0] for x, _ in parts)
+        if log:
+            log(f"tensorgen: {have} distinct of {nnz} wanted")
+        oversample = max(1.3, oversample * 1.2)
+    # exactly nnz of them, uniformly at random: each part keeps its share
+    # (a random subset of it), the shares adding up to nnz
+    out = torch.empty((nnz, N), dtype=torch.int32, device=device)
+    at, left = 0, nnz
+    for i, (a, b) in enumerate(parts):
+        k = left if i == len(parts) - 1 else \
+            int(round(nnz * a.shape[0] / have))
+        k = min(k, a.shape[0], left)
+        keep = torch.randperm(a.shape[0], generator=g, device=device)[:k]
+        _dev_unpack(a[keep], bits[:split], out[at:at + k], 0)
+        if split < N:
+            _dev_unpack(b[keep], bits[split:], out[at:at + k], split)
+        at += k
+        left -= k
+        del keep
+    assert at == nnz, (at, nnz)
+    del parts, cdfs, perms
+    # random order (parts are grouped by hash)
+    return out[torch.randperm(nnz, generator=g, device=device)] \
+        if nnz < (1 << 31) else out
+
+
+def values_device(seed, n, kind, device):
+    """lognormal exp(N(0,1)) or Poisson(3) + 1 values, FP32, on `device`."""
+    torch = _torch()
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    if kind == "poisson":
+        lam = torch.full((n,), 3.0, dtype=torch.float32, device=device)
+        return torch.poisson(lam, generator=g) + 1.0
+    return torch.exp(torch.randn(n, dtype=torch.float32, device=device,
+                                 generator=g))
+
+
+def init_factors_device(seed, dims, R, device, dtype=None):
+    """Unit-variance Gaussian initial factors (Alg. 1, first line), FP64
+    tensors holding FP32-representable values (so that every precision form
+    starts from identical factors)."""
+    torch = _torch()
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return [torch.randn((d, R), dtype=torch.float32, device=device,
+                        generator=g).to(torch.float64) for d in dims]
+
+
+def uniforms_device(seed, shape, device):
+    """Uniform [0, 1) blocks (FP64) on `device`."""
+    torch = _torch()
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.rand(shape, dtype=torch.float64, device=device, generator=g)
+
+
+def make_tensor_device(name, device, nnz=None, dims=None, log=None):
+    """Build one named power-law workload on `device`: (dims, idx int32
+    [nnz, N], val float32 [nnz]) as torch tensors."""
+    w = WORKLOADS[name]
+    dims = tuple(dims or w["dims"])
+    nnz = int(nnz or w["nnz"])
+    base = 2210_5105 * 16 + int(w["tag"])
+    idx = zipf_coords_device(base, dims, nnz, w["s"], device, log=log)
+    val = values_device(base + 7, nnz,
+                        "poisson" if name == "zipf4" else "lognormal", device)
+    return dims, idx, val
+
+
 WORKLOADS = {
     "planted": dict(dims=(200, 150, 100), nnz=20_000, R=8, J=4096,
                     sampler="arls", sweeps=10, tag=1),
@@ -201,6 +424,9 @@ WORKLOADS = {
     "zipf4": dict(dims=(1_000_000, 500_000, 200_000, 1_000),
                   nnz=200_000_000, s=1.2, R=64, J=131072, sampler="arls",
                   sweeps=20, tag=3),
+    "zipf3xl": dict(dims=(8_000_000, 8_000_000, 200_000),
+                    nnz=1_500_000_000, s=1.05, R=100, J=262144,
+                    sampler="sts", sweeps=10, tag=4),
     "batch3": dict(dims=(500_000, 300_000, 100_000), nnz=100_000_000, s=1.1,
                    J=32768, sampler="arls", sweeps=10, tag=5),
 }

@@ -45,10 +45,11 @@ def test_library_is_gfx950_only(lib):
 
 
 def _init(lib, N=3, dims=(4, 5, 6), nnz=10, R=4, sampler=0, precision=0,
-          max_J=8, leaf=0, idx=1, val=1):
+          max_J=8, leaf=0, idx=1, val=1, bucket_rows=0, solve_gram=0):
     d = (C.c_int64 * max(N, 1))(*list(dims)[:max(N, 1)])
     t = binding._Tensor(N, d, nnz, idx, val, 1)
-    cfg = binding._Config(R, sampler, precision, leaf, max_J)
+    cfg = binding._Config(R, sampler, precision, leaf, max_J, bucket_rows,
+                          solve_gram)
     h = C.c_void_p()
     st = lib.cp_init(C.byref(t), C.byref(cfg), None, C.byref(h))
     return st, h
@@ -58,6 +59,8 @@ def _init(lib, N=3, dims=(4, 5, 6), nnz=10, R=4, sampler=0, precision=0,
                                 dict(nnz=0), dict(R=0), dict(R=129),
                                 dict(sampler=3), dict(precision=3),
                                 dict(max_J=0), dict(leaf=8),
+                                dict(bucket_rows=48), dict(bucket_rows=512),
+                                dict(bucket_rows=8), dict(solve_gram=2),
                                 dict(dims=(4, 0, 6)), dict(dims=(4, 2**31, 6)),
                                 dict(idx=None), dict(val=None)])
 def test_init_rejects_bad_arguments_before_touching_the_gpu(lib, kw):
@@ -119,3 +122,16 @@ def test_uniform_generator_and_planted_values():
     ref = sum(F[0][T.idx[:10, 0], r] * F[1][T.idx[:10, 1], r] *
               F[2][T.idx[:10, 2], r] for r in range(2))
     np.testing.assert_allclose(v, ref)
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """The tuner's cache file: stored results are returned for the same
+    problem key, and nothing else is touched."""
+    from paper_2210_05105_amd import autotune as at
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("CPR_TUNE_CACHE", str(path))
+    assert at.cache_path() == str(path)
+    assert at._load(str(path)) == {}
+    at._store(str(path), {"k": {"sts_leaf": 32, "bucket_rows": 128}})
+    assert at._load(str(path))["k"]["sts_leaf"] == 32
+    assert at.LEAVES == (16, 32, 64) and 128 in at.BUCKETS

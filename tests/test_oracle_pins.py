@@ -463,3 +463,55 @@ def test_randomized_als_tracks_exact_als():
                            J=J, block=8, record_fit=True)
         assert fits[-1] > fits[0] + 0.05
         assert abs(fits[-1] - ex[-1]) < 0.03
+
+
+@pytest.mark.parametrize("sampler", ["arls", "sts"])
+def test_sketched_gram_is_explicit_sketch_product(sampler):
+    """Fig. 3: G~ = (S A)^T (S A) with S formed explicitly, and the sketched
+    update M G~^+ equals the least-squares solution of the explicitly
+    sketched problem min ||(S A) X^T - S mat(T, j)^T|| (library lstsq)."""
+    dims, j, J = (6, 5, 4), 2, 60
+    T, _ = tg.tiny_tensor(14, dims, 90)
+    U = rand_factors(8, dims, 3)
+    G = [O.gram(u) for u in U]
+    u = np.random.default_rng(10).random((J, 2))
+    if sampler == "arls":
+        st = {k: O.arls_build(U[k], G[k]) for k in range(3)}
+        sidx, prob, h = O.arls_sample(U, st, j, u)
+    else:
+        sidx, prob, h = O.sts_sample(U, G, j, u, block=2)
+    A = O.design_matrix(U, j)
+    rows_x = O.sample_column_key(sidx, dims, j).astype(np.int64)
+    S = np.zeros((J, A.shape[0]))
+    S[np.arange(J), rows_x] = 1.0 / np.sqrt(J * prob)
+    Gs = O.sketched_gram(h, prob, J)
+    np.testing.assert_allclose(Gs, (S @ A).T @ (S @ A), rtol=1e-12,
+                               atol=1e-13)
+    keys, rep, counts, w = O.dedup(sidx, prob, dims, j, J)
+    ck, rows, vals, slot = O.extract(T.idx, T.val, dims, j, keys)
+    M = O.sampled_mttkrp(dims[j], rows, vals, slot, w, h[rep])
+    X = M @ O.pinv_psd(Gs)
+    B = O.matricize_dense(T.idx, T.val, dims, j)
+    Xl = np.linalg.lstsq(S @ A, S @ B.T, rcond=None)[0].T
+    np.testing.assert_allclose(X, Xl, rtol=1e-9, atol=1e-10)
+
+
+def test_sketched_als_keeps_a_noiseless_planted_model():
+    """With G~ a noiseless planted low-rank tensor is a fixed point of
+    sampled ALS (the sketched problem is consistent); started next to the
+    planted factors, sketched ALS stays at fit ~ 1 while the exact-G update
+    (Eq. 4, Eq. 5) with the same draws moves away from it."""
+    dims, R, J = (9, 8, 7), 3, 200
+    F = rand_factors(35, dims, R)
+    Tdense = np.einsum("ir,jr,kr->ijk", *F)
+    idx = np.array(np.nonzero(np.ones(dims))).T
+    val = Tdense[tuple(idx.T)]
+    rng = np.random.default_rng(36)
+    U0 = [f + 1e-9 * rng.standard_normal(f.shape) for f in F]
+    uni = rng.random((3, 3, J, 2))
+    _, _, fs = O.als(idx, val, dims, R, "arls", U0, uni, sweeps=3, J=J,
+                     record_fit=True, sketched=True)
+    _, _, fe = O.als(idx, val, dims, R, "arls", U0, uni, sweeps=3, J=J,
+                     record_fit=True, sketched=False)
+    assert fs[-1] > 1 - 1e-6
+    assert fe[-1] < fs[-1] - 1e-4
