@@ -471,11 +471,16 @@ def main():
                              dims, R, sampler, precision, J, log=log)
         leaf = tuned["sts_leaf"] or leaf
         log(f"autotune: {tuned}")
-    # a uniform sample of the nonzeros (the COO is in random order) for the
-    # oracle's bounded extraction, kept on the host
+    # a uniform sample of the nonzeros for the oracle's bounded extraction,
+    # kept on the host
     S = min(nnz, 8_000_000)
-    idx_s = idx_d[:S].cpu().numpy()
-    val_s = val_d[:S].double().cpu().numpy()
+    gs = torch.Generator(device=dev)
+    gs.manual_seed(17)
+    pick = torch.randint(nnz, (S,), device=dev, generator=gs) \
+        if S < nnz else torch.arange(nnz, device=dev)
+    idx_s = idx_d[pick].cpu().numpy()
+    val_s = val_d[pick].double().cpu().numpy()
+    del pick
     # after the timed sweeps, a short pass with events on every phase gives
     # the breakdown (events cost the stream a few microseconds each, so the
     # timed sweeps record them only around the two phases the line reports)

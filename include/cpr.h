@@ -91,6 +91,8 @@ typedef struct {
                            of two in [16, 256]                             */
   int32_t solve_gram;   /* cp_solve_gram: the R x R matrix G of the update
                            U_j = M G^+                                     */
+  int32_t solve_refine; /* cp_solve_refine: one step of iterative
+                           refinement on the row solve X = M G^+          */
 } cp_config;
 
 typedef enum {
@@ -100,6 +102,17 @@ typedef enum {
                            draw s adds h_s h_s^T / (J p_s); the draws still
                            follow the exact leverage laws                   */
 } cp_solve_gram;
+
+typedef enum {
+  CP_REFINE_AUTO = 0,  /* on for CP_FP64, off for CP_FP32 / CP_MIXED       */
+  CP_REFINE_ON = 1,    /* X = M G^+ + (M - (M G^+) G) G^+, all FP64: removes
+                          the solve's own rounding (three R x R products
+                          per row instead of one)                          */
+  CP_REFINE_OFF = 2    /* X = M G^+ in FP64.  With FP32 factors M carries
+                          the FP32 MTTKRP's rounding, which the condition
+                          of G amplifies far above the FP64 rounding the
+                          refinement removes                               */
+} cp_solve_refine;
 
 /*
  * cp_init - build the per-mode column-sorted indices and allocate all state.

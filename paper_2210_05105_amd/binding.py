@@ -37,11 +37,16 @@ class _Tensor(C.Structure):
                 ("val_is_fp64", C.c_int32)]
 
 
+def _refine_code(refine):
+    """cp_solve_refine: None -> automatic (by precision), True / False."""
+    return 0 if refine is None else (1 if refine else 2)
+
+
 class _Config(C.Structure):
     _fields_ = [("R", C.c_int32), ("sampler", C.c_int32),
                 ("precision", C.c_int32), ("sts_leaf", C.c_int32),
                 ("max_J", C.c_int64), ("bucket_rows", C.c_int32),
-                ("solve_gram", C.c_int32)]
+                ("solve_gram", C.c_int32), ("solve_refine", C.c_int32)]
 
 
 _lib = None
@@ -164,7 +169,7 @@ class Context:
 
     def __init__(self, idx, val, dims, R, sampler="arls", precision="fp64",
                  max_J=1, sts_leaf=0, stream=None, bucket_rows=0,
-                 sketched=False):
+                 sketched=False, refine=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -185,7 +190,7 @@ class Context:
                     val.data_ptr(), int(val.dtype == torch.float64))
         cfg = _Config(self.R, SAMPLERS[sampler], PRECISIONS[precision],
                       int(sts_leaf), int(max_J), int(bucket_rows),
-                      int(bool(sketched)))
+                      int(bool(sketched)), _refine_code(refine))
         h = C.c_void_p()
         st = lib.cp_init(C.byref(t), C.byref(cfg),
                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -347,7 +352,7 @@ class Batch:
 
     def __init__(self, idx, val, dims, ranks, sampler="arls",
                  precision="fp64", J=1, sts_leaf=0, nstreams=0, stream=None,
-                 bucket_rows=0):
+                 bucket_rows=0, refine=None):
         import torch
         self._torch = torch
         lib = load_library()
@@ -366,7 +371,8 @@ class Batch:
         t = _Tensor(self.N, d, int(val.shape[0]), idx.data_ptr(),
                     val.data_ptr(), int(val.dtype == torch.float64))
         cfg = _Config(0, SAMPLERS[sampler], PRECISIONS[precision],
-                      int(sts_leaf), self.J, int(bucket_rows), 0)
+                      int(sts_leaf), self.J, int(bucket_rows), 0,
+                      _refine_code(refine))
         rk = (C.c_int32 * self.B)(*self.ranks)
         h = C.c_void_p()
         st = lib.cp_batch_init(C.byref(t), self.B, rk, C.byref(cfg),

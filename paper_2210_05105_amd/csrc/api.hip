@@ -60,6 +60,7 @@ struct cp_ctx {
   int bb_fixed = -1;         // bucket shift set by the caller (-1: by rank)
   int bb = 7;                // bucket shift of this context's rank
   bool sketched = false;     // solve with the sketched Gram of the draws
+  bool refine = true;        // one refinement step on the row solve
   double *hs = nullptr;      // J x R: draws scaled by 1 / sqrt(J p)
   double *Gs = nullptr;      // R x R: their Gram
   // bucket shift of the sampled MTTKRP for rank r
@@ -370,7 +371,7 @@ void do_solve(cp_ctx *c, int mode) {
     }
     const int nblk = solve_blocks(I);
     solve_rows<T>(static_cast<const T *>(c->M), I, c->R, Gf, Gp, c->X,
-                  c->partial, nblk, c->w.stats + 3, c->s);
+                  c->partial, nblk, c->w.stats + 3, c->refine, c->s);
     column_norms(c->partial, nblk, c->R, c->sigma, c->d_err, c->s);
   }
   // the pass that stages the new factor for its Gram (or for its tree's
@@ -431,6 +432,8 @@ void set_config(cp_ctx *c, int N, const int64_t *dims, const cp_config *cfg) {
   c->max_J = cfg->max_J;
   c->sketched = cfg->solve_gram == CP_GRAM_SKETCHED &&
                 cfg->sampler != CP_SAMPLER_EXACT;
+  c->refine = cfg->solve_refine == CP_REFINE_ON ||
+              (cfg->solve_refine == CP_REFINE_AUTO && c->f64);
   c->bb_fixed = -1;
   for (int b = 4; b <= 8; ++b)
     if (cfg->bucket_rows == (1 << b)) c->bb_fixed = b;
@@ -599,13 +602,7 @@ void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
   if (c->sampler != CP_SAMPLER_EXACT) {
     // records sit in each bucket's fixed region: nnz of them at most
     dalloc(c, &c->w.rec, (size_t)c->nnz * bucket_record_bytes((int)ts));
-    for (int r = 1; r <= Rws; ++r)
-      ensure_bucket_regions(own, c->bshift(r), c->w.bk,
-                            c->w.scan_tmp);
   }
-  // bucket fill cursors start at zero; the accumulation plan clears them
-  // again after every sampled MTTKRP
-  zero_fill<int64_t>(c->w.bk, (size_t)5 * (nbk + 1), c->s);
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);
   size_t blk = 0;  // largest B x R block of a split bucket
@@ -663,10 +660,16 @@ void borrow_workspace(cp_ctx *c, const cp_ctx *ws) {
   c->Gs = ws->Gs;
 }
 
-// The bucket regions matching this context's rank.
-void select_bucket_regions(cp_ctx *c, const cp_ctx *own) {
+// The bucket regions matching this context's rank (built in `own`, the
+// index holder, on first use of a bucket size; the workspace's bucket
+// array serves as their scratch and is then cleared: the fill cursors start
+// at zero, and the accumulation plan clears them after every sampled MTTKRP).
+void select_bucket_regions(cp_ctx *c, cp_ctx *own) {
   const int bb = c->bshift(c->R);
   c->bb = bb;
+  if (c->sampler != CP_SAMPLER_EXACT)
+    ensure_bucket_regions(own, bb, c->w.bk, c->w.scan_tmp);
+  zero_fill<int64_t>(c->w.bk, (size_t)5 * (c->w.bk_max + 1), c->s);
   for (int k = 0; k < c->N; ++k) c->ix[k].bk_start = own->bk_start_bb[bb][k];
 }
 
@@ -804,6 +807,7 @@ cp_status cp_init(const cp_tensor *t, const cp_config *cfg, void *stream,
     return CP_EINVAL;
   if (!valid_bucket_rows(cfg->bucket_rows)) return CP_EINVAL;
   if (cfg->solve_gram < 0 || cfg->solve_gram > 1) return CP_EINVAL;
+  if (cfg->solve_refine < 0 || cfg->solve_refine > 2) return CP_EINVAL;
   cp_ctx *c = new (std::nothrow) cp_ctx;
   if (!c) return CP_ENOMEM;
   c->s = static_cast<hipStream_t>(stream);
@@ -1265,6 +1269,7 @@ cp_status cp_batch_init(const cp_tensor *t, int32_t B, const int32_t *ranks,
     return CP_EINVAL;
   if (!valid_bucket_rows(cfg->bucket_rows)) return CP_EINVAL;
   if (cfg->solve_gram < 0 || cfg->solve_gram > 1) return CP_EINVAL;
+  if (cfg->solve_refine < 0 || cfg->solve_refine > 2) return CP_EINVAL;
   cp_batch *bt = new (std::nothrow) cp_batch;
   if (!bt) return CP_ENOMEM;
   *out = bt;

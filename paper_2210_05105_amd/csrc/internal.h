@@ -124,12 +124,12 @@ void column_norms(const double *partial, int nblk, int R, double *sigma,
 void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
                    double *ggt_out, double *trace_out, double *scratch,
                    uint32_t *err, hipStream_t s);
-// X = M G^+ with one refinement step (FP64), written as double; per-block
-// column sums of squares into partial (nblk x R).
+// X = M G^+ (FP64), with one refinement step when `refine`, written as
+// double; per-block column sums of squares into partial (nblk x R).
 template <typename T>
 void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
                 const double *Gp, double *X, double *partial, int nblk,
-                int64_t *rows_out, hipStream_t s);
+                int64_t *rows_out, bool refine, hipStream_t s);
 int solve_blocks(int64_t I);
 // sigma from partial sums; U = X / sigma (zero columns stay zero).
 template <typename T>
@@ -281,6 +281,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// A lane id the compiler cannot see through: index arithmetic derived from
+// it stays inside the loop that uses it instead of being hoisted out as
+// loop-invariant registers (one per fragment).
+__device__ __forceinline__ int opaque_lane() {
+  int z;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+  return lane_id() + z;
+}
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

@@ -121,15 +121,16 @@ k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
 }
 
 // ---------------------------------------------------------------------------
-// Gram U^T U in reduced precision (FP32 factors).  The staged rows are FP32
-// in LDS; output tiles accumulate on FP32 MFMA in FP32, flushed into FP64
-// registers after every staged chunk (at most GL_ROWS rows of FP32
-// accumulation per flush), then per-block partials reduced in FP64 in a
-// fixed order as for the FP64 Gram.
-//   GRAM_F32:    v_mfma_f32_16x16x4f32 on the FP32 values.
-//   GRAM_BF16X3: each value split u = hi + lo into two BF16 numbers
-//                (round to nearest even); u_a u_b is taken as
-//                hi_a hi_b + hi_a lo_b + lo_a hi_b on
+// Gram U^T U in reduced precision (FP32 factors).  Blocks of 8 waves stage
+// GL_RC-row chunks of U (read linearly, coalesced) in LDS; output tiles
+// accumulate on FP32 MFMA in FP32, flushed into FP64 registers after every
+// chunk (GL_RC rows of FP32 accumulation per flush), then per-block partials
+// reduced in FP64 in a fixed order as for the FP64 Gram.
+//   GRAM_F32:    v_mfma_f32_16x16x4f32 on the FP32 values (LDS row-major).
+//   GRAM_BF16X3: each value split once, at staging, into u = hi + lo, two
+//                BF16 numbers (round to nearest even), kept column-major in
+//                LDS so that one 8-byte read gives a lane its 4 k-values;
+//                u_a u_b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b on
 //                v_mfma_f32_16x16x16bf16 (products exact in FP32, relative
 //                error of the dropped lo_a lo_b term about 2^-16).
 // D layout of both FP32 MFMAs: lane l, element v holds D[4 (l / 16) + v]
@@ -137,8 +138,11 @@ k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
 // ---------------------------------------------------------------------------
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
-constexpr int GL_ELEMS = 4096;  // staged FP32 entries per chunk (16 KiB)
-constexpr int GL_ROWS = 256;    // longest FP32 accumulation between flushes
+constexpr int GL_THREADS = 512;
+constexpr int GL_RC = 64;           // rows per staged chunk (multiple of 16)
+constexpr int GL_CS = GL_RC + 4;    // BF16 column stride in LDS (shorts)
+constexpr int GL_MAXBLK = 1024;
+constexpr int GL_PE = GL_RC * MAXR / GL_THREADS;  // staged values per thread
 
 __device__ __forceinline__ short bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -149,11 +153,26 @@ __device__ __forceinline__ float bf16_val(short h) {
   return __uint_as_float(((uint32_t)(uint16_t)h) << 16);
 }
 
+int gram_lp_blocks(int64_t I, int64_t *rows_per_blk) {
+  const int64_t chunks = std::max<int64_t>((I + GL_RC - 1) / GL_RC, 1);
+  int nblk = (int)std::min<int64_t>(chunks, GL_MAXBLK);
+  const int64_t cpb = (chunks + nblk - 1) / nblk;
+  *rows_per_blk = cpb * GL_RC;
+  return (int)std::max<int64_t>(1, (I + *rows_per_blk - 1) / *rows_per_blk);
+}
+
 template <int MODE, int TPW, bool SCALE>
-__global__ void __launch_bounds__(GR_THREADS)
+__global__ void __launch_bounds__(GL_THREADS)
 k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
           int64_t I, int R, int Rp, int64_t rows_per_blk, double *partial) {
-  extern __shared__ float ldsf[];  // RC x Rp
+  constexpr int LDS_BYTES = MODE == GRAM_F32 ? GL_RC * (MAXR + 4) * 4
+                                             : 2 * MAXR * GL_CS * 2;
+  __shared__ __align__(16) char lds_raw[LDS_BYTES];
+  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS
+  float *ldsf = reinterpret_cast<float *>(lds_raw);  // F32: GL_RC x RS
+  short *hiT = reinterpret_cast<short *>(lds_raw);   // BF16: Rp x GL_CS
+  short *loT = hiT + MAXR * GL_CS;
+  const int RS = Rp + 4;  // F32 row stride
   const int w = threadIdx.x / WAVE, l = lane_id();
   const int nt = Rp / 16;
   const int ntri = nt * (nt + 1) / 2;
@@ -162,7 +181,7 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
   double accd[TPW][4];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
-    int t = w + 4 * i;
+    const int t = w + (GL_THREADS / WAVE) * i;
     ta[i] = tb[i] = -1;
     acc[i] = float4_t{0, 0, 0, 0};
 #pragma unroll
@@ -174,53 +193,69 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
       tb[i] = a + rem;
     }
   }
+  // padding (columns R..Rp-1, rows past a short last chunk) stays zero
+  for (int e = threadIdx.x; e < LDS_BYTES / 4; e += GL_THREADS)
+    reinterpret_cast<uint32_t *>(lds_raw)[e] = 0u;
+  if constexpr (SCALE)
+    for (int c = threadIdx.x; c < R; c += GL_THREADS) ssg[c] = sigma[c];
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(I, r0 + rows_per_blk);
-  // chunk rows: a multiple of 16 (the BF16 k-step), at most GL_ROWS
-  int RC = (GL_ELEMS / Rp) & ~15;
-  RC = RC < GL_ROWS ? RC : GL_ROWS;
-  const int NE = RC * Rp;
-  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS per entry
-  if constexpr (SCALE) {
-    for (int c = threadIdx.x; c < R; c += GR_THREADS) ssg[c] = sigma[c];
-    __syncthreads();
-  }
-  constexpr int PE = GL_ELEMS / GR_THREADS;
-  float v[PE];
+  const float rinv = 1.0f / (float)R;
+  // the chunk's nrow x R values are contiguous: value f of the chunk is
+  // row f / R, column f % R (the float quotient is exact to well under the
+  // 0.5 / R margin for f < GL_RC * MAXR)
+  using V = typename std::conditional<SCALE, double, float>::type;
+  V v[GL_PE];
   auto load = [&](int64_t c0) {
-    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
+    const int nv = (int)std::min<int64_t>(GL_RC, r1 - c0) * R;
 #pragma unroll
-    for (int q = 0; q < PE; ++q) {
-      const int e = q * GR_THREADS + threadIdx.x;
-      const int rr = e / Rp, cc = e - rr * Rp;
-      const int rc = rr < nrow ? rr : nrow - 1, ccc = cc < R ? cc : R - 1;
-      if constexpr (SCALE) {
-        const double x = X[(c0 + rc) * R + ccc];
-        const double sg = ssg[ccc];
-        v[q] = (float)(sg > 0 ? x / sg : 0.0);
-      } else {
-        v[q] = U[(c0 + rc) * R + ccc];
+    for (int q = 0; q < GL_PE; ++q) {
+      const int f = q * GL_THREADS + threadIdx.x;
+      if (f < nv) {
+        if constexpr (SCALE) v[q] = X[c0 * R + f];
+        else v[q] = U[c0 * R + f];
       }
     }
   };
   if (r0 < r1) load(r0);
-  for (int64_t c0 = r0; c0 < r1; c0 += RC) {
-    const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
-    __syncthreads();
+  for (int64_t c0 = r0; c0 < r1; c0 += GL_RC) {
+    const int nrow = (int)std::min<int64_t>(GL_RC, r1 - c0);
+    const int nv = nrow * R;
+    __syncthreads();  // the previous chunk's products are done
+    if (nrow < GL_RC)  // short last chunk: clear the rows it leaves
+      for (int e = threadIdx.x; e < (GL_RC - nrow) * R; e += GL_THREADS) {
+        const int rr = nrow + e / R, cc = e % R;
+        if constexpr (MODE == GRAM_F32) ldsf[rr * RS + cc] = 0.0f;
+        else hiT[cc * GL_CS + rr] = loT[cc * GL_CS + rr] = 0;
+      }
 #pragma unroll
-    for (int q = 0; q < PE; ++q) {
-      const int e = q * GR_THREADS + threadIdx.x;
-      const int rr = e / Rp, cc = e - rr * Rp;
-      const bool in = rr < nrow && cc < R;
-      if constexpr (SCALE)
-        if (in && e < NE) Uout[(c0 + rr) * R + cc] = v[q];
-      if (e < NE) ldsf[e] = in ? v[q] : 0.0f;
+    for (int q = 0; q < GL_PE; ++q) {
+      const int f = q * GL_THREADS + threadIdx.x;
+      if (f < nv) {
+        const int rr = (int)(((float)f + 0.5f) * rinv), cc = f - rr * R;
+        float x;
+        if constexpr (SCALE) {
+          const double sg = ssg[cc];
+          x = (float)(sg > 0 ? v[q] / sg : 0.0);
+          Uout[c0 * R + f] = x;
+        } else {
+          x = v[q];
+        }
+        if constexpr (MODE == GRAM_F32) {
+          ldsf[rr * RS + cc] = x;
+        } else {
+          const short h = bf16_rne(x);
+          hiT[cc * GL_CS + rr] = h;
+          loT[cc * GL_CS + rr] = bf16_rne(x - bf16_val(h));
+        }
+      }
     }
     __syncthreads();
-    if (c0 + RC < r1) load(c0 + RC);
+    if (c0 + GL_RC < r1) load(c0 + GL_RC);
     if constexpr (MODE == GRAM_F32) {
-      for (int k0 = 0; k0 < RC; k0 += 4) {
-        const float *rowp = ldsf + (k0 + l / 16) * Rp + (l % 16);
+#pragma unroll 2
+      for (int k0 = 0; k0 < GL_RC; k0 += 4) {
+        const float *rowp = ldsf + (k0 + l / 16) * RS + (l % 16);
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
           if (ta[i] < 0) continue;
@@ -229,22 +264,18 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
         }
       }
     } else {
-      for (int k0 = 0; k0 < RC; k0 += 16) {
-        const float *rowp = ldsf + (k0 + 4 * (l / 16)) * Rp + (l % 16);
+#pragma unroll 1
+      for (int k0 = 0; k0 < GL_RC; k0 += 16) {
+        const int ko = k0 + 4 * (l / 16);
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
           if (ta[i] < 0) continue;
-          short4_t ah, al, bh, bl;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float a = rowp[q * Rp + ta[i] * 16];
-            const float b = rowp[q * Rp + tb[i] * 16];
-            const short a1 = bf16_rne(a), b1 = bf16_rne(b);
-            ah[q] = a1;
-            bh[q] = b1;
-            al[q] = bf16_rne(a - bf16_val(a1));
-            bl[q] = bf16_rne(b - bf16_val(b1));
-          }
+          const int ca = (ta[i] * 16 + (l % 16)) * GL_CS + ko;
+          const int cb = (tb[i] * 16 + (l % 16)) * GL_CS + ko;
+          const short4_t ah = *reinterpret_cast<const short4_t *>(hiT + ca);
+          const short4_t al = *reinterpret_cast<const short4_t *>(loT + ca);
+          const short4_t bh = *reinterpret_cast<const short4_t *>(hiT + cb);
+          const short4_t bl = *reinterpret_cast<const short4_t *>(loT + cb);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[i], 0, 0, 0);
           acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[i], 0, 0, 0);
@@ -689,6 +720,10 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
 
 // ---------------------------------------------------------------------------
 // Row solve: X[i] = m G^+ + (m - (m G^+) G) G^+  (FP64), column sums of X^2.
+// REFINE = false drops the refinement term: X[i] = m G^+, a third of the
+// MFMA work (the default for FP32 factors, whose M comes from an FP32
+// MTTKRP: its rounding, amplified by the condition of G, bounds the
+// accuracy of X far above the FP64 rounding the refinement removes).
 // One wave per 16-row tile of M, on FP64 MFMA in transposed form:
 // X^T = (G^+)^T M^T.  With A = (G^+)^T (or G^T) and B = M^T, the accumulator
 // of tile t holds X[row0 + l % 16][16 t + l / 16 + 4 v] in lane l, element v,
@@ -710,16 +745,33 @@ __device__ __forceinline__ double afrag(const double *A, int R, int t, int ks,
   return (i < R && k < R) ? v : 0.0;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool REFINE>
 __global__ void __launch_bounds__(SV_THREADS)
-__attribute__((amdgpu_waves_per_eu(NT <= 2 ? 2 : 1)))
+__attribute__((amdgpu_waves_per_eu((NT <= 2 || !REFINE) ? 2 : 1)))
 k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         double *X, double *partial, int64_t *rows_out) {
   constexpr int KS = 4 * NT;          // k-steps
   constexpr int RP = 16 * NT;
-  constexpr bool LDS = NT <= 4;       // G, G^+ staged in LDS (zero padded)
+  constexpr int NM = REFINE ? 2 : 1;  // matrices staged: G^+ (and G)
+  constexpr bool LDS = NT <= 4;       // staged square (zero padded)
+  // wider ranks: their upper triangles, packed
+  // (RP (RP + 1) / 2 doubles each: 51 KiB at RP = 112, 66 KiB at RP = 128)
+  constexpr int PT = RP * (RP + 1) / 2;
   const int l = lane_id(), w = threadIdx.x / WAVE;
-  __shared__ double sG[LDS ? 2 * RP * RP : 1];
+  __shared__ double sG[LDS ? NM * RP * RP : NM * PT];
+  if (!LDS) {
+    for (int e = threadIdx.x; e < RP * RP; e += SV_THREADS) {
+      const int a = e / RP, b = e % RP;
+      if (a <= b) {
+        const bool in = a < R && b < R;
+        const int ec = in ? a * R + b : 0;
+        const int pi = a * (2 * RP - a + 1) / 2 + (b - a);
+        sG[pi] = in ? Gp[ec] : 0.0;
+        if constexpr (REFINE) sG[PT + pi] = in ? G[ec] : 0.0;
+      }
+    }
+    __syncthreads();
+  }
   if (LDS) {
     constexpr int NS = (RP * RP + SV_THREADS - 1) / SV_THREADS;
     double gp[NS], g[NS];
@@ -729,7 +781,7 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
       const int a = e / RP, b = e % RP;
       const int ec = (e < RP * RP && a < R && b < R) ? a * R + b : 0;
       gp[q] = Gp[ec];
-      g[q] = G[ec];
+      if constexpr (REFINE) g[q] = G[ec];
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
@@ -738,23 +790,38 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
       const double m = (e < RP * RP && a < R && b < R) ? 1.0 : 0.0;
       if (e < RP * RP) {
         sG[e] = gp[q] * m;
-        sG[RP * RP + e] = g[q] * m;
+        if constexpr (REFINE) sG[RP * RP + e] = g[q] * m;
       }
     }
     __syncthreads();
   }
   // (A^T)[i][k] fragments, i = 16 t + l % 16, k = 4 ks + l / 16
+  int lz = l;  // the tile loop re-derives it opaquely (see opaque_lane)
+  auto pk = [&](int t, int ks) -> int {  // packed index of a symmetric pair
+    const int i = 16 * t + (lz % 16), k = 4 * ks + lz / 16;
+    const int a = k < i ? k : i, b = k < i ? i : k;
+    return a * (2 * RP - a + 1) / 2 + (b - a);
+  };
   auto fp = [&](int t, int ks) -> double {
     return LDS ? sG[(4 * ks + l / 16) * RP + 16 * t + (l % 16)]
-               : afrag<NT>(Gp, R, t, ks, l);
+               : sG[pk(t, ks)];
   };
   auto fg = [&](int t, int ks) -> double {
     return LDS ? sG[RP * RP + (4 * ks + l / 16) * RP + 16 * t + (l % 16)]
-               : afrag<NT>(G, R, t, ks, l);
+               : sG[PT + pk(t, ks)];
   };
-  double ss[NT][4];
+  // Column sums of X^2: in registers for NT <= 4; wider ranks add each
+  // tile's sums (a shuffle tree over its 16 rows) to the wave's row of
+  // `red` in LDS, in tile order, to leave registers to the products (and
+  // do not prefetch the next tile: one tile's MFMA work hides its loads).
+  constexpr bool WIDE = NT > 4;
+  __shared__ double red[SV_THREADS / WAVE][MAXR];
+  if constexpr (WIDE) {
+    for (int c = l; c < MAXR; c += WAVE) red[w][c] = 0.0;
+  }
+  double ss[WIDE ? 1 : NT][4];
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+  for (int t = 0; t < (WIDE ? 1 : NT); ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) ss[t][v] = 0.0;
   int nrows = 0;
@@ -775,16 +842,18 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
     }
   };
   int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
-  if (tile < ntiles) load_tile(tile);
+  if (!WIDE && tile < ntiles) load_tile(tile);
   for (; tile < ntiles; tile += tstep) {
     const int64_t row = tile * 16 + (l % 16);
+    if constexpr (WIDE) load_tile(tile);
     T cur[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) cur[ks] = raw[ks];
-    if (tile + tstep < ntiles) load_tile(tile + tstep);
+    if (!WIDE && tile + tstep < ntiles) load_tile(tile + tstep);
     // G, G^+ fragments are read from LDS in every tile rather than held in
     // registers
-    if (LDS) asm volatile("" ::: "memory");
+    asm volatile("" ::: "memory");
+    if constexpr (WIDE) lz = opaque_lane();
     double mf[KS];
     bool nz = false;
 #pragma unroll
@@ -795,7 +864,8 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
     }
     const uint64_t b = __ballot(nz);
     nrows += __popcll((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xffffull);
-    // X^T = G^+ M^T
+    // X^T = G^+ M^T (wide ranks: a scheduling barrier per output tile
+    // keeps each tile's fragment loads next to its MFMAs)
     double4_t ax[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -805,7 +875,9 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fp(t, ks), mf[ks], ax[t],
                                                      0, 0, 0);
       }
+      if constexpr (WIDE) __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (REFINE) {
     // R^T = M^T - G X^T
     double rf[KS];
 #pragma unroll
@@ -818,6 +890,7 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) rf[4 * t + v] = mf[4 * t + v] - ar[v];
+      if constexpr (WIDE) __builtin_amdgcn_sched_barrier(0);
     }
     // X^T += G^+ R^T
 #pragma unroll
@@ -827,6 +900,8 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
         ax[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fp(t, ks), rf[ks], ax[t],
                                                      0, 0, 0);
       }
+      if constexpr (WIDE) __builtin_amdgcn_sched_barrier(0);
+    }
     }
     if (row < I) {
 #pragma unroll
@@ -836,8 +911,19 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
           const int c = 16 * t + l / 16 + 4 * v;
           if (c < R) {
             X[row * R + c] = ax[t][v];
-            ss[t][v] += ax[t][v] * ax[t][v];
+            if constexpr (!WIDE) ss[t][v] += ax[t][v] * ax[t][v];
           }
+        }
+    }
+    if constexpr (WIDE) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 16 * t + l / 16 + 4 * v;
+          double q = (row < I) ? ax[t][v] * ax[t][v] : 0.0;
+          for (int o = 1; o < 16; o <<= 1) q += __shfl_xor(q, o, WAVE);
+          if ((l % 16) == 0 && c < R) red[w][c] += q;
         }
     }
   }
@@ -853,16 +939,17 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
   }
   // fixed-order reduction of the column sums: the 16 row lanes of a column
   // (shuffle tree), then waves (LDS, in wave order)
-  __shared__ double red[SV_THREADS / WAVE][MAXR];
+  if constexpr (!WIDE) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double s = ss[t][v];
-      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, WAVE);
-      const int c = 16 * t + l / 16 + 4 * v;
-      if ((l % 16) == 0 && c < R) red[w][c] = s;
-    }
+      for (int v = 0; v < 4; ++v) {
+        double s = ss[t][v];
+        for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, WAVE);
+        const int c = 16 * t + l / 16 + 4 * v;
+        if ((l % 16) == 0 && c < R) red[w][c] = s;
+      }
+  }
   __syncthreads();
   for (int c = threadIdx.x; c < R; c += SV_THREADS) {
     double v = 0;
@@ -934,7 +1021,7 @@ void convert_values(const void *src, int src_fp64, void *dst, int dst_fp64,
 
 size_t gram_temp_bytes(int64_t I, int R) {
   int64_t rpb;
-  int nblk = gram_blocks(I, &rpb);
+  const int nblk = std::max(gram_blocks(I, &rpb), gram_lp_blocks(I, &rpb));
   return (size_t)nblk * R * R * sizeof(double) + 256;
 }
 
@@ -950,18 +1037,18 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
   double *partial = static_cast<double *>(tmp);
   if constexpr (std::is_same<T, float>::value) {
     if (mode != GRAM_F64) {
-#define CPR_GRAM_LP(M, K)                                                    \
-  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE>), dim3(nblk), dim3(GR_THREADS), \
-                     GL_ELEMS * sizeof(float), s, U, X, sigma, Uout, I, R,   \
-                     Rp, rpb, partial)
-#define CPR_GRAM_LP_T(M)                        \
-  switch (tpw) {                                \
-    case 1: CPR_GRAM_LP(M, 1); break;           \
-    case 2: CPR_GRAM_LP(M, 2); break;           \
-    case 3: CPR_GRAM_LP(M, 3); break;           \
-    case 4: CPR_GRAM_LP(M, 4); break;           \
-    case 6: case 5: CPR_GRAM_LP(M, 6); break;   \
-    default: CPR_GRAM_LP(M, 9); break;          \
+      const int nbl = gram_lp_blocks(I, &rpb);
+      const int tpl = (ntri + GL_THREADS / WAVE - 1) / (GL_THREADS / WAVE);
+#define CPR_GRAM_LP(M, K)                                                   \
+  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE>), dim3(nbl), dim3(GL_THREADS), \
+                     0, s, U, X, sigma, Uout, I, R, Rp, rpb, partial)
+#define CPR_GRAM_LP_T(M)              \
+  switch (tpl) {                      \
+    case 1: CPR_GRAM_LP(M, 1); break; \
+    case 2: CPR_GRAM_LP(M, 2); break; \
+    case 3: CPR_GRAM_LP(M, 3); break; \
+    case 4: CPR_GRAM_LP(M, 4); break; \
+    default: CPR_GRAM_LP(M, 5); break; \
   }
       if (mode == GRAM_F32) {
         CPR_GRAM_LP_T(GRAM_F32)
@@ -971,7 +1058,7 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
 #undef CPR_GRAM_LP_T
 #undef CPR_GRAM_LP
       CPR_LAUNCH_CHECK();
-      colsum(partial, nblk, R * R, G, 0, nullptr, s);
+      colsum(partial, nbl, R * R, G, 0, nullptr, s);
       CPR_LAUNCH_CHECK();
       return;
     }
@@ -1068,29 +1155,43 @@ int solve_blocks(int64_t I) {
   return (int)std::min<int64_t>(SV_RESBLK, std::max<int64_t>(1, (I + 63) / 64));
 }
 
+template <typename T, bool RF>
+void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
+                   const double *Gp, double *X, double *partial, int nblk,
+                   int64_t *rows_out, hipStream_t s) {
+  const dim3 g(nblk), b(SV_THREADS);
+#define CPR_SOLVE(NT)                                                      \
+  hipLaunchKernelGGL((k_solve<T, NT, RF>), g, b, 0, s, M, I, R, Gfull, Gp, \
+                     X, partial, rows_out)
+  switch ((R + 15) / 16) {
+    case 1: CPR_SOLVE(1); break;
+    case 2: CPR_SOLVE(2); break;
+    case 3: CPR_SOLVE(3); break;
+    case 4: CPR_SOLVE(4); break;
+    case 5: CPR_SOLVE(5); break;
+    case 6: CPR_SOLVE(6); break;
+    case 7: CPR_SOLVE(7); break;
+    default: CPR_SOLVE(8); break;
+  }
+#undef CPR_SOLVE
+  CPR_LAUNCH_CHECK();
+}
+
 template <typename T>
 void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
                 const double *Gp, double *X, double *partial, int nblk,
-                int64_t *rows_out, hipStream_t s) {
-  const dim3 g(nblk), b(SV_THREADS);
-  switch ((R + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_solve<T, 1>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 2: hipLaunchKernelGGL((k_solve<T, 2>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 3: hipLaunchKernelGGL((k_solve<T, 3>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 4: hipLaunchKernelGGL((k_solve<T, 4>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 5: hipLaunchKernelGGL((k_solve<T, 5>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 6: hipLaunchKernelGGL((k_solve<T, 6>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    case 7: hipLaunchKernelGGL((k_solve<T, 7>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-    default: hipLaunchKernelGGL((k_solve<T, 8>), g, b, 0, s, M, I, R, Gfull, Gp, X, partial, rows_out); break;
-  }
-  CPR_LAUNCH_CHECK();
+                int64_t *rows_out, bool refine, hipStream_t s) {
+  if (refine)
+    solve_rows_nt<T, true>(M, I, R, Gfull, Gp, X, partial, nblk, rows_out, s);
+  else
+    solve_rows_nt<T, false>(M, I, R, Gfull, Gp, X, partial, nblk, rows_out, s);
 }
 template void solve_rows<float>(const float *, int64_t, int, const double *,
                                 const double *, double *, double *, int,
-                                int64_t *, hipStream_t);
+                                int64_t *, bool, hipStream_t);
 template void solve_rows<double>(const double *, int64_t, int, const double *,
                                  const double *, double *, double *, int,
-                                 int64_t *, hipStream_t);
+                                 int64_t *, bool, hipStream_t);
 
 template <typename T>
 void finish_normalize(const double *X, int64_t I, int R, const double *partial,

@@ -18,14 +18,31 @@ constexpr int FT_MAXBLK = 2048;
 // and their coordinates (decoded from the column keys, mode 1 fastest) are
 // staged in LDS; each group of L lanes takes one nonzero, finds its column
 // by bisection of the staged offsets and adds
-// v * sum_r sigma_r U_0[i_0, r] prod_{k > 0} U_k[i_k, r].
+// v * sum_r sigma_r U_0[i_0, r] prod_{k > 0} U_k[i_k, r], lane gl of the
+// group holding the VW consecutive columns from gl VW (one 16-byte load per
+// factor row when R is a multiple of VW).
 constexpr int FI_E = 1024;
+
+template <typename T, int VW>
+__device__ __forceinline__ void fit_cols(const T *r, int cb, int R, bool vec,
+                                         T (&x)[VW]) {
+  if (vec) {
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    const vec_t v = *reinterpret_cast<const vec_t *>(r + (cb <= R - VW ? cb : R - VW));
+#pragma unroll
+    for (int q = 0; q < VW; ++q) x[q] = v[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < VW; ++q) x[q] = r[cb + q < R ? cb + q : R - 1];
+  }
+}
 
 template <typename T, int L>
 __global__ void __launch_bounds__(FT_THREADS)
 k_fit_index(const int64_t *col_ptr, const uint64_t *col_key, int64_t n_cols,
             const int32_t *row, const T *val, int64_t nnz, const T *U0,
             ModeList ml, const double *sigma, int R, double *partial) {
+  constexpr int VW = 16 / sizeof(T);
   constexpr int GPW = WAVE / L, GPB = GPW * (FT_THREADS / WAVE);
   __shared__ int64_t sptr[FI_E + 1];
   __shared__ int32_t scrd[FI_E][MAXN - 1];
@@ -33,6 +50,11 @@ k_fit_index(const int64_t *col_ptr, const uint64_t *col_key, int64_t n_cols,
   __shared__ double red[FT_THREADS / WAVE];
   const int l = lane_id(), w = threadIdx.x / WAVE;
   const int gl = l % L, grp = w * GPW + l / L;
+  const int cb = gl * VW;
+  const bool vec = R % VW == 0;
+  double sg[VW];  // sigma of this lane's columns (zero past R)
+#pragma unroll
+  for (int q = 0; q < VW; ++q) sg[q] = cb + q < R ? sigma[cb + q] : 0.0;
   const int64_t nrange = (nnz + FI_E - 1) / FI_E;
   double acc = 0;
   for (int64_t rg = blockIdx.x; rg < nrange; rg += gridDim.x) {
@@ -63,14 +85,20 @@ k_fit_index(const int64_t *col_ptr, const uint64_t *col_key, int64_t n_cols,
         const int mid = (lo + hi + 1) >> 1;
         if (sptr[mid] <= e) lo = mid; else hi = mid - 1;
       }
-      const int64_t i0 = row[e];
-      double part = 0;
-      for (int r = gl; r < R; r += L) {
-        double p = sigma[r] * (double)U0[i0 * R + r];
-        for (int q = 0; q < ml.n; ++q)
-          p *= (double)static_cast<const T *>(ml.U[q])[(int64_t)scrd[lo][q] * R + r];
-        part += p;
+      T x[VW];
+      fit_cols<T, VW>(U0 + (int64_t)row[e] * R, cb, R, vec, x);
+      double p[VW];
+#pragma unroll
+      for (int q = 0; q < VW; ++q) p[q] = sg[q] * (double)x[q];
+      for (int k = 0; k < ml.n; ++k) {
+        fit_cols<T, VW>(static_cast<const T *>(ml.U[k]) + (int64_t)scrd[lo][k] * R,
+                        cb, R, vec, x);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) p[q] *= (double)x[q];
       }
+      double part = 0;
+#pragma unroll
+      for (int q = 0; q < VW; ++q) part += p[q];
       acc += part * (double)val[e];
     }
     __syncthreads();
@@ -146,9 +174,13 @@ void fit_inner_index(const int64_t *col_ptr, const uint64_t *col_key,
 #define CPR_FIT(L)                                                         \
   hipLaunchKernelGGL((k_fit_index<T, L>), g, b, 0, s, col_ptr, col_key,    \
                      n_cols, row, val, nnz, U0, ml, sigma, R, partial)
-  if (R <= 8) CPR_FIT(8);
-  else if (R <= 16) CPR_FIT(16);
-  else if (R <= 32) CPR_FIT(32);
+  // L lanes of VW columns cover the rank (L VW >= R, R <= 128)
+  const int vw = 16 / (int)sizeof(T), need = (R + vw - 1) / vw;
+  if (need <= 2) CPR_FIT(2);
+  else if (need <= 4) CPR_FIT(4);
+  else if (need <= 8) CPR_FIT(8);
+  else if (need <= 16) CPR_FIT(16);
+  else if (need <= 32) CPR_FIT(32);
   else CPR_FIT(64);
 #undef CPR_FIT
   CPR_LAUNCH_CHECK();

@@ -392,23 +392,45 @@ k_bk_plan(const int64_t *bk_start, int64_t *bk_fill, int nbk,
 // the bucket's nonzeros in the whole mode bound the nonzeros any solve can
 // extract into it (extracted positions are distinct).  starts = exclusive
 // prefix sums of the row-bucket histogram (nbk + 1 entries).
-__global__ void __launch_bounds__(MT_THREADS)
+//
+// Power-law rows put a large share of the nonzeros in a few buckets, and
+// global atomics on one address serialise; so each workgroup counts one
+// window of BH_WIN buckets in LDS over one chunk of the nonzeros (grid.x =
+// chunks, grid.y = windows) and flushes its window with one atomic per
+// bucket.  Every window re-reads the row array: (nbk / BH_WIN) passes.
+constexpr int BH_THREADS = 1024;
+constexpr int BH_WIN = 32768;  // 128 KiB of u32 counters
+__global__ void __launch_bounds__(BH_THREADS)
 k_bucket_hist(const int32_t *row, int64_t nnz, int nbk, int bb, int64_t *cnt) {
-  extern __shared__ uint32_t bh[];  // nbk when nbk <= BK_LDS_MAX
-  const bool use_lds = nbk <= BK_LDS_MAX;
-  if (use_lds)
-    for (int b = threadIdx.x; b < nbk; b += MT_THREADS) bh[b] = 0;
+  extern __shared__ uint32_t bh[];
+  const int b0 = blockIdx.y * BH_WIN;
+  const int nw = nbk - b0 < BH_WIN ? nbk - b0 : BH_WIN;
+  for (int b = threadIdx.x; b < nw; b += BH_THREADS) bh[b] = 0;
   __syncthreads();
-  for (int64_t e = (int64_t)blockIdx.x * MT_THREADS + threadIdx.x; e < nnz;
-       e += (int64_t)gridDim.x * MT_THREADS) {
-    const int b = row[e] >> bb;
-    if (use_lds) atomicAdd(&bh[b], 1u);
-    else atomicAdd((unsigned long long *)&cnt[b], 1ull);
+  // chunk of whole int4 groups (the row array is 16-byte aligned)
+  const int64_t nq = nnz >> 2;
+  const int64_t per = (nq + gridDim.x - 1) / gridDim.x;
+  const int64_t q0 = (int64_t)blockIdx.x * per;
+  const int64_t q1 = q0 + per < nq ? q0 + per : nq;
+  const int4 *row4 = reinterpret_cast<const int4 *>(row);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += BH_THREADS) {
+    const int4 r = row4[q];
+    const unsigned a = (unsigned)((r.x >> bb) - b0), b = (unsigned)((r.y >> bb) - b0),
+                   c = (unsigned)((r.z >> bb) - b0), d = (unsigned)((r.w >> bb) - b0);
+    if (a < (unsigned)nw) atomicAdd(&bh[a], 1u);
+    if (b < (unsigned)nw) atomicAdd(&bh[b], 1u);
+    if (c < (unsigned)nw) atomicAdd(&bh[c], 1u);
+    if (d < (unsigned)nw) atomicAdd(&bh[d], 1u);
   }
+  if (blockIdx.x == 0)  // the last nnz % 4 nonzeros
+    for (int64_t e = (nq << 2) + threadIdx.x; e < nnz; e += BH_THREADS) {
+      const unsigned a = (unsigned)((row[e] >> bb) - b0);
+      if (a < (unsigned)nw) atomicAdd(&bh[a], 1u);
+    }
   __syncthreads();
-  if (use_lds)
-    for (int b = threadIdx.x; b < nbk; b += MT_THREADS)
-      if (bh[b]) atomicAdd((unsigned long long *)&cnt[b], (unsigned long long)bh[b]);
+  for (int b = threadIdx.x; b < nw; b += BH_THREADS)
+    if (bh[b])
+      atomicAdd((unsigned long long *)&cnt[b0 + b], (unsigned long long)bh[b]);
 }
 
 // One extracted nonzero in bucket order: key = (distinct column u << 8) |
@@ -949,10 +971,13 @@ void bucket_regions(const int32_t *row, int64_t nnz, int64_t I, int bb,
                     hipStream_t s) {
   const int nbk = (int)((I + (1 << bb) - 1) >> bb);
   zero_fill<int64_t>(cnt, nbk + 1, s);
-  const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
-  const int64_t g = std::min<int64_t>(std::max<int64_t>(ceil_div(nnz, MT_THREADS), 1), 2048);
-  hipLaunchKernelGGL(k_bucket_hist, dim3((unsigned)g), dim3(MT_THREADS), hl, s,
-                     row, nnz, nbk, bb, cnt);
+  const int nwin = (nbk + BH_WIN - 1) / BH_WIN;
+  const size_t hl = (size_t)std::min(nbk, BH_WIN) * 4;
+  // about one workgroup per CU and window, fewer for small inputs
+  const int64_t chunks = std::min<int64_t>(
+      std::max<int64_t>(ceil_div(nnz, (int64_t)BH_THREADS * 16), 1), 256);
+  hipLaunchKernelGGL(k_bucket_hist, dim3((unsigned)chunks, (unsigned)nwin),
+                     dim3(BH_THREADS), hl, s, row, nnz, nbk, bb, cnt);
   CPR_LAUNCH_CHECK();
   exclusive_scan_i64(cnt, starts, nbk + 1, scan_tmp, s);
 }

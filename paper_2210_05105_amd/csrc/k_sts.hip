@@ -1250,15 +1250,6 @@ __device__ __forceinline__ double tile_mass_s(const double (&xA)[4 * NT],
 
 // The same for Q = G_{>k} (*) G^node with the node's packed upper triangle
 // nd (global) and the G_{>k} fragments sG (LDS, off-diagonal blocks doubled).
-// A lane id the compiler cannot see through: index arithmetic derived from
-// it stays inside the loop that uses it instead of being hoisted out as
-// loop-invariant registers (one per fragment).
-__device__ __forceinline__ int opaque_lane() {
-  int z;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-  return lane_id() + z;
-}
-
 template <int NT>
 __device__ __forceinline__ double tile_mass_node(const double (&xA)[4 * NT],
                                                  const double *nd,

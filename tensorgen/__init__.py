@@ -306,8 +306,9 @@ def zipf_coords_device(seed, dims, nnz, s, device, oversample=1.6,
     """Distinct coordinates with Zipf(s) marginals per mode, on `device`.
 
     Raw draws are packed into one or two int64 keys (modes split where 64
-    bits would be exceeded), deduplicated, and a uniformly random subset of
-    exactly nnz distinct tuples is returned (int32 [nnz, N], random order).
+    bits would be exceeded), deduplicated, and a random subset of exactly
+    nnz distinct tuples is returned (int32 [nnz, N], grouped by hash part,
+    sorted by key within a part).
     """
     torch = _torch()
     g = torch.Generator(device=device)
@@ -350,15 +351,25 @@ def zipf_coords_device(seed, dims, nnz, s, device, oversample=1.6,
         if log:
             log(f"tensorgen: {have} distinct of {nnz} wanted")
         oversample = max(1.3, oversample * 1.2)
-    # exactly nnz of them, uniformly at random: each part keeps its share
-    # (a random subset of it), the shares adding up to nnz
+    # exactly nnz of them: each part keeps its share k of its n distinct
+    # tuples by Bernoulli(k / n) thinning, the few (about sqrt(k)) kept too
+    # many or too few settled at the part's end
     out = torch.empty((nnz, N), dtype=torch.int32, device=device)
     at, left = 0, nnz
     for i, (a, b) in enumerate(parts):
-        k = left if i == len(parts) - 1 else \
-            int(round(nnz * a.shape[0] / have))
-        k = min(k, a.shape[0], left)
-        keep = torch.randperm(a.shape[0], generator=g, device=device)[:k]
+        n_p = a.shape[0]
+        k = left if i == len(parts) - 1 else int(round(nnz * n_p / have))
+        k = min(k, n_p, left)
+        keep = torch.rand(n_p, generator=g, device=device) < (k / n_p)
+        m = int(keep.sum())
+        if m > k:  # drop the last m - k kept
+            pos = torch.nonzero(keep).squeeze(1)
+            keep[pos[k:]] = False
+            del pos
+        elif m < k:  # add the first k - m not kept
+            pos = torch.nonzero(~keep).squeeze(1)
+            keep[pos[:k - m]] = True
+            del pos
         _dev_unpack(a[keep], bits[:split], out[at:at + k], 0)
         if split < N:
             _dev_unpack(b[keep], bits[split:], out[at:at + k], split)
@@ -367,9 +378,7 @@ def zipf_coords_device(seed, dims, nnz, s, device, oversample=1.6,
         del keep
     assert at == nnz, (at, nnz)
     del parts, cdfs, perms
-    # random order (parts are grouped by hash)
-    return out[torch.randperm(nnz, generator=g, device=device)] \
-        if nnz < (1 << 31) else out
+    return out
 
 
 def values_device(seed, n, kind, device):

@@ -45,11 +45,12 @@ def test_library_is_gfx950_only(lib):
 
 
 def _init(lib, N=3, dims=(4, 5, 6), nnz=10, R=4, sampler=0, precision=0,
-          max_J=8, leaf=0, idx=1, val=1, bucket_rows=0, solve_gram=0):
+          max_J=8, leaf=0, idx=1, val=1, bucket_rows=0, solve_gram=0,
+          solve_refine=0):
     d = (C.c_int64 * max(N, 1))(*list(dims)[:max(N, 1)])
     t = binding._Tensor(N, d, nnz, idx, val, 1)
     cfg = binding._Config(R, sampler, precision, leaf, max_J, bucket_rows,
-                          solve_gram)
+                          solve_gram, solve_refine)
     h = C.c_void_p()
     st = lib.cp_init(C.byref(t), C.byref(cfg), None, C.byref(h))
     return st, h
@@ -61,6 +62,7 @@ def _init(lib, N=3, dims=(4, 5, 6), nnz=10, R=4, sampler=0, precision=0,
                                 dict(max_J=0), dict(leaf=8),
                                 dict(bucket_rows=48), dict(bucket_rows=512),
                                 dict(bucket_rows=8), dict(solve_gram=2),
+                                dict(solve_refine=3), dict(solve_refine=-1),
                                 dict(dims=(4, 0, 6)), dict(dims=(4, 2**31, 6)),
                                 dict(idx=None), dict(val=None)])
 def test_init_rejects_bad_arguments_before_touching_the_gpu(lib, kw):

@@ -120,6 +120,41 @@ def test_error_of_each_result_against_fp64(dev, prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_solve_refinement_below_fp32_rounding(dev, prec):
+    """The row solve with one refinement step (refine=True) and without (the
+    default of the FP32 forms), from the same stored factors and draws, so
+    the same M up to the FP32 MTTKRP's order of accumulation.  Both are
+    within the FP32 bar of the FP64 solve of the oracle's M, and refining
+    does not reduce that error materially: M's FP32 rounding, amplified by
+    the condition of G, bounds it, not the solve's FP64 rounding."""
+    T = tg.zipf_tensor(85, (3000, 2000, 1500), 200_000, s=1.1)
+    R, J, j = 32, 8192, 1
+    errs = {}
+    for refine in (True, False):
+        ctx = make_ctx(dev, T, R, "arls", prec, J, refine=refine)
+        _, runi = init_ctx(ctx, T.dims, R, 86, fp32=True)
+        U, _ = gpu_state(ctx)
+        u = tg.uniform_block(runi, J, 3)
+        gidx, gprob = ctx.sample(j, torch.from_numpy(u))
+        gidx, gprob = to_np(gidx).astype(np.int64), to_np(gprob)
+        ctx.sampled_mttkrp(j, want_M=False)
+        ctx.solve_factor(j)
+        Uj = to_np(ctx.get_factor(j))
+        ctx.close()
+        from tests.helpers import oracle_sampled_M
+        Mx = oracle_sampled_M(T, T.dims, j, gidx, gprob, U, J)["M"]
+        Ghx = O.gram_hadamard([O.gram(x) for x in U], j)
+        Ux, _ = O.solve(Mx, O.pinv_psd(Ghx))
+        errs[refine] = rel_fro(Uj, Ux)
+        kappa = cond_psd(Ghx)
+    print(f"\n[{prec}] U_j error vs FP64 (cond(G) = {kappa:.1f}): refined "
+          f"{errs[True]:.2e}, unrefined {errs[False]:.2e}")
+    for e in errs.values():
+        assert e < 1e-5 + 10 * kappa * GRAM_ATOL[prec]
+    assert errs[False] < 1.5 * errs[True] + 1e-9
+
+
 @pytest.mark.parametrize("sampler", ["arls", "sts"])
 def test_mixed_and_fp64_reach_equal_fit(dev, sampler):
     """Identical inputs (FP32-representable tensor values and initial
