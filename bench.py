@@ -8,8 +8,8 @@ the resident synthetic tensor.  The default workload is the largest
 single-GPU configuration: the 3-way power-law tensor 8,000,000 x 8,000,000 x
 200,000 with 1.5 billion nonzeros (Zipf(1.05) indices, lognormal FP32
 values), R = 100, J = 262,144 draws per mode solve, STS-CP, mixed precision
-(FP32 MTTKRP, split-BF16 MFMA factor Grams, FP64 sampler and refined
-solve), generated on the GPU.  Other workloads: zipf3 (100,000 x 80,000 x
+(FP32 MTTKRP, split-BF16 MFMA factor Grams, FP64 sampler and row solve),
+generated on the GPU.  Other workloads: zipf3 (100,000 x 80,000 x
 60,000, 50M nonzeros, R = 32), zipf4 (4-way, 200M nonzeros, R = 64,
 CP-ARLS-LEV), planted (200 x 150 x 100, R = 8).  Prints one JSON line.
 """
@@ -66,6 +66,9 @@ def parse():
                    metavar=("FETCH_DB", "WRITE_DB", "SOLVES"),
                    help="reduce two rocprofv3 --pmc databases to HBM bytes "
                         "per mode solve and exit")
+    p.add_argument("--kernel-stats", metavar="DB",
+                   help="print per-kernel totals of a rocprofv3 "
+                        "--kernel-trace database as a markdown table and exit")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also copy MIB MiB device to device (a plain copy "
                         "kernel of known size, to scale HBM counters)")
@@ -221,6 +224,34 @@ def source_digest(files):
     return h.hexdigest()[:16]
 
 
+def short_kernel_name(n):
+    import re
+    n = re.sub(r"^void ", "", n)
+    n = re.sub(r"cpr::\(anonymous namespace\)::", "", n)
+    return re.sub(r"\(.*$", "", n)
+
+
+def kernel_stats(db, top=60):
+    """Markdown table of per-kernel time from a rocprofv3 database."""
+    import sqlite3
+    from collections import defaultdict
+    cur = sqlite3.connect(db).cursor()
+    tot, cnt = defaultdict(float), defaultdict(int)
+    for n, b, e in cur.execute("select kernel_name, start, end from kernels"):
+        k = short_kernel_name(n)
+        tot[k] += e - b
+        cnt[k] += 1
+    allt = sum(tot.values())
+    out = ["| kernel | calls | total ms | avg us | % |",
+           "|---|---:|---:|---:|---:|"]
+    for k in sorted(tot, key=lambda k: -tot[k])[:top]:
+        out.append(f"| {k} | {cnt[k]} | {tot[k] / 1e6:.2f} | "
+                   f"{tot[k] / cnt[k] / 1e3:.1f} | {100 * tot[k] / allt:.1f} |")
+    out.append(f"\ntotal kernel time {allt / 1e6:.1f} ms over "
+               f"{sum(cnt.values())} dispatches")
+    return "\n".join(out)
+
+
 def reduce_counters(fetch_db, write_db, solves, calib_mib):
     """HBM bytes per mode solve of each kernel set, from two rocprofv3 --pmc
     databases (FETCH_SIZE, WRITE_SIZE; KiB per dispatch).  Each counter is
@@ -236,6 +267,15 @@ def reduce_counters(fetch_db, write_db, solves, calib_mib):
             "order by dispatch_id"))
         copies = [v for k, v in rows if "copyBuffer" in k][:3]
         factor = calib_mib * 1024.0 / (sum(copies) / len(copies))
+        log(f"{name}: the calibration copies read {copies} KiB: "
+            f"factor {factor:.4f}")
+        per = {}
+        for k, v in rows:
+            if "copyBuffer" not in k:
+                per[short_kernel_name(k)] = per.get(short_kernel_name(k), 0) + v
+        for k, v in per.items():
+            out.setdefault("per_kernel", {}).setdefault(k, {})[
+                name + "_MiB_per_solve"] = v * factor / 1024.0 / solves
         for ks, (prefix, _) in KERNEL_SETS.items():
             kib = sum(v for k, v in rows if prefix in k)
             d = out.setdefault(ks, {})
@@ -243,6 +283,12 @@ def reduce_counters(fetch_db, write_db, solves, calib_mib):
             d[name + "_factor"] = factor
     for ks, (_, files) in KERNEL_SETS.items():
         out[ks]["source_digest"] = source_digest(files)
+    per = out.pop("per_kernel", {})
+    log("| kernel | fetch MiB/solve | write MiB/solve |")
+    log("|---|---:|---:|")
+    for k in sorted(per, key=lambda k: -sum(per[k].values())):
+        log(f"| {k} | {per[k].get('fetch_MiB_per_solve', 0):.1f} | "
+            f"{per[k].get('write_MiB_per_solve', 0):.1f} |")
     return out
 
 
@@ -432,6 +478,9 @@ def bench_batch(a, w, dev, precision, leaf):
 
 def main():
     a = parse()
+    if a.kernel_stats:
+        print(kernel_stats(a.kernel_stats))
+        return
     if a.reduce_counters:
         fdb, wdb, solves = a.reduce_counters
         print(json.dumps(reduce_counters(fdb, wdb, float(solves),
