@@ -313,8 +313,13 @@ def build_inputs(a, w, dev):
     if a.workload in DEVICE_GENERATED:
         dims, idx_d, val_d = tg.make_tensor_device(a.workload, dev, log=log)
         base = 2210_5105 * 16 + int(w["tag"])
-        U0 = tg.init_factors_device(base + 11, dims, w["R"], dev) \
-            if "R" in w else None
+        if "R" not in w:
+            U0 = None
+        elif w.get("init") == "slice_scaled":
+            U0 = tg.init_factors_slice_scaled_device(base + 11, dims, w["R"],
+                                                     idx_d)
+        else:
+            U0 = tg.init_factors_device(base + 11, dims, w["R"], dev)
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     else:
@@ -567,6 +572,7 @@ def main():
     phases = {k: dict(ms_total=v[0], launches=v[1]) for k, v in ph.items()}
     roof = None
     mttkrp = None
+    sts_draw = None
 
     def per_launch(k):  # from the timed sweeps when they timed phase k
         src = ph_timed if ph_timed.get(k, (0, 0))[1] else ph
@@ -581,6 +587,14 @@ def main():
                       nnz_extracted_per_solve=cnt["nnz"] / solves,
                       distinct_columns_per_solve=cnt["unique"] / solves,
                       rows_out_per_solve=cnt["rows"] / solves)
+        if sampler == "sts" and ph.get("sample", (0, 0))[1]:
+            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaf)
+                          for j in range(N)])
+            ms_s = per_launch("sample")
+            ach = fl / (ms_s * 1e-3) / 1e12
+            sts_draw = dict(flops_per_launch=fl, ms_per_launch=ms_s,
+                            achieved_TFs=ach, frac_of_fp64_peak=ach /
+                            FP64_PEAK_TFS)
         dom = max(ph, key=lambda k: ph[k][0])
         ms_dom = per_launch(dom)
         if dom == "sample" and sampler == "sts":
@@ -624,7 +638,7 @@ def main():
                    "autotuned": tuned},
         "fit": fit, "init_s": t_init,
         "compare": compare,
-        "sampled_mttkrp": mttkrp, "phases": phases,
+        "sampled_mttkrp": mttkrp, "sts_draw": sts_draw, "phases": phases,
         "phases_sweeps": extra,
         "roofline": roof, "cpu_baseline": cpu,
     }

@@ -108,10 +108,11 @@ typedef enum {
   CP_REFINE_ON = 1,    /* X = M G^+ + (M - (M G^+) G) G^+, all FP64: removes
                           the solve's own rounding (three R x R products
                           per row instead of one)                          */
-  CP_REFINE_OFF = 2    /* X = M G^+ in FP64.  With FP32 factors M carries
-                          the FP32 MTTKRP's rounding, which the condition
-                          of G amplifies far above the FP64 rounding the
-                          refinement removes                               */
+  CP_REFINE_OFF = 2    /* X = M G^+ alone: FP64 MFMA in CP_FP64; in the
+                          FP32 forms FP32 MFMA (G^+ rounded to FP32, FP32
+                          accumulation, X stored FP64), whose rounding is
+                          of the order of what M already carries from the
+                          FP32 MTTKRP                                      */
 } cp_solve_refine;
 
 /*

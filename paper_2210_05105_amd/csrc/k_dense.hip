@@ -721,9 +721,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
 // ---------------------------------------------------------------------------
 // Row solve: X[i] = m G^+ + (m - (m G^+) G) G^+  (FP64), column sums of X^2.
 // REFINE = false drops the refinement term: X[i] = m G^+, a third of the
-// MFMA work (the default for FP32 factors, whose M comes from an FP32
-// MTTKRP: its rounding, amplified by the condition of G, bounds the
-// accuracy of X far above the FP64 rounding the refinement removes).
+// MFMA work.  (FP32 factors without refinement take k_solve_f32 below.)
 // One wave per 16-row tile of M, on FP64 MFMA in transposed form:
 // X^T = (G^+)^T M^T.  With A = (G^+)^T (or G^T) and B = M^T, the accumulator
 // of tile t holds X[row0 + l % 16][16 t + l / 16 + 4 v] in lane l, element v,
@@ -958,6 +956,114 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
   }
 }
 
+// Row solve of the FP32 forms without refinement: X^T = (G^+)^T M^T on
+// v_mfma_f32_16x16x4f32 (G^+ rounded to FP32 once, staged in LDS; M is
+// FP32 already; FP32 accumulation over the R terms of an entry), written as
+// FP64, column sums of X^2 in FP64.  Twice the FP32 MFMA rate of the FP64
+// MFMA, and a relative error of the order of M's own FP32 rounding.  The D
+// layout puts X[row0 + l % 16][16 t + 4 (l / 16) + v] in lane l, element v:
+// four consecutive columns of one row per lane.
+template <int NT>
+__global__ void __launch_bounds__(SV_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_solve_f32(const float *M, int64_t I, int R, const double *Gp, double *X,
+            double *partial, int64_t *rows_out) {
+  constexpr int KS = 4 * NT;
+  constexpr int RP = 16 * NT;
+  constexpr int RS = RP + 4;  // LDS row stride (floats)
+  __shared__ float sG[RP * RS];
+  __shared__ double red[SV_THREADS / WAVE][MAXR];
+  const int l = lane_id(), w = threadIdx.x / WAVE;
+  for (int e = threadIdx.x; e < RP * RP; e += SV_THREADS) {
+    const int a = e / RP, b = e % RP;
+    sG[a * RS + b] = (a < R && b < R) ? (float)Gp[a * R + b] : 0.0f;
+  }
+  for (int c = l; c < MAXR; c += WAVE) red[w][c] = 0.0;
+  __syncthreads();
+  int nrows = 0;
+  const int64_t ntiles = (I + 15) / 16;
+  const int64_t tstep = (int64_t)gridDim.x * (SV_THREADS / WAVE);
+  float raw[KS];
+  auto load_tile = [&](int64_t tl) {
+    const int64_t rr = tl * 16 + (l % 16);
+    const float *mrow = M + (rr < I ? rr : I - 1) * R;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + l / 16;
+      raw[ks] = mrow[k < R ? k : R - 1];
+    }
+  };
+  int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
+  if (tile < ntiles) load_tile(tile);
+  for (; tile < ntiles; tile += tstep) {
+    const int64_t row = tile * 16 + (l % 16);
+    float mf[KS];
+    bool nz = false;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = 4 * ks + l / 16;
+      mf[ks] = (row < I && k < R) ? raw[ks] : 0.0f;
+      nz |= (mf[ks] != 0.0f);
+    }
+    if (tile + tstep < ntiles) load_tile(tile + tstep);
+    const uint64_t b = __ballot(nz);
+    nrows += __popcll((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xffffull);
+    // the G^+ fragments are read from LDS in every tile (an opaque lane
+    // index keeps them from being hoisted out of the tile loop into
+    // registers), one output tile at a time
+    asm volatile("" ::: "memory");
+    const int lz = opaque_lane();
+    const float *gA = sG + (lz / 16) * RS + (lz % 16);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      float4_t acc = float4_t{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
+            gA[4 * ks * RS + 16 * t], mf[ks], acc, 0, 0, 0);
+      const int c0 = 16 * t + 4 * (l / 16);
+      double x[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[v] = (double)acc[v];
+      if (row < I) {
+        double *dst = X + row * R + c0;
+        if (c0 + 3 < R && (R & 1) == 0) {
+          reinterpret_cast<double2 *>(dst)[0] = make_double2(x[0], x[1]);
+          reinterpret_cast<double2 *>(dst)[1] = make_double2(x[2], x[3]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (c0 + v < R) dst[v] = x[v];
+        }
+      }
+      // this tile's column sums of X^2: the 16 row lanes (shuffle tree),
+      // added to the wave's row of `red` in tile order
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double q = row < I ? x[v] * x[v] : 0.0;
+        for (int o = 1; o < 16; o <<= 1) q += __shfl_xor(q, o, WAVE);
+        if ((l % 16) == 0 && c0 + v < R) red[w][c0 + v] += q;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (rows_out) {
+    __shared__ int cnt[SV_THREADS / WAVE];
+    if (l == 0) cnt[w] = nrows;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int n = 0;
+      for (int q = 0; q < SV_THREADS / WAVE; ++q) n += cnt[q];
+      if (n) atomicAdd((unsigned long long *)rows_out, (unsigned long long)n);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < R; c += SV_THREADS) {
+    double v = 0;
+    for (int q = 0; q < SV_THREADS / WAVE; ++q) v += red[q][c];
+    partial[(int64_t)blockIdx.x * R + c] = v;
+  }
+}
+
 template <typename T>
 __global__ void k_colsumsq(const T *X, int64_t I, int R, double *partial) {
   // block b sums rows b, b + grid, ... ; thread c owns column c
@@ -1160,9 +1266,15 @@ void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
                    const double *Gp, double *X, double *partial, int nblk,
                    int64_t *rows_out, hipStream_t s) {
   const dim3 g(nblk), b(SV_THREADS);
-#define CPR_SOLVE(NT)                                                      \
-  hipLaunchKernelGGL((k_solve<T, NT, RF>), g, b, 0, s, M, I, R, Gfull, Gp, \
-                     X, partial, rows_out)
+  constexpr bool F32 = std::is_same<T, float>::value && !RF;
+#define CPR_SOLVE(NT)                                                        \
+  if constexpr (F32)                                                         \
+    hipLaunchKernelGGL((k_solve_f32<NT>), g, b, 0, s,                        \
+                       reinterpret_cast<const float *>(M), I, R, Gp, X,      \
+                       partial, rows_out);                                   \
+  else                                                                       \
+    hipLaunchKernelGGL((k_solve<T, NT, RF>), g, b, 0, s, M, I, R, Gfull, Gp, \
+                       X, partial, rows_out)
   switch ((R + 15) / 16) {
     case 1: CPR_SOLVE(1); break;
     case 2: CPR_SOLVE(2); break;

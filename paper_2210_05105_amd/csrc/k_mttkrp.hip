@@ -1,19 +1,22 @@
 // Sketch application and the sampled MTTKRP (Section 2.2, Eq. 7, Section 4.3).
 //
-// 1. lookup: column key of each drawn Khatri-Rao row, binary search in the
-//    mode's sorted distinct column keys; the first draw of each column
-//    claims it with atomicMin.
+// 1. lookup: column key of each drawn Khatri-Rao row, probed in the mode's
+//    open-addressing hash of its distinct column keys; per block, the draws
+//    of one column are pre-merged in an LDS hash (smallest draw index) and
+//    the block's first draw of each column is published with one atomicMin.
 // 2. merge: draws of the same column are merged (count c, weight
 //    w = c / (J p)); distinct columns u are compacted in first-draw order,
 //    the lengths of their nonzero ranges are prefix-summed, and
 //    hc[u] = w h[first draw] holds the column's weighted Khatri-Rao row.
 // 3. MTTKRP by blocks of B output rows (the paper's transposition of the
 //    extracted nonzeros to row order, Section 4.3, as one counting-sort
-//    pass): count the extracted nonzeros per row block, scatter compact
-//    records (u, row % B, v) grouped by block, then accumulate each block's
-//    records into its B rows of M.  Positions of one column are row-sorted,
-//    so a wave's consecutive positions form a few runs of one block and
-//    count/scatter take one atomic per run.
+//    pass): each block's records sit in a fixed region (sized once from the
+//    mode's row histogram); the scatter places compact records
+//    (u, row % B, v) in their block's region, one atomic per run of one
+//    block in a wave (positions of one column are row-sorted), then each
+//    block's records are accumulated into its B rows of M.  Record order
+//    inside a region follows the atomics, so FP32 sums are not bitwise
+//    reproducible run to run (their order of addition varies).
 #include "internal.h"
 
 #include <algorithm>
