@@ -335,6 +335,10 @@ def build_inputs(a, w, dev):
     return dims, N, idx_d, val_d, U0
 
 
+def dev_of(t):
+    return t.device
+
+
 def run_form(a, w, dims, N, idx_d, val_d, U0, uni, precision, leaf, timed,
              bucket_rows=0):
     """Build a context in one precision form and run warmup + timed sweeps.
@@ -351,7 +355,9 @@ def run_form(a, w, dims, N, idx_d, val_d, U0, uni, precision, leaf, timed,
     torch.cuda.synchronize()
     t_init = time.time() - t0
     torch.cuda.empty_cache()
-    log(f"[{precision}] cp_init (per-mode index build) {t_init:.2f}s")
+    free_b, total_b = torch.cuda.mem_get_info(dev_of(idx_d))
+    log(f"[{precision}] cp_init (per-mode index build) {t_init:.2f}s; device "
+        f"memory free {free_b / 2**30:.1f} of {total_b / 2**30:.1f} GiB")
     for k in range(N):
         ctx.set_factor(k, U0[k])
     if a.warmup:
@@ -515,6 +521,14 @@ def main():
     if a.workload == "batch3":
         return bench_batch(a, w, dev, precision, leaf)
     R, J, sampler = w["R"], w["J"], w["sampler"]
+    if a.autotune and a.workload in DEVICE_GENERATED and \
+            w["nnz"] >= 1_000_000_000:
+        print("bench.py --autotune is not available for the billion-nonzero "
+              "workload: its candidate contexts (leaf size 16: a 53 GB tree; "
+              "256-row buckets: 28 GB of split-bucket blocks) come within a "
+              "few GB of the HBM capacity, and a run there faulted the GPU; "
+              "see DESIGN.md (autotuner)", file=sys.stderr)
+        sys.exit(2)
     dims, N, idx_d, val_d, U0 = build_inputs(a, w, dev)
     nnz = int(idx_d.shape[0])
     tuned = None

@@ -11,7 +11,8 @@ Parameters are chosen by timing whole ALS sweeps on the caller's own tensor
 - ``nstreams``: for batched restarts, concurrent streams in {1, 2, 4, 8}.
 
 The search is coordinate-wise (F first with the default B, then B with the
-best F; streams last for batches).  Results are cached in a JSON file
+best F; streams last for batches).  A candidate the library refuses for
+lack of device memory (CP_ENOMEM) is skipped.  Results are cached in a JSON file
 (``CPR_TUNE_CACHE`` or ``~/.cache/cpr_autotune.json``) keyed by the device
 name, tensor dimensions and nonzero count, rank(s), sampler, precision and
 J.  Only the public API of the library is used; nothing here computes any
@@ -99,6 +100,20 @@ def _time_context(idx, val, dims, R, sampler, precision, J, leaf, buckets,
         torch.cuda.empty_cache()
 
 
+def _try(fn, log):
+    """A candidate's time, or None if the library refuses it for lack of
+    device memory (CP_ENOMEM: every context keeps a reserve free)."""
+    from .binding import CprError
+    try:
+        return fn()
+    except CprError as e:
+        if e.name != "CP_ENOMEM":
+            raise
+        if log:
+            log(f"autotune: candidate skipped ({e})")
+        return None
+
+
 def tune_context(idx, val, dims, R, sampler, precision, J, sweeps=2,
                  seed=7, use_cache=True, log=None):
     """Best (sts_leaf, bucket_rows) for one decomposition of this tensor.
@@ -117,18 +132,24 @@ def tune_context(idx, val, dims, R, sampler, precision, J, sweeps=2,
     leaves = LEAVES if sampler == "sts" else (0,)
     best_leaf, best = None, None
     for F in leaves:
-        ms = _time_context(idx, val, dims, R, sampler, precision, J, F, 0,
-                           sweeps, seed)
+        ms = _try(lambda: _time_context(idx, val, dims, R, sampler, precision,
+                                        J, F, 0, sweeps, seed), log)
         tried[f"leaf={F},buckets=auto"] = ms
+        if ms is None:
+            continue
         if log:
             log(f"autotune: leaf {F} -> {ms:.3f} ms/sweep")
         if best is None or ms < best:
             best_leaf, best = F, ms
     best_b = 0
+    if best is None:
+        raise RuntimeError("autotune: no candidate fits this device")
     for B in BUCKETS:
-        ms = _time_context(idx, val, dims, R, sampler, precision, J,
-                           best_leaf, B, sweeps, seed)
+        ms = _try(lambda: _time_context(idx, val, dims, R, sampler, precision,
+                                        J, best_leaf, B, sweeps, seed), log)
         tried[f"leaf={best_leaf},buckets={B}"] = ms
+        if ms is None:
+            continue
         if log:
             log(f"autotune: buckets {B} -> {ms:.3f} ms/sweep")
         if ms < best:
@@ -166,24 +187,30 @@ def tune_batch(idx, val, dims, ranks, sampler, precision, J, sweeps=2,
         for ns in STREAMS:
             if ns > len(ranks):
                 continue
-            bt = Batch(idx, val, dims, ranks, sampler, precision, J=J,
-                       sts_leaf=F, nstreams=ns)
-            try:
-                for b, R in enumerate(ranks):
-                    for k, d in enumerate(dims):
-                        bt.set_factor(b, k, torch.randn(
-                            (d, R), dtype=torch.float64, device=dev,
-                            generator=g))
-                ms = _time_sweeps(lambda n: [bt.sweep(uni) for _ in range(n)],
-                                  sweeps)
-            finally:
-                bt.close()
-                torch.cuda.empty_cache()
+            def one():
+                bt = Batch(idx, val, dims, ranks, sampler, precision, J=J,
+                           sts_leaf=F, nstreams=ns)
+                try:
+                    for b, R in enumerate(ranks):
+                        for k, d in enumerate(dims):
+                            bt.set_factor(b, k, torch.randn(
+                                (d, R), dtype=torch.float64, device=dev,
+                                generator=g))
+                    return _time_sweeps(
+                        lambda n: [bt.sweep(uni) for _ in range(n)], sweeps)
+                finally:
+                    bt.close()
+                    torch.cuda.empty_cache()
+            ms = _try(one, log)
             tried[f"leaf={F},streams={ns}"] = ms
+            if ms is None:
+                continue
             if log:
                 log(f"autotune: batch leaf {F} streams {ns} -> {ms:.3f} ms")
             if best is None or ms < best:
                 best, choice = ms, (F, ns)
+    if choice is None:
+        raise RuntimeError("autotune: no candidate fits this device")
     res = dict(sts_leaf=choice[0], nstreams=choice[1], ms_per_sweep=best,
                tried=tried, at=time.strftime("%Y-%m-%d %H:%M:%S"))
     if use_cache:

@@ -60,9 +60,13 @@ def declared_symbols(header=HEADER):
     return sorted(set(re.findall(r"\b(cp_[a-z_0-9]+)\s*\(", text)))
 
 
-def load_library(path=LIB_PATH):
-    """Load libcpr.so (built by paper_2210_05105_amd.build); raise if absent."""
+def load_library(path=None):
+    """Load libcpr.so (built by paper_2210_05105_amd.build; another build
+    of it if the CPR_LIBRARY environment variable names one); raise if
+    absent."""
     global _lib
+    if path is None:
+        path = os.environ.get("CPR_LIBRARY") or LIB_PATH
     if _lib is not None:
         return _lib
     if not os.path.exists(path):

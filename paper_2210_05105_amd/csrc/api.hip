@@ -96,11 +96,24 @@ void hip_ok(hipError_t e, const char *what) {
     throw Fail{CP_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
+// device memory every context leaves free (runtime queues and scratch,
+// the caller's own tensors)
+constexpr size_t kMemReserve = size_t(4) << 30;
+
 template <typename P>
 void dalloc(cp_ctx *c, P **p, size_t bytes) {
   void *q = nullptr;
   if (hipMalloc(&q, std::max<size_t>(bytes, 16)) != hipSuccess)
     throw Fail{CP_ENOMEM, "device allocation failed"};
+  // keep a reserve of device memory free for the runtime and the caller:
+  // a context that would leave less is refused rather than run at capacity
+  size_t fr = 0, tot = 0;
+  if (bytes >= (size_t(1) << 26) && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+      fr < kMemReserve) {
+    (void)hipFree(q);
+    throw Fail{CP_ENOMEM, "device memory would fall below the reserve of " +
+                              std::to_string(kMemReserve >> 30) + " GiB"};
+  }
   c->allocs.push_back(q);
   *p = static_cast<P *>(q);
 }
@@ -470,6 +483,11 @@ void init_index(cp_ctx *c, const cp_tensor *t) {
     if (!e.empty())
       throw Fail{e.find("63 bits") != std::string::npos ? CP_EUNSUPPORTED
                                                          : CP_ENOMEM, e};
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < kMemReserve)
+      throw Fail{CP_ENOMEM, "the mode indices leave less than the reserve of " +
+                                std::to_string(kMemReserve >> 30) +
+                                " GiB of device memory"};
     read_errors(c);
     c->max_cols = std::max(c->max_cols, c->ix[k].n_cols);
   }
@@ -602,6 +620,11 @@ void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
   if (c->sampler != CP_SAMPLER_EXACT) {
     // records sit in each bucket's fixed region: nnz of them at most
     dalloc(c, &c->w.rec, (size_t)c->nnz * bucket_record_bytes((int)ts));
+    if (two_pass_placement(nbk)) {  // some mode places in two passes
+      dalloc(c, &c->w.rec1, (size_t)c->nnz * super_record_bytes((int)ts));
+      dalloc(c, &c->w.sb, (size_t)super_work_entries() * 8);
+      zero_fill<int64_t>(c->w.sb, super_work_entries(), c->s);
+    }
   }
   dalloc(c, &c->w.tile_first, (size_t)bucket_tiles(cap) * 8);
   dalloc(c, &c->w.item_bk, (size_t)bucket_max_items(cap, nbk) * 4);

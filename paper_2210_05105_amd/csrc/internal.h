@@ -220,6 +220,9 @@ struct SampleWork {
                      // fixed offsets 0, bk_max + 1, 2 (bk_max + 1)
   int64_t bk_max;    // buckets of the largest mode
   void *rec;         // nnz records: extracted nonzeros in bucket regions
+  void *rec1;        // nnz first-pass records (two-pass placement) or null
+  int64_t *sb;       // super_work_entries(): super-bucket fill cursors (zero
+                     // between calls), their copy, chunk starts
   int64_t rec_cap;
   void *part;        // per-slice blocks of split buckets (B x R each)
 };
@@ -227,6 +230,12 @@ int bucket_shift(int R, int tsize);
 int64_t bucket_max_items(int64_t rec_cap, int64_t nbk);
 int64_t bucket_tiles(int64_t rec_cap);
 size_t bucket_record_bytes(int tsize);
+// two-pass placement of the sampled MTTKRP's records (super buckets, then
+// buckets) for modes with many buckets: first-pass record size, whether a
+// mode of nbk buckets takes it, and the entries of SampleWork::sb
+size_t super_record_bytes(int tsize);
+bool two_pass_placement(int64_t nbk);
+int64_t super_work_entries();
 template <typename T>
 void set_sample_rows(const ModeList &ml, int64_t J, int R, const int32_t *sidx,
                      const double *prob, T *h, uint32_t *err, hipStream_t s);

@@ -444,19 +444,33 @@ struct BkRec {
   T coef;
 };
 
+// The same nonzero in the first of two placement passes (grouped by super
+// bucket: 2^sh consecutive buckets), with its whole row.
 template <typename T>
+struct BkRec1 {
+  uint32_t u;
+  int32_t row;
+  T coef;
+};
+
+// SUPER: the first of two placement passes.  Groups are then super buckets
+// (nbk of them, <= SB_MAX: 2^sh buckets each, so that a 4096-position tile
+// puts runs of about 16 records in each group it touches), whose regions
+// are the unions of their buckets' regions; records are BkRec1.
+template <typename T, bool SUPER>
 __global__ void __launch_bounds__(MT_THREADS)
 k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
              const int64_t *tile_first,
              const int64_t *uq_base, const int32_t *row, const T *val, int nbk,
-             int bb, const int64_t *bk_start, int64_t *bk_fill,
-             BkRec<T> *rec) {
+             int bb, int sh, const int64_t *bk_start, int64_t *bk_fill,
+             void *rec_out) {
   extern __shared__ int64_t sc_lds[];  // base, cnt: nbk each (<= BK_LDS_MAX)
   int64_t *base = sc_lds;  // record position of the tile's first record
   uint32_t *cnt = reinterpret_cast<uint32_t *>(sc_lds + nbk);
   __shared__ int32_t cst[BK_TILE + 1];
   const int64_t nz = counts[1];
-  const bool use_lds = nbk <= BK_LDS_MAX;
+  const bool use_lds = SUPER || nbk <= BK_LDS_MAX;
+  const int gshift = SUPER ? bb + sh : bb;  // row -> group
   const int64_t ntile = (nz + BK_TILE - 1) / BK_TILE;
   const uint32_t bmask = (1u << bb) - 1;
   const int l = lane_id();
@@ -471,22 +485,22 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
     __syncthreads();
     int64_t p[BK_ITEMS];
     int my_bk[BK_ITEMS];
-    uint32_t my_key[BK_ITEMS];
+    uint32_t my_u[BK_ITEMS];
+    int32_t my_rw[BK_ITEMS];
     T my_cf[BK_ITEMS];
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
       const int pos = i * MT_THREADS + threadIdx.x;
       const int64_t e = e0 + pos < e1 ? e0 + pos : e1 - 1;
       const int64_t u = ub + find_local(cst, ncol, (int)(e - e0));
-      my_key[i] = (uint32_t)u << 8;
+      my_u[i] = (uint32_t)u;
       p[i] = uq_base[u] + e;
     }
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
-      const int rw = row[p[i]];
-      my_key[i] |= (uint32_t)rw & bmask;
+      my_rw[i] = row[p[i]];
       my_cf[i] = val[p[i]];
-      my_bk[i] = rw >> bb;
+      my_bk[i] = my_rw[i] >> gshift;
     }
 #pragma unroll
     for (int i = 0; i < BK_ITEMS; ++i) {
@@ -502,7 +516,7 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
       for (int b = threadIdx.x; b < nbk; b += MT_THREADS) {
         const uint32_t c = cnt[b];
         if (c)
-          base[b] = bk_start[b] +
+          base[b] = bk_start[SUPER ? (int64_t)b << sh : b] +
                     (int64_t)atomicAdd((unsigned long long *)&bk_fill[b],
                                        (unsigned long long)c);
         cnt[b] = 0;
@@ -521,10 +535,130 @@ k_bk_scatter(const int64_t *counts, const int64_t *uq_off,
                             (unsigned long long *)&bk_fill[bk],
                             (unsigned long long)len);
       off = __shfl(off, lead, WAVE);
-      if (bk >= 0) rec[off + (l - lead)] = BkRec<T>{my_key[i], my_cf[i]};
+      if (bk >= 0) {
+        if constexpr (SUPER)
+          static_cast<BkRec1<T> *>(rec_out)[off + (l - lead)] =
+              BkRec1<T>{my_u[i], my_rw[i], my_cf[i]};
+        else
+          static_cast<BkRec<T> *>(rec_out)[off + (l - lead)] = BkRec<T>{
+              (my_u[i] << 8) | ((uint32_t)my_rw[i] & bmask), my_cf[i]};
+      }
     }
     __syncthreads();
   }
+}
+
+// Second placement pass: the records of each super bucket, in chunks of
+// DS_CHUNK, counted per bucket in LDS; one global atomic per (chunk,
+// bucket) reserves the chunk's run in the bucket's region, so runs of about
+// DS_CHUNK / 2^sh records are written together.  k_ds_plan first lists the
+// chunks (ds_start: exclusive prefix sums of the chunks per super bucket),
+// takes the fill counts of pass 1 (ds_fill) and clears them for the next
+// call.
+constexpr int SB_MAX = 256;      // super buckets at most
+constexpr int DS_THREADS = 512;
+constexpr int DS_ITEMS = 16;
+constexpr int DS_CHUNK = DS_THREADS * DS_ITEMS;
+constexpr int DS_LDS_MAX = 4096;  // buckets per super bucket at most
+
+__global__ void __launch_bounds__(SB_MAX)
+k_ds_plan(int64_t *sfill, int nsb, int64_t *ds_fill, int64_t *ds_start) {
+  __shared__ int64_t wsum[SB_MAX / WAVE];
+  const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
+  const int64_t f = t < nsb ? sfill[t] : 0;
+  const int64_t n = (f + DS_CHUNK - 1) / DS_CHUNK;
+  int64_t inc = n;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t y = __shfl_up(inc, o, WAVE);
+    if (l >= o) inc += y;
+  }
+  if (l == WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  int64_t off = 0;
+  for (int i = 0; i < w; ++i) off += wsum[i];
+  if (t < nsb) {
+    ds_fill[t] = f;
+    ds_start[t] = off + inc - n;
+    sfill[t] = 0;
+  }
+  if (t == SB_MAX - 1) ds_start[nsb] = off + inc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(DS_THREADS)
+k_bk_distribute(const int64_t *ds_start, const int64_t *ds_fill, int nsb,
+                int sh, int nbk, int bb, const int64_t *bk_start,
+                int64_t *bk_fill, const BkRec1<T> *rec1, BkRec<T> *rec) {
+  __shared__ int64_t base[DS_LDS_MAX];
+  __shared__ uint32_t cnt[DS_LDS_MAX];
+  const int l = lane_id();
+  const uint32_t bmask = (1u << bb) - 1;
+  const int64_t nitems = ds_start[nsb];
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    int lo = 0, hi = nsb;  // last super bucket with ds_start <= it
+    while (hi - lo > 1) {
+      const int m = (lo + hi) >> 1;
+      if (ds_start[m] <= it) lo = m; else hi = m;
+    }
+    const int sb = lo;
+    const int64_t b0 = (int64_t)sb << sh;
+    const int nb = (int)(nbk - b0 < (1 << sh) ? nbk - b0 : (1 << sh));
+    const int64_t reg = bk_start[b0];
+    const int64_t r0 = reg + (it - ds_start[sb]) * DS_CHUNK;
+    const int64_t r1 = r0 + DS_CHUNK < reg + ds_fill[sb] ? r0 + DS_CHUNK
+                                                          : reg + ds_fill[sb];
+    for (int b = threadIdx.x; b < nb; b += DS_THREADS) cnt[b] = 0;
+    __syncthreads();
+    BkRec1<T> my[DS_ITEMS];
+    int lb[DS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < DS_ITEMS; ++i) {
+      const int64_t r = r0 + i * DS_THREADS + threadIdx.x;
+      my[i] = rec1[r < r1 ? r : r1 - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < DS_ITEMS; ++i) {
+      const bool valid = r0 + i * DS_THREADS + threadIdx.x < r1;
+      lb[i] = valid ? (int)((my[i].row >> bb) - b0) : -1;
+      int lead, len;
+      bucket_runs(lb[i], valid, lead, len);
+      if (valid && lead == l) atomicAdd(&cnt[lb[i]], (uint32_t)len);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += DS_THREADS) {
+      const uint32_t c = cnt[b];
+      if (c)
+        base[b] = bk_start[b0 + b] +
+                  (int64_t)atomicAdd((unsigned long long *)&bk_fill[b0 + b],
+                                     (unsigned long long)c);
+      cnt[b] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < DS_ITEMS; ++i) {
+      int lead, len;
+      bucket_runs(lb[i], lb[i] >= 0, lead, len);
+      int64_t off = 0;
+      if (lb[i] >= 0 && lead == l)
+        off = base[lb[i]] + (int64_t)atomicAdd(&cnt[lb[i]], (uint32_t)len);
+      off = __shfl(off, lead, WAVE);
+      if (lb[i] >= 0)
+        rec[off + (l - lead)] = BkRec<T>{
+            (my[i].u << 8) | ((uint32_t)my[i].row & bmask), my[i].coef};
+    }
+    __syncthreads();
+  }
+}
+
+// Super-bucket shift of a mode with nbk buckets for the two-pass placement
+// (-1: one pass).  One pass when the buckets are few enough that a tile's
+// runs are already long, or too many for one super bucket's LDS counts.
+int super_shift(int64_t nbk) {
+  if (nbk <= SB_MAX) return -1;
+  int sh = 0;
+  while (((nbk + (int64_t(1) << sh) - 1) >> sh) > SB_MAX) ++sh;
+  return (1 << sh) <= DS_LDS_MAX ? sh : -1;
 }
 
 // Accumulation without floating-point LDS atomics (they run at a small
@@ -898,13 +1032,31 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   int64_t *bk_fill = w.bk, *bk_end = w.bk + (w.bk_max + 1),
           *item_start = w.bk + 2 * (w.bk_max + 1);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
-  const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
-  hipLaunchKernelGGL((k_bk_scatter<T>), gt, b, 3 * hl, s, w.counts, w.uq_off,
-                     w.tile_first, w.uq_base, row, val, nbk, bb, bk_start,
-                     bk_fill, rec);
-  CPR_LAUNCH_CHECK();
+  const int sh = w.rec1 ? super_shift(nbk) : -1;
+  if (sh >= 0) {  // two passes: super buckets, then buckets
+    const int nsb = (int)((nbk + (1 << sh) - 1) >> sh);
+    int64_t *sfill = w.sb, *ds_fill = w.sb + (SB_MAX + 1),
+            *ds_start = w.sb + 2 * (SB_MAX + 1);
+    hipLaunchKernelGGL((k_bk_scatter<T, true>), gt, b, 3 * (size_t)nsb * 4, s,
+                       w.counts, w.uq_off, w.tile_first, w.uq_base, row, val,
+                       nsb, bb, sh, bk_start, sfill, w.rec1);
+    CPR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ds_plan, dim3(1), dim3(SB_MAX), 0, s, sfill, nsb,
+                       ds_fill, ds_start);
+    CPR_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_bk_distribute<T>), gt, dim3(DS_THREADS), 0, s,
+                       ds_start, ds_fill, nsb, sh, nbk, bb, bk_start, bk_fill,
+                       static_cast<const BkRec1<T> *>(w.rec1), rec);
+    CPR_LAUNCH_CHECK();
+  } else {
+    const size_t hl = nbk <= BK_LDS_MAX ? (size_t)nbk * 4 : 0;
+    hipLaunchKernelGGL((k_bk_scatter<T, false>), gt, b, 3 * hl, s, w.counts,
+                       w.uq_off, w.tile_first, w.uq_base, row, val, nbk, bb, 0,
+                       bk_start, bk_fill, static_cast<void *>(rec));
+    CPR_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_bk_plan, dim3(1), dim3(PL_THREADS), 0, s, bk_start,
                      bk_fill, nbk, bk_end, item_start, w.item_bk);
   CPR_LAUNCH_CHECK();
@@ -960,6 +1112,14 @@ int64_t bucket_max_items(int64_t rec_cap, int64_t nbk) {
 size_t bucket_record_bytes(int tsize) {
   return tsize == 4 ? sizeof(BkRec<float>) : sizeof(BkRec<double>);
 }
+
+size_t super_record_bytes(int tsize) {
+  return tsize == 4 ? sizeof(BkRec1<float>) : sizeof(BkRec1<double>);
+}
+
+bool two_pass_placement(int64_t nbk) { return super_shift(nbk) >= 0; }
+
+int64_t super_work_entries() { return 3 * (SB_MAX + 1); }
 template void sampled_mttkrp<float>(const SampleWork &, int64_t,
                                     const int64_t *, const int32_t *,
                                     const float *, const int64_t *, int, int,

@@ -394,20 +394,20 @@ def values_device(seed, n, kind, device):
 
 
 def init_factors_device(seed, dims, R, device, dtype=None):
-    """Unit-variance Gaussian initial factors (Alg. 1, first line), FP64
-    tensors holding FP32-representable values (so that every precision form
-    starts from identical factors)."""
+    """Unit-variance Gaussian initial factors (Alg. 1, first line) as FP32
+    tensors (so that every precision form starts from identical factors;
+    the library takes them as FP64, converted one mode at a time)."""
     torch = _torch()
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     return [torch.randn((d, R), dtype=torch.float32, device=device,
-                        generator=g).to(torch.float64) for d in dims]
+                        generator=g) for d in dims]
 
 
 def init_factors_slice_scaled_device(seed, dims, R, idx):
     """Gaussian initial factors whose row i of mode k is scaled by
     sqrt(number of nonzeros in slice i of mode k) (rows of empty slices are
-    zero), FP64 holding FP32-representable values.  A data-aware start for
+    zero), FP32.  A data-aware start for
     tensors whose unfoldings have far more columns than nonzeros (the 4-way
     workload: about 1e14 columns per unfolding for 2e8 nonzeros): from
     unscaled Gaussian rows the leverage laws are nearly uniform, the draws
@@ -417,7 +417,7 @@ def init_factors_slice_scaled_device(seed, dims, R, idx):
     U = init_factors_device(seed, dims, R, idx.device)
     for k, d in enumerate(dims):
         cnt = torch.bincount(idx[:, k].long(), minlength=d).to(torch.float32)
-        U[k] = (U[k].to(torch.float32) * cnt.sqrt()[:, None]).to(torch.float64)
+        U[k] = U[k] * cnt.sqrt()[:, None]
     return U
 
 

@@ -11,12 +11,14 @@ from tests.helpers import (compare_arls_indices, compare_sts_indices,
                            to_np)
 
 
-def make_ctx(dev, T, R, sampler, precision, J, leaf=0, refine=None):
+def make_ctx(dev, T, R, sampler, precision, J, leaf=0, refine=None,
+             bucket_rows=0):
     from paper_2210_05105_amd import Context
     vdt = np.float64 if precision == "fp64" else np.float32
     return Context(torch.from_numpy(np.ascontiguousarray(T.idx)).to(dev),
                    torch.from_numpy(T.val.astype(vdt)).to(dev), T.dims, R,
-                   sampler, precision, max_J=J, sts_leaf=leaf, refine=refine)
+                   sampler, precision, max_J=J, sts_leaf=leaf, refine=refine,
+                   bucket_rows=bucket_rows)
 
 
 def init_ctx(ctx, dims, R, seed, fp32=False):

@@ -163,6 +163,24 @@ def test_mode_order_with_growing_bucket_count(dev):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_two_pass_record_placement(dev, prec, tol):
+    """Modes with more than 256 output-row buckets place the sampled
+    MTTKRP's records in two passes (super buckets of 2^sh buckets, then
+    buckets): 16-row buckets give mode 0 1,250 buckets (two passes, 8 per
+    super bucket), mode 1 375 (two passes, 2 per super bucket) and mode 2 19
+    (one pass).  Power-law rows put long runs in a few buckets.  The order
+    0, 2, 1, 0 checks that the super-bucket cursors are left clear."""
+    T = tg.zipf_tensor(44, (20000, 6000, 300), 120_000, s=1.1)
+    R, J = 16, 6000
+    ctx = make_ctx(dev, T, R, "arls", prec, J, bucket_rows=16)
+    _, runi = init_ctx(ctx, T.dims, R, 21, fp32=(prec != "fp64"))
+    for j in (0, 2, 1, 0):
+        u = tg.uniform_block(runi, J, 3)
+        check_mode_solve(ctx, T, j, u, J, "arls", tol)
+    ctx.close()
+
+
 def test_arls_fp32_4way_mode_solves(dev):
     T = tg.zipf_tensor(43, (2000, 1000, 400, 20), 150_000, s=1.2)
     R, J = 24, 3000
