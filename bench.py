@@ -236,8 +236,10 @@ def kernel_stats(db, top=60):
     import sqlite3
     from collections import defaultdict
     cur = sqlite3.connect(db).cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    name = "kernel_name" if "kernel_name" in cols else "name"
     tot, cnt = defaultdict(float), defaultdict(int)
-    for n, b, e in cur.execute("select kernel_name, start, end from kernels"):
+    for n, b, e in cur.execute(f"select {name}, start, end from kernels"):
         k = short_kernel_name(n)
         tot[k] += e - b
         cnt[k] += 1

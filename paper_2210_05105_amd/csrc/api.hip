@@ -602,7 +602,8 @@ void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
   const int64_t nbk = (c->max_I + (1 << bb_min) - 1) >> bb_min;
   dalloc(c, &c->w.scan_tmp, std::max(scan_temp_bytes(J),
                                      scan_temp_bytes(nbk + 1)));
-  dalloc(c, &c->w.bk, (size_t)5 * (nbk + 1) * 8);
+  dalloc(c, &c->w.bk,
+         (size_t)std::max<int64_t>(bucket_work_entries(nbk), nbk + 1) * 8);
   c->w.bk_max = nbk;
   // record capacity: at most J distinct columns are extracted, so the J
   // longest columns of a mode bound the extracted nonzeros of any solve
@@ -692,7 +693,10 @@ void select_bucket_regions(cp_ctx *c, cp_ctx *own) {
   c->bb = bb;
   if (c->sampler != CP_SAMPLER_EXACT)
     ensure_bucket_regions(own, bb, c->w.bk, c->w.scan_tmp);
-  zero_fill<int64_t>(c->w.bk, (size_t)5 * (c->w.bk_max + 1), c->s);
+  zero_fill<int64_t>(c->w.bk,
+                     (size_t)std::max<int64_t>(bucket_work_entries(c->w.bk_max),
+                                               c->w.bk_max + 1),
+                     c->s);
   for (int k = 0; k < c->N; ++k) c->ix[k].bk_start = own->bk_start_bb[bb][k];
 }
 

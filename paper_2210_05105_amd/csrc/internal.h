@@ -216,8 +216,9 @@ struct SampleWork {
   int64_t *stats;    // cumulative: solves, distinct columns, nonzeros, rows
   int64_t *scratch;  // 4 J: first-draw flags, lengths, per-block totals
   void *scan_tmp;    // scan_temp_bytes(max(J, buckets + 1))
-  int64_t *bk;       // 5 (bk_max + 1): fill cursors, ends, slice starts at
-                     // fixed offsets 0, bk_max + 1, 2 (bk_max + 1)
+  int64_t *bk;       // bucket_work_entries(bk_max): fill cursors (zero
+                     // between calls), ends, slice starts, split buckets,
+                     // plan totals
   int64_t bk_max;    // buckets of the largest mode
   void *rec;         // nnz records: extracted nonzeros in bucket regions
   void *rec1;        // nnz first-pass records (two-pass placement) or null
@@ -229,6 +230,8 @@ struct SampleWork {
 int bucket_shift(int R, int tsize);
 int64_t bucket_max_items(int64_t rec_cap, int64_t nbk);
 int64_t bucket_tiles(int64_t rec_cap);
+// int64 entries of SampleWork::bk for a workspace of at most bk_max buckets
+int64_t bucket_work_entries(int64_t bk_max);
 size_t bucket_record_bytes(int tsize);
 // two-pass placement of the sampled MTTKRP's records (super buckets, then
 // buckets) for modes with many buckets: first-pass record size, whether a

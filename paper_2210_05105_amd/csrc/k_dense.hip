@@ -449,6 +449,78 @@ __device__ bool chol_inverse(double *A, int R, double tol, double *W,
   return true;
 }
 
+// As chol_inverse, for R > 64, where A alone fills the LDS: L^{-1} is kept
+// in the strict upper triangle of A, transposed (W[i][c] at A[c][i], i > c;
+// L stays in the lower triangle), with its diagonal in wd (R doubles of
+// LDS), so the substitution and the product W^T W read LDS only.  Thread c
+// forms column c of W in order of rows.
+__device__ bool chol_inverse_lds(double *A, int R, double tol, double *wd,
+                                 double *Gp, int *flag) {
+  const int t = threadIdx.x;
+  const int tr = t / 16, tc = t % 16;  // 16 x 16 thread grid of the update
+  if (t == 0) *flag = 1;
+  __syncthreads();
+  for (int k = 0; k < R; ++k) {
+    const double d = A[k * R + k];
+    if (!(d > tol)) {
+      if (t == 0) *flag = 0;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+    const double lkk = sqrt(d);
+    for (int i = k + 1 + t; i < R; i += PV_THREADS) A[i * R + k] /= lkk;
+    __syncthreads();
+    if (t == 0) A[k * R + k] = lkk;
+    // trailing update of the lower triangle
+    for (int i = k + 1 + tr; i < R; i += 16) {
+      const double aik = A[i * R + k];
+      for (int c = k + 1 + tc; c <= i; c += 16) A[i * R + c] -= aik * A[c * R + k];
+    }
+    __syncthreads();
+  }
+  // W = L^{-1}: W[c][c] = 1 / L[c][c];
+  // W[i][c] = -(sum_{k = c}^{i - 1} L[i][k] W[k][c]) / L[i][i], i > c
+  // (four partial sums in flight: the LDS loads pipeline)
+  for (int c = t; c < R; c += PV_THREADS) {
+    const double wcc = 1.0 / A[c * R + c];
+    wd[c] = wcc;
+    const double *wc = A + c * R;  // W[k][c] at wc[k], k > c
+    for (int i = c + 1; i < R; ++i) {
+      const double *li = A + i * R;
+      double s0 = li[c] * wcc, s1 = 0, s2 = 0, s3 = 0;
+      int k = c + 1;
+      for (; k + 3 < i; k += 4) {
+        s0 += li[k] * wc[k];
+        s1 += li[k + 1] * wc[k + 1];
+        s2 += li[k + 2] * wc[k + 2];
+        s3 += li[k + 3] * wc[k + 3];
+      }
+      for (; k < i; ++k) s0 += li[k] * wc[k];
+      A[c * R + i] = -((s0 + s1) + (s2 + s3)) / li[i];
+    }
+  }
+  __syncthreads();
+  // Gp = W^T W: Gp[a][b] = sum_{k >= max(a, b)} W[k][a] W[k][b]
+  for (int e = t; e < R * R; e += PV_THREADS) {
+    const int a = e / R, b = e % R;
+    const int k0 = a > b ? a : b;
+    const double wa = k0 == a ? wd[a] : A[a * R + k0];
+    const double wb = k0 == b ? wd[b] : A[b * R + k0];
+    const double *ra = A + a * R, *rb = A + b * R;
+    double s0 = wa * wb, s1 = 0, s2 = 0, s3 = 0;
+    int k = k0 + 1;
+    for (; k + 3 < R; k += 4) {
+      s0 += ra[k] * rb[k];
+      s1 += ra[k + 1] * rb[k + 1];
+      s2 += ra[k + 2] * rb[k + 2];
+      s3 += ra[k + 3] * rb[k + 3];
+    }
+    for (; k < R; ++k) s0 += ra[k] * rb[k];
+    Gp[e] = (s0 + s1) + (s2 + s3);
+  }
+  return true;
+}
+
 // Inverse of the symmetric A (LDS, R <= 32) by Gauss-Jordan elimination
 // without row exchanges, in one wave: lane c < R holds column c of A and
 // lane R + c column c of the identity, R values each in registers.  Step k
@@ -608,6 +680,7 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
   __shared__ double red[PV_THREADS / WAVE];
   __shared__ __align__(16) double gjcol[32];  // pivot column of the one-wave inverse
   __shared__ double rot[4 * (MAXR / 2 + 1)];
+  __shared__ double wdiag[MAXR];  // diagonal of L^{-1} (R > 64)
   __shared__ int flag;
   const int t = threadIdx.x;
   double tr = 0, dmax = 0;
@@ -662,8 +735,10 @@ k_hadamard_pinv(ModeList ml, int R, double *Gfull, double *Gp, double *ggt,
     __threadfence_block();
     __syncthreads();
     ok = flag != 0;
-  } else {
+  } else if (R <= 64) {
     ok = chol_inverse(A, R, tol, W, Gp, &flag);
+  } else {
+    ok = chol_inverse_lds(A, R, tol, wdiag, Gp, &flag);
   }
   if (!ok) {
     __syncthreads();

@@ -349,46 +349,112 @@ __device__ __forceinline__ void bucket_runs(int bk, bool valid, int &leader,
   len = nxt - l;
 }
 
-// Accumulation plan in one workgroup: bucket b's records occupy
-// [bk_start[b], bk_start[b] + bk_fill[b]) of its fixed region; bk_end is
-// that end, item_start the exclusive prefix sums of the slices per bucket
-// and item_bk[i] the bucket of slice i.  Every bucket gets at least one
-// slice (an empty one writes zero rows), so the accumulation writes every
-// row of M.  Thread t takes a contiguous run of buckets.
+// Accumulation plan: bucket b's records occupy [bk_start[b], bk_start[b] +
+// bk_fill[b]) of its fixed region; bk_end is that end, item_start the
+// exclusive prefix sums of the slices per bucket (nbk + 1 entries) and
+// item_bk[i] the bucket of slice i; split lists the buckets of more than
+// one slice (nsplit of them), for k_bk_combine.  Every bucket gets at least
+// one slice (an empty one writes zero rows), so the accumulation writes
+// every row of M.  Two launches over blocks of PL_THREADS consecutive
+// buckets (coalesced): per-block totals, then offsets (the sum of the
+// earlier blocks' totals) and the block's scans.
 constexpr int PL_THREADS = 1024;
-__global__ void __launch_bounds__(PL_THREADS)
-k_bk_plan(const int64_t *bk_start, int64_t *bk_fill, int nbk,
-          int64_t *bk_end, int64_t *item_start, int32_t *item_bk) {
-  __shared__ int64_t wb[PL_THREADS / WAVE];
-  const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
-  const int per = (nbk + 1 + PL_THREADS - 1) / PL_THREADS;
-  const int b0 = t * per, b1 = b0 + per < nbk + 1 ? b0 + per : nbk + 1;
-  auto slices = [&](int b) -> int64_t {
-    if (b >= nbk) return 0;
-    const int64_t n = bk_fill[b];
-    return n > BK_SLICE ? (n + BK_SLICE - 1) / BK_SLICE : 1;
-  };
-  int64_t sb = 0;
-  for (int b = b0; b < b1; ++b) sb += slices(b);
-  int64_t ib = sb;
+
+__device__ __forceinline__ int64_t plan_slices(const int64_t *bk_fill, int nbk,
+                                               int64_t b) {
+  if (b >= nbk) return 0;
+  const int64_t n = bk_fill[b];
+  return n > BK_SLICE ? (n + BK_SLICE - 1) / BK_SLICE : 1;
+}
+
+// block-wide exclusive scan of (a, c) per thread, totals in ta, tc
+__device__ __forceinline__ void plan_scan2(int64_t &a, int64_t &c, int64_t &ta,
+                                           int64_t &tc) {
+  __shared__ int64_t wa[PL_THREADS / WAVE], wc[PL_THREADS / WAVE];
+  const int l = lane_id(), w = threadIdx.x / WAVE;
+  int64_t ia = a, ic = c;
 #pragma unroll
   for (int o = 1; o < WAVE; o <<= 1) {
-    const int64_t yb = __shfl_up(ib, o, WAVE);
-    if (l >= o) ib += yb;
+    const int64_t ya = __shfl_up(ia, o, WAVE), yc = __shfl_up(ic, o, WAVE);
+    if (l >= o) {
+      ia += ya;
+      ic += yc;
+    }
   }
-  if (l == WAVE - 1) wb[w] = ib;
+  if (l == WAVE - 1) {
+    wa[w] = ia;
+    wc[w] = ic;
+  }
   __syncthreads();
-  int64_t ob = ib - sb;
-  for (int i = 0; i < w; ++i) ob += wb[i];
-  for (int b = b0; b < b1; ++b) {
-    const int64_t ni = slices(b);
-    if (b < nbk) bk_end[b] = bk_start[b] + bk_fill[b];
-    item_start[b] = ob;
-    for (int64_t i = 0; i < ni; ++i) item_bk[ob + i] = b;
-    ob += ni;
+  int64_t oa = 0, oc = 0;
+  ta = tc = 0;
+  for (int i = 0; i < PL_THREADS / WAVE; ++i) {
+    if (i < w) {
+      oa += wa[i];
+      oc += wc[i];
+    }
+    ta += wa[i];
+    tc += wc[i];
   }
-  __syncthreads();  // every fill cursor read: clear them for the next call
-  for (int b = b0; b < b1; ++b) bk_fill[b] = 0;
+  a = oa + ia - a;
+  c = oc + ic - c;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(PL_THREADS)
+k_bk_plan_count(const int64_t *bk_fill, int nbk, int64_t *btot) {
+  const int64_t b = (int64_t)blockIdx.x * PL_THREADS + threadIdx.x;
+  int64_t sl = plan_slices(bk_fill, nbk, b);
+  int64_t sp = sl > 1 ? 1 : 0;
+  int64_t ts, tp;
+  plan_scan2(sl, sp, ts, tp);
+  if (threadIdx.x == 0) {
+    btot[2 * blockIdx.x] = ts;
+    btot[2 * blockIdx.x + 1] = tp;
+  }
+}
+
+__global__ void __launch_bounds__(PL_THREADS)
+k_bk_plan(const int64_t *bk_start, int64_t *bk_fill, int nbk,
+          const int64_t *btot, int64_t *bk_end, int64_t *item_start,
+          int32_t *item_bk, int64_t *split, int64_t *nsplit) {
+  __shared__ int64_t red[2][PL_THREADS / WAVE];
+  const int t = threadIdx.x, l = lane_id(), w = t / WAVE;
+  // offsets of this block: the earlier blocks' totals
+  int64_t os = 0, op = 0;
+  for (int i = t; i < (int)blockIdx.x; i += PL_THREADS) {
+    os += btot[2 * i];
+    op += btot[2 * i + 1];
+  }
+#pragma unroll
+  for (int o = WAVE / 2; o >= 1; o >>= 1) {
+    os += __shfl_xor(os, o, WAVE);
+    op += __shfl_xor(op, o, WAVE);
+  }
+  if (l == 0) {
+    red[0][w] = os;
+    red[1][w] = op;
+  }
+  __syncthreads();
+  os = op = 0;
+  for (int i = 0; i < PL_THREADS / WAVE; ++i) {
+    os += red[0][i];
+    op += red[1][i];
+  }
+  const int64_t b = (int64_t)blockIdx.x * PL_THREADS + t;
+  const int64_t fill = b < nbk ? bk_fill[b] : 0;
+  const int64_t ni = plan_slices(bk_fill, nbk, b);
+  int64_t es = ni, ep = ni > 1 ? 1 : 0;
+  int64_t ts, tp;
+  plan_scan2(es, ep, ts, tp);
+  if (b < nbk) {
+    bk_end[b] = bk_start[b] + fill;
+    bk_fill[b] = 0;  // read: clear it for the next call
+  }
+  if (b <= nbk) item_start[b] = os + es;
+  for (int64_t i = 0; i < ni; ++i) item_bk[os + es + i] = (int32_t)b;
+  if (ni > 1) split[op + ep] = b;
+  if (blockIdx.x == gridDim.x - 1 && t == 0) *nsplit = op + tp;
 }
 
 // Fixed record regions of the output-row buckets of one mode (built once):
@@ -938,18 +1004,22 @@ __global__ void k_debug_unique(const int64_t *counts, const int32_t *uq_s,
 }
 
 // Rows of a split bucket: sum of its slices' blocks, in slice order.
+// Split buckets only: entry e of bucket split[i]'s B x R block is the sum
+// of its slices' blocks, in slice order.
 template <typename T>
-__global__ void k_bk_combine(const int64_t *item_start, int nbk, int bb, int R,
-                             int64_t I, const T *part, T *M) {
+__global__ void k_bk_combine(const int64_t *item_start, const int64_t *split,
+                             const int64_t *nsplit, int bb, int R, int64_t I,
+                             const T *part, T *M) {
   const int B = 1 << bb;
   const int64_t per = (int64_t)B * R;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-       g < (int64_t)nbk * per; g += (int64_t)gridDim.x * blockDim.x) {
-    const int bk = (int)(g / per);
-    const int e = (int)(g - (int64_t)bk * per);
+  const int64_t total = *nsplit * per;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t si = g / per;
+    const int e = (int)(g - si * per);
+    const int64_t bk = split[si];
     const int64_t k0 = item_start[bk], k1 = item_start[bk + 1];
-    if (k1 - k0 < 2) continue;
-    const int64_t row0 = (int64_t)bk * B;
+    const int64_t row0 = bk * B;
     if (row0 + e / R >= I) continue;
     T acc = 0;
     for (int64_t k = k0; k < k1; ++k) acc += part[k * per + e];
@@ -1030,7 +1100,10 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
   // fixed offsets: the fill cursors of every mode stay zero between calls
   // (each plan clears the ones it read), whatever the mode's bucket count
   int64_t *bk_fill = w.bk, *bk_end = w.bk + (w.bk_max + 1),
-          *item_start = w.bk + 2 * (w.bk_max + 1);
+          *item_start = w.bk + 2 * (w.bk_max + 1),
+          *split = w.bk + 3 * (w.bk_max + 1),
+          *btot = w.bk + 4 * (w.bk_max + 1),
+          *nsplit = btot + 2 * ((w.bk_max + 1 + PL_THREADS - 1) / PL_THREADS);
   const dim3 b(MT_THREADS), gt(mttkrp_grid());
   BkRec<T> *rec = static_cast<BkRec<T> *>(w.rec);
   T *part = static_cast<T *>(w.part);
@@ -1057,8 +1130,13 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
                        bk_start, bk_fill, static_cast<void *>(rec));
     CPR_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_bk_plan, dim3(1), dim3(PL_THREADS), 0, s, bk_start,
-                     bk_fill, nbk, bk_end, item_start, w.item_bk);
+  const int nplan = (int)((nbk + 1 + PL_THREADS - 1) / PL_THREADS);
+  hipLaunchKernelGGL(k_bk_plan_count, dim3(nplan), dim3(PL_THREADS), 0, s,
+                     bk_fill, nbk, btot);
+  CPR_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bk_plan, dim3(nplan), dim3(PL_THREADS), 0, s, bk_start,
+                     bk_fill, nbk, btot, bk_end, item_start, w.item_bk, split,
+                     nsplit);
   CPR_LAUNCH_CHECK();
   constexpr int VW = 16 / sizeof(T);  // columns per lane
   // records, then the boundary partials: 2 per lane group, L VW columns
@@ -1099,11 +1177,18 @@ void sampled_mttkrp(const SampleWork &w, int64_t I, const int64_t *col_ptr,
     else launch(k_bk_accum<T, 64, VW, false>, 13);
   }
   CPR_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_bk_combine<T>), gt, b, 0, s, item_start, nbk, bb, R, I,
-                     part, M);
+  hipLaunchKernelGGL((k_bk_combine<T>), gt, b, 0, s, item_start, split,
+                     nsplit, bb, R, I, part, M);
   CPR_LAUNCH_CHECK();
 }
 int64_t bucket_tiles(int64_t rec_cap) { return rec_cap / BK_TILE + 2; }
+
+int64_t bucket_work_entries(int64_t bk_max) {
+  // fill cursors, ends, slice starts, split buckets (bk_max + 1 each), the
+  // plan's per-block totals and the split count
+  return 4 * (bk_max + 1) + 2 * ((bk_max + 1 + PL_THREADS - 1) / PL_THREADS) +
+         1;
+}
 
 int64_t bucket_max_items(int64_t rec_cap, int64_t nbk) {
   return rec_cap / BK_SLICE + nbk + 1;

@@ -1589,64 +1589,79 @@ k_sts_final_w(int R, int64_t J, const double *hbuf, const double *Gp,
   }
 }
 
-// Tree leaves, wide ranks: one leaf per block, the NT (NT + 1) / 2 tiles of
-// its Gram split over the 4 waves (tile i to wave i % 4); every wave reads
-// the leaf's rows, wave 0 writes the renormalised factor (SCALE).  Internal
-// nodes come from k_tree_up.
+// Tree leaves, wide ranks: one block per pair of sibling leaves (two leaf
+// Grams, then their parent as the sum of the two, kept in registers: the
+// upper levels then start one level up), the NT (NT + 1) / 2 tiles of a
+// Gram split over the 4 waves (tile i to wave i % 4); every wave reads the
+// leaves' rows, wave 0 writes the renormalised factor (SCALE).  Nodes above
+// the parents come from k_tree_up.
 template <typename T, int NT, bool SCALE, int W>
-__device__ __forceinline__ void leaf_tiles(const T *U, const double *X,
-                                           const double (&sg)[NT], T *Uout,
-                                           int64_t I, int R, int F,
-                                           int64_t leaf, double *node) {
-  constexpr int NTRI = NT * (NT + 1) / 2, RP = 16 * NT;
+__device__ __forceinline__ void leaf_acc(const T *U, const double *X,
+                                         const double (&sg)[NT], T *Uout,
+                                         int64_t I, int R, int F, int64_t leaf,
+                                         double4_t (&acc)[(NT * (NT + 1) / 2 - W + 3) / 4 > 0
+                                                              ? (NT * (NT + 1) / 2 - W + 3) / 4
+                                                              : 1]) {
+  constexpr int NTRI = NT * (NT + 1) / 2;
   constexpr int NMY = (NTRI - W + 3) / 4;  // tiles of this wave
+  constexpr int QH = 2;  // k-steps whose rows are read together
   const int l = lane_id();
-  double4_t acc[NMY > 0 ? NMY : 1];
 #pragma unroll
   for (int i = 0; i < (NMY > 0 ? NMY : 1); ++i) acc[i] = double4_t{0, 0, 0, 0};
   const int64_t rbase = leaf * F;
   for (int k0 = 0; k0 < F; k0 += 16) {
-    double col[4][NT];
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int64_t r = rbase + k0 + 4 * qq + l / 16;
-      const int64_t ro = (r < I ? r : I - 1) * R;
+    for (int q0 = 0; q0 < 4; q0 += QH) {
+      double col[QH][NT];
 #pragma unroll
-      for (int ta = 0; ta < NT; ++ta) {
-        const int ca = ta * 16 + (l % 16);
-        const int cc = ca < R ? ca : R - 1;
-        if constexpr (SCALE) col[qq][ta] = X[ro + cc];
-        else col[qq][ta] = (double)U[ro + cc];
-      }
-    }
+      for (int qq = 0; qq < QH; ++qq) {
+        const int64_t r = rbase + k0 + 4 * (q0 + qq) + l / 16;
+        const int64_t ro = (r < I ? r : I - 1) * R;
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int64_t r = rbase + k0 + 4 * qq + l / 16;
-      const double rm = r < I ? 1.0 : 0.0;
-#pragma unroll
-      for (int ta = 0; ta < NT; ++ta) {
-        const int ca = ta * 16 + (l % 16);
-        double x = col[qq][ta];
-        if constexpr (SCALE) {
-          const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
-          if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
-          x = (double)u;
+        for (int ta = 0; ta < NT; ++ta) {
+          const int ca = ta * 16 + (l % 16);
+          const int cc = ca < R ? ca : R - 1;
+          if constexpr (SCALE) col[qq][ta] = X[ro + cc];
+          else col[qq][ta] = (double)U[ro + cc];
         }
-        col[qq][ta] = x * (ca < R ? rm : 0.0);
       }
-    }
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
+      for (int qq = 0; qq < QH; ++qq) {
+        const int64_t r = rbase + k0 + 4 * (q0 + qq) + l / 16;
+        const double rm = r < I ? 1.0 : 0.0;
 #pragma unroll
-      for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-        for (int tb = ta; tb < NT; ++tb) {
-          const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
-          if (i % 4 == W)
-            acc[i / 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                col[qq][ta], col[qq][tb], acc[i / 4], 0, 0, 0);
+        for (int ta = 0; ta < NT; ++ta) {
+          const int ca = ta * 16 + (l % 16);
+          double x = col[qq][ta];
+          if constexpr (SCALE) {
+            const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
+            if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
+            x = (double)u;
+          }
+          col[qq][ta] = x * (ca < R ? rm : 0.0);
         }
+      }
+#pragma unroll
+      for (int qq = 0; qq < QH; ++qq)
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = ta; tb < NT; ++tb) {
+            const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+            if (i % 4 == W)
+              acc[i / 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                  col[qq][ta], col[qq][tb], acc[i / 4], 0, 0, 0);
+          }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
+}
+
+template <int NT, int W, int NA>
+__device__ __forceinline__ void write_tiles(const double4_t (&acc)[NA],
+                                            double *node) {
+  constexpr int RP = 16 * NT;
+  const int l = lane_id();
 #pragma unroll
   for (int ta = 0; ta < NT; ++ta)
 #pragma unroll
@@ -1663,11 +1678,67 @@ __device__ __forceinline__ void leaf_tiles(const T *U, const double *X,
     }
 }
 
-template <typename T, int NT, bool SCALE>
+// The tile entries as the full R x R matrix G (both halves), for a node
+// that is the tree's root.
+template <int NT, int W, int NA>
+__device__ __forceinline__ void write_full(const double4_t (&acc)[NA],
+                                           double *G, int R) {
+  const int l = lane_id();
+#pragma unroll
+  for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+    for (int tb = ta; tb < NT; ++tb) {
+      const int i = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+      if (i % 4 == W) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ga = ta * 16 + (l / 16) + 4 * v;
+          const int gb = tb * 16 + (l % 16);
+          if (ga <= gb && gb < R) {
+            G[ga * R + gb] = acc[i / 4][v];
+            G[gb * R + ga] = acc[i / 4][v];
+          }
+        }
+      }
+    }
+}
+
+// PAIR: leaves 2b and 2b + 1 and their parent; else leaf b alone.  G (or
+// null) receives the root when this block writes it (P2 = 2 with pairs).
+// The first leaf's tiles wait in LDS (each lane its own entries, so no
+// barrier) while the second leaf is formed in the same registers.
+template <typename T, int NT, bool SCALE, bool PAIR, int W>
+__device__ __forceinline__ void leaf_block(const T *U, const double *X,
+                                           const double (&sg)[NT], T *Uout,
+                                           int64_t I, int R, int F, int64_t P2,
+                                           int64_t b, double *tree, double *G,
+                                           double4_t *stash) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  constexpr int NTRI = NT * (NT + 1) / 2;
+  constexpr int NA = (NTRI - W + 3) / 4 > 0 ? (NTRI - W + 3) / 4 : 1;
+  const int l = lane_id();
+  double4_t a0[NA];
+  if constexpr (!PAIR) {
+    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, b, a0);
+    write_tiles<NT, W>(a0, tree + (P2 + b) * (int64_t)P);
+  } else {
+    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, 2 * b, a0);
+    write_tiles<NT, W>(a0, tree + (P2 + 2 * b) * (int64_t)P);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) stash[i * WAVE + l] = a0[i];
+    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, 2 * b + 1, a0);
+    write_tiles<NT, W>(a0, tree + (P2 + 2 * b + 1) * (int64_t)P);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) a0[i] += stash[i * WAVE + l];
+    write_tiles<NT, W>(a0, tree + (P2 / 2 + b) * (int64_t)P);
+    if (G && P2 == 2) write_full<NT, W>(a0, G, R);
+  }
+}
+
+template <typename T, int NT, bool SCALE, bool PAIR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_tree_build_w(const T *U, const double *X, const double *sigma, T *Uout,
-               int64_t I, int R, int F, int64_t P2, double *tree) {
-  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+               int64_t I, int R, int F, int64_t P2, double *tree, double *G) {
   const int l = lane_id();
   double sg[NT];
 #pragma unroll
@@ -1675,13 +1746,16 @@ k_tree_build_w(const T *U, const double *X, const double *sigma, T *Uout,
     const int ca = ta * 16 + (l % 16);
     sg[ta] = SCALE ? sigma[ca < R ? ca : R - 1] : 1.0;
   }
-  const int64_t leaf = blockIdx.x;
-  double *node = tree + (P2 + leaf) * (int64_t)P;
-  switch (threadIdx.x / WAVE) {
-    case 0: leaf_tiles<T, NT, SCALE, 0>(U, X, sg, Uout, I, R, F, leaf, node); break;
-    case 1: leaf_tiles<T, NT, SCALE, 1>(U, X, sg, Uout, I, R, F, leaf, node); break;
-    case 2: leaf_tiles<T, NT, SCALE, 2>(U, X, sg, Uout, I, R, F, leaf, node); break;
-    default: leaf_tiles<T, NT, SCALE, 3>(U, X, sg, Uout, I, R, F, leaf, node); break;
+  constexpr int NAMAX = (NT * (NT + 1) / 2 + 3) / 4;
+  __shared__ double4_t stash[PAIR ? 4 * NAMAX * WAVE : 1];
+  const int64_t b = blockIdx.x;
+  const int w = threadIdx.x / WAVE;
+  double4_t *st = stash + (PAIR ? w * NAMAX * WAVE : 0);
+  switch (w) {
+    case 0: leaf_block<T, NT, SCALE, PAIR, 0>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 1: leaf_block<T, NT, SCALE, PAIR, 1>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 2: leaf_block<T, NT, SCALE, PAIR, 2>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    default: leaf_block<T, NT, SCALE, PAIR, 3>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
   }
 }
 
@@ -1795,7 +1869,8 @@ void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
                 int64_t I, int R, int F, int64_t P2, double *tree, double *G,
                 hipStream_t s) {
   const int nt = (R + 15) / 16;
-  const int lb = nt >= WNT_MIN ? 0 : tree_leaf_shift(R, P2);
+  // wide ranks: one block per pair of leaves (their parents written too)
+  const int lb = nt >= WNT_MIN ? (P2 >= 2 ? 1 : 0) : tree_leaf_shift(R, P2);
   const size_t lds = ((size_t)1 << lb) * sts_packed(R) * 8;
   const dim3 g((unsigned)(P2 >> lb)), b(256);
   switch (nt) {
@@ -1803,10 +1878,18 @@ void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
     case 2: hipLaunchKernelGGL((k_tree_build<T, 2, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
     case 3: hipLaunchKernelGGL((k_tree_build<T, 3, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
     case 4: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
-    case 5: hipLaunchKernelGGL((k_tree_build_w<T, 5, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
-    case 6: hipLaunchKernelGGL((k_tree_build_w<T, 6, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
-    case 7: hipLaunchKernelGGL((k_tree_build_w<T, 7, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
-    default: hipLaunchKernelGGL((k_tree_build_w<T, 8, SCALE>), g, b, 0, s, U, X, sigma, Uout, I, R, F, P2, tree); break;
+#define CPR_TBW(NT)                                                         \
+  if (lb)                                                                   \
+    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, true>), g, b, 0, s, U, \
+                       X, sigma, Uout, I, R, F, P2, tree, G);               \
+  else                                                                      \
+    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, false>), g, b, 0, s,   \
+                       U, X, sigma, Uout, I, R, F, P2, tree, G)
+    case 5: CPR_TBW(5); break;
+    case 6: CPR_TBW(6); break;
+    case 7: CPR_TBW(7); break;
+    default: CPR_TBW(8); break;
+#undef CPR_TBW
   }
   CPR_LAUNCH_CHECK();
   // subtree roots: nodes P2 >> lb .. 2 (P2 >> lb) - 1

@@ -99,6 +99,24 @@ def test_sts_fp64_mode_solves(dev, R, J, leaf):
     ctx.close()
 
 
+@pytest.mark.parametrize("dims", [(300, 100, 90), (300, 60, 50)])
+def test_sts_wide_rank_small_trees(dev, dims):
+    """Rank 100 with 64-row leaves on tree factors of 65-128 rows (two
+    leaves: the block that forms the pair of leaves also writes their
+    parent, the root, and the factor's Gram) and of at most 64 rows (one
+    leaf, the root)."""
+    T, _ = tg.tiny_tensor(52, dims, 20000, rank=4, noise_var=0.01)
+    R, J = 100, 256
+    ctx = make_ctx(dev, T, R, "sts", "fp64", J, 64)
+    _, runi = init_ctx(ctx, T.dims, R, 53)
+    acc = 0
+    for j in (0, 1, 2, 0):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-10)
+    assert acc <= 2
+    ctx.close()
+
+
 def test_sts_fp32_zipf_mode_solves(dev):
     T = tg.zipf_tensor(42, (3000, 2400, 1800), 200_000, s=1.1)
     R, J = 32, 4096
