@@ -61,6 +61,8 @@ struct cp_ctx {
   int bb = 7;                // bucket shift of this context's rank
   bool sketched = false;     // solve with the sketched Gram of the draws
   bool refine = true;        // one refinement step on the row solve
+  bool x32 = false;          // the solve's rows X are FP32 (FP32 forms, no
+                             // refinement), else FP64
   double *hs = nullptr;      // J x R: draws scaled by 1 / sqrt(J p)
   double *Gs = nullptr;      // R x R: their Gram
   // bucket shift of the sampled MTTKRP for rank r
@@ -392,12 +394,12 @@ void do_solve(cp_ctx *c, int mode) {
   if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, mode) &&
       c->P2[mode] >= 2) {
     PhaseScope ps(c, PH_SAMPLER_BUILD);  // the tree's root is the Gram
-    sts_build_scaled<T>(c->X, c->sigma, U, I, c->R, c->F, c->P2[mode],
-                        c->tree[mode], c->G[mode], c->s);
+    sts_build_scaled<T>(c->X, c->x32, c->sigma, U, I, c->R, c->F,
+                        c->P2[mode], c->tree[mode], c->G[mode], c->s);
   } else {
     {
       PhaseScope ps(c, PH_GRAM);
-      gram_scaled<T>(c->X, c->sigma, I, c->R, U, c->G[mode], c->tmp,
+      gram_scaled<T>(c->X, c->x32, c->sigma, I, c->R, U, c->G[mode], c->tmp,
                      c->gram_mode, c->s);
     }
     rebuild_sampler<T>(c, mode);
@@ -447,6 +449,7 @@ void set_config(cp_ctx *c, int N, const int64_t *dims, const cp_config *cfg) {
                 cfg->sampler != CP_SAMPLER_EXACT;
   c->refine = cfg->solve_refine == CP_REFINE_ON ||
               (cfg->solve_refine == CP_REFINE_AUTO && c->f64);
+  c->x32 = !c->f64 && !c->refine;
   c->bb_fixed = -1;
   for (int b = 4; b <= 8; ++b)
     if (cfg->bucket_rows == (1 << b)) c->bb_fixed = b;

@@ -108,9 +108,11 @@ void gram(const T *U, int64_t I, int R, double *G, void *tmp, int mode,
           hipStream_t s);
 // The same after the solve: U = X / sigma written in the factor's precision
 // (zero columns stay zero) by the pass that stages it, G of the stored U.
+// X holds float rows when x32 (the FP32 forms' unrefined solve), else
+// double.
 template <typename T>
-void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
-                 double *G, void *tmp, int mode, hipStream_t s);
+void gram_scaled(const void *X, bool x32, const double *sigma, int64_t I,
+                 int R, T *U, double *G, void *tmp, int mode, hipStream_t s);
 // G~ = sum_s h_s h_s^T / (J p_s) over J draws (h: J x R, factor precision),
 // the sketched Gram of Fig. 3; hs: J x R FP64 scratch, tmp as for gram.
 template <typename T>
@@ -124,11 +126,12 @@ void column_norms(const double *partial, int nblk, int R, double *sigma,
 void hadamard_pinv(const ModeList &ml, int R, double *Gfull, double *Gp,
                    double *ggt_out, double *trace_out, double *scratch,
                    uint32_t *err, hipStream_t s);
-// X = M G^+ (FP64), with one refinement step when `refine`, written as
-// double; per-block column sums of squares into partial (nblk x R).
+// X = M G^+ (FP64 MFMA, with one refinement step when `refine`, written as
+// double; FP32 factors without refinement: FP32 MFMA, X written as float);
+// per-block column sums of squares into partial (nblk x R).
 template <typename T>
 void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
-                const double *Gp, double *X, double *partial, int nblk,
+                const double *Gp, void *X, double *partial, int nblk,
                 int64_t *rows_out, bool refine, hipStream_t s);
 int solve_blocks(int64_t I);
 // sigma from partial sums; U = X / sigma (zero columns stay zero).
@@ -171,9 +174,9 @@ void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
 // factor's precision (zero columns stay zero) and builds on the stored
 // values; the root, which is U^T U, is written to G (R x R) when P2 >= 2.
 template <typename T>
-void sts_build_scaled(const double *X, const double *sigma, T *U, int64_t I,
-                      int R, int F, int64_t P2, double *tree, double *G,
-                      hipStream_t s);
+void sts_build_scaled(const void *X, bool x32, const double *sigma, T *U,
+                      int64_t I, int R, int F, int64_t P2, double *tree,
+                      double *G, hipStream_t s);
 // per-slot record of the level-by-level tree descent (slots grouped by node)
 struct SlotBuf {
   int32_t *s;  // sample

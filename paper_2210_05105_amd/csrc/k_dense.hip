@@ -161,9 +161,9 @@ int gram_lp_blocks(int64_t I, int64_t *rows_per_blk) {
   return (int)std::max<int64_t>(1, (I + *rows_per_blk - 1) / *rows_per_blk);
 }
 
-template <int MODE, int TPW, bool SCALE>
+template <int MODE, int TPW, bool SCALE, typename XT>
 __global__ void __launch_bounds__(GL_THREADS)
-k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
+k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
           int64_t I, int R, int Rp, int64_t rows_per_blk, double *partial) {
   constexpr int LDS_BYTES = MODE == GRAM_F32 ? GL_RC * (MAXR + 4) * 4
                                              : 2 * MAXR * GL_CS * 2;
@@ -204,7 +204,7 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
   // the chunk's nrow x R values are contiguous: value f of the chunk is
   // row f / R, column f % R (the float quotient is exact to well under the
   // 0.5 / R margin for f < GL_RC * MAXR)
-  using V = typename std::conditional<SCALE, double, float>::type;
+  using V = typename std::conditional<SCALE, XT, float>::type;
   V v[GL_PE];
   auto load = [&](int64_t c0) {
     const int nv = (int)std::min<int64_t>(GL_RC, r1 - c0) * R;
@@ -236,7 +236,7 @@ k_gram_lp(const float *U, const double *X, const double *sigma, float *Uout,
         float x;
         if constexpr (SCALE) {
           const double sg = ssg[cc];
-          x = (float)(sg > 0 ? v[q] / sg : 0.0);
+          x = (float)(sg > 0 ? (double)v[q] / sg : 0.0);
           Uout[c0 * R + f] = x;
         } else {
           x = v[q];
@@ -1033,14 +1033,14 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
 
 // Row solve of the FP32 forms without refinement: X^T = (G^+)^T M^T on
 // v_mfma_f32_16x16x4f32 (G^+ rounded to FP32 once, staged in LDS; M is
-// FP32 already; FP32 accumulation over the R terms of an entry), written as
-// FP64, column sums of X^2 in FP64.  Twice the FP32 MFMA rate of the FP64
+// FP32 already; FP32 accumulation over the R terms of an entry), X written
+// in FP32, column sums of X^2 in FP64.  Twice the FP32 MFMA rate of the FP64
 // MFMA, and a relative error of the order of M's own FP32 rounding.  The D
 // layout puts X[row0 + l % 16][16 t + 4 (l / 16) + v] in lane l, element v:
 // four consecutive columns of one row per lane.
 template <int NT>
 __global__ void __launch_bounds__(SV_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
-k_solve_f32(const float *M, int64_t I, int R, const double *Gp, double *X,
+k_solve_f32(const float *M, int64_t I, int R, const double *Gp, float *X,
             double *partial, int64_t *rows_out) {
   constexpr int KS = 4 * NT;
   constexpr int RP = 16 * NT;
@@ -1100,14 +1100,14 @@ k_solve_f32(const float *M, int64_t I, int R, const double *Gp, double *X,
 #pragma unroll
       for (int v = 0; v < 4; ++v) x[v] = (double)acc[v];
       if (row < I) {
-        double *dst = X + row * R + c0;
-        if (c0 + 3 < R && (R & 1) == 0) {
-          reinterpret_cast<double2 *>(dst)[0] = make_double2(x[0], x[1]);
-          reinterpret_cast<double2 *>(dst)[1] = make_double2(x[2], x[3]);
+        float *dst = X + row * R + c0;
+        if (c0 + 3 < R && (R & 3) == 0) {
+          *reinterpret_cast<float4 *>(dst) =
+              make_float4(acc[0], acc[1], acc[2], acc[3]);
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (c0 + v < R) dst[v] = x[v];
+            if (c0 + v < R) dst[v] = acc[v];
         }
       }
       // this tile's column sums of X^2: the 16 row lanes (shuffle tree),
@@ -1206,8 +1206,10 @@ size_t gram_temp_bytes(int64_t I, int R) {
   return (size_t)nblk * R * R * sizeof(double) + 256;
 }
 
-template <typename T, bool SCALE>
-void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
+// XT: the type of the solve's rows X when SCALE (FP32 only for FP32
+// factors, which take the reduced-precision Gram)
+template <typename T, bool SCALE, typename XT = double>
+void gram_any(const T *U, const XT *X, const double *sigma, T *Uout,
               int64_t I, int R, double *G, void *tmp, int mode,
               hipStream_t s) {
   int64_t rpb;
@@ -1221,8 +1223,9 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
       const int nbl = gram_lp_blocks(I, &rpb);
       const int tpl = (ntri + GL_THREADS / WAVE - 1) / (GL_THREADS / WAVE);
 #define CPR_GRAM_LP(M, K)                                                   \
-  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE>), dim3(nbl), dim3(GL_THREADS), \
-                     0, s, U, X, sigma, Uout, I, R, Rp, rpb, partial)
+  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE, XT>), dim3(nbl),              \
+                     dim3(GL_THREADS), 0, s, U, X, sigma, Uout, I, R, Rp, rpb, \
+                     partial)
 #define CPR_GRAM_LP_T(M)              \
   switch (tpl) {                      \
     case 1: CPR_GRAM_LP(M, 1); break; \
@@ -1244,6 +1247,10 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
       return;
     }
   }
+  if constexpr (!std::is_same<XT, double>::value) {
+    // FP32 rows X come only with the FP32 forms' reduced-precision Grams
+    throw HipFail(hipErrorInvalidValue, __FILE__, __LINE__);
+  } else {
 #define CPR_GRAM(K) \
   launch_gram<T, K, SCALE>(U, X, sigma, Uout, I, R, Rp, partial, nblk, rpb, s)
   switch (tpw) {
@@ -1257,12 +1264,14 @@ void gram_any(const T *U, const double *X, const double *sigma, T *Uout,
 #undef CPR_GRAM
   colsum(partial, nblk, R * R, G, 0, nullptr, s);
   CPR_LAUNCH_CHECK();
+  }
 }
 
 template <typename T>
 void gram(const T *U, int64_t I, int R, double *G, void *tmp, int mode,
           hipStream_t s) {
-  gram_any<T, false>(U, nullptr, nullptr, nullptr, I, R, G, tmp, mode, s);
+  gram_any<T, false, double>(U, nullptr, nullptr, nullptr, I, R, G, tmp, mode,
+                            s);
 }
 template void gram<float>(const float *, int64_t, int, double *, void *, int,
                           hipStream_t);
@@ -1270,13 +1279,22 @@ template void gram<double>(const double *, int64_t, int, double *, void *,
                            int, hipStream_t);
 
 template <typename T>
-void gram_scaled(const double *X, const double *sigma, int64_t I, int R, T *U,
-                 double *G, void *tmp, int mode, hipStream_t s) {
-  gram_any<T, true>(nullptr, X, sigma, U, I, R, G, tmp, mode, s);
+void gram_scaled(const void *X, bool x32, const double *sigma, int64_t I,
+                 int R, T *U, double *G, void *tmp, int mode, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (x32) {
+      gram_any<T, true, float>(nullptr, static_cast<const float *>(X), sigma,
+                               U, I, R, G, tmp, mode, s);
+      return;
+    }
+  }
+  gram_any<T, true, double>(nullptr, static_cast<const double *>(X), sigma, U,
+                            I, R, G, tmp, mode, s);
 }
-template void gram_scaled<float>(const double *, const double *, int64_t, int,
-                                 float *, double *, void *, int, hipStream_t);
-template void gram_scaled<double>(const double *, const double *, int64_t,
+template void gram_scaled<float>(const void *, bool, const double *, int64_t,
+                                 int, float *, double *, void *, int,
+                                 hipStream_t);
+template void gram_scaled<double>(const void *, bool, const double *, int64_t,
                                   int, double *, double *, void *, int,
                                   hipStream_t);
 
@@ -1297,7 +1315,7 @@ void sketched_gram(const T *h, const double *prob, int64_t J, int R,
   hipLaunchKernelGGL((k_scale_draws<T>), dim3(ceil_div(J * R, 256)),
                      dim3(256), 0, s, h, prob, J, R, hs);
   CPR_LAUNCH_CHECK();
-  gram_any<double, false>(hs, nullptr, nullptr, nullptr, J, R, Gs, tmp,
+  gram_any<double, false, double>(hs, nullptr, nullptr, nullptr, J, R, Gs, tmp,
                           GRAM_F64, s);
 }
 template void sketched_gram<float>(const float *, const double *, int64_t,
@@ -1338,18 +1356,18 @@ int solve_blocks(int64_t I) {
 
 template <typename T, bool RF>
 void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
-                   const double *Gp, double *X, double *partial, int nblk,
+                   const double *Gp, void *Xv, double *partial, int nblk,
                    int64_t *rows_out, hipStream_t s) {
   const dim3 g(nblk), b(SV_THREADS);
   constexpr bool F32 = std::is_same<T, float>::value && !RF;
 #define CPR_SOLVE(NT)                                                        \
   if constexpr (F32)                                                         \
     hipLaunchKernelGGL((k_solve_f32<NT>), g, b, 0, s,                        \
-                       reinterpret_cast<const float *>(M), I, R, Gp, X,      \
-                       partial, rows_out);                                   \
+                       reinterpret_cast<const float *>(M), I, R, Gp,         \
+                       static_cast<float *>(Xv), partial, rows_out);         \
   else                                                                       \
     hipLaunchKernelGGL((k_solve<T, NT, RF>), g, b, 0, s, M, I, R, Gfull, Gp, \
-                       X, partial, rows_out)
+                       static_cast<double *>(Xv), partial, rows_out)
   switch ((R + 15) / 16) {
     case 1: CPR_SOLVE(1); break;
     case 2: CPR_SOLVE(2); break;
@@ -1366,7 +1384,7 @@ void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
 
 template <typename T>
 void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
-                const double *Gp, double *X, double *partial, int nblk,
+                const double *Gp, void *X, double *partial, int nblk,
                 int64_t *rows_out, bool refine, hipStream_t s) {
   if (refine)
     solve_rows_nt<T, true>(M, I, R, Gfull, Gp, X, partial, nblk, rows_out, s);
@@ -1374,10 +1392,10 @@ void solve_rows(const T *M, int64_t I, int R, const double *Gfull,
     solve_rows_nt<T, false>(M, I, R, Gfull, Gp, X, partial, nblk, rows_out, s);
 }
 template void solve_rows<float>(const float *, int64_t, int, const double *,
-                                const double *, double *, double *, int,
+                                const double *, void *, double *, int,
                                 int64_t *, bool, hipStream_t);
 template void solve_rows<double>(const double *, int64_t, int, const double *,
-                                 const double *, double *, double *, int,
+                                 const double *, void *, double *, int,
                                  int64_t *, bool, hipStream_t);
 
 template <typename T>

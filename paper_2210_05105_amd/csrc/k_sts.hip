@@ -17,6 +17,8 @@
 // and the index is min{ i : t < F(i) }.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace cpr {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -108,9 +110,9 @@ constexpr int TB_LBMAX = 16;
 // U = X / sigma (zero columns stay zero) in the factor's precision; the
 // Grams are of the stored values.  G (or null) receives the root as an
 // R x R matrix when this launch writes the root.
-template <typename T, int NT, bool SCALE>
+template <typename T, int NT, bool SCALE, typename XT>
 __global__ void __launch_bounds__(256)
-k_tree_build(const T *U, const double *X, const double *sigma, T *Uout,
+k_tree_build(const T *U, const XT *X, const double *sigma, T *Uout,
              int64_t I, int R, int F, int64_t P2, int lb, double *tree,
              double *G) {
   constexpr int NTRI = NT * (NT + 1) / 2, RP = 16 * NT;
@@ -145,7 +147,7 @@ k_tree_build(const T *U, const double *X, const double *sigma, T *Uout,
         for (int ta = 0; ta < NT; ++ta) {
           const int ca = ta * 16 + (l % 16);
           const int cc = ca < R ? ca : R - 1;
-          if constexpr (SCALE) col[q][ta] = X[ro + cc];
+          if constexpr (SCALE) col[q][ta] = (double)X[ro + cc];
           else col[q][ta] = (double)U[ro + cc];
         }
       }
@@ -1595,8 +1597,8 @@ k_sts_final_w(int R, int64_t J, const double *hbuf, const double *Gp,
 // Gram split over the 4 waves (tile i to wave i % 4); every wave reads the
 // leaves' rows, wave 0 writes the renormalised factor (SCALE).  Nodes above
 // the parents come from k_tree_up.
-template <typename T, int NT, bool SCALE, int W>
-__device__ __forceinline__ void leaf_acc(const T *U, const double *X,
+template <typename T, int NT, bool SCALE, int W, typename XT>
+__device__ __forceinline__ void leaf_acc(const T *U, const XT *X,
                                          const double (&sg)[NT], T *Uout,
                                          int64_t I, int R, int F, int64_t leaf,
                                          double4_t (&acc)[(NT * (NT + 1) / 2 - W + 3) / 4 > 0
@@ -1621,7 +1623,7 @@ __device__ __forceinline__ void leaf_acc(const T *U, const double *X,
         for (int ta = 0; ta < NT; ++ta) {
           const int ca = ta * 16 + (l % 16);
           const int cc = ca < R ? ca : R - 1;
-          if constexpr (SCALE) col[qq][ta] = X[ro + cc];
+          if constexpr (SCALE) col[qq][ta] = (double)X[ro + cc];
           else col[qq][ta] = (double)U[ro + cc];
         }
       }
@@ -1707,8 +1709,8 @@ __device__ __forceinline__ void write_full(const double4_t (&acc)[NA],
 // null) receives the root when this block writes it (P2 = 2 with pairs).
 // The first leaf's tiles wait in LDS (each lane its own entries, so no
 // barrier) while the second leaf is formed in the same registers.
-template <typename T, int NT, bool SCALE, bool PAIR, int W>
-__device__ __forceinline__ void leaf_block(const T *U, const double *X,
+template <typename T, int NT, bool SCALE, bool PAIR, int W, typename XT>
+__device__ __forceinline__ void leaf_block(const T *U, const XT *X,
                                            const double (&sg)[NT], T *Uout,
                                            int64_t I, int R, int F, int64_t P2,
                                            int64_t b, double *tree, double *G,
@@ -1719,14 +1721,14 @@ __device__ __forceinline__ void leaf_block(const T *U, const double *X,
   const int l = lane_id();
   double4_t a0[NA];
   if constexpr (!PAIR) {
-    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, b, a0);
+    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, b, a0);
     write_tiles<NT, W>(a0, tree + (P2 + b) * (int64_t)P);
   } else {
-    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, 2 * b, a0);
+    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, 2 * b, a0);
     write_tiles<NT, W>(a0, tree + (P2 + 2 * b) * (int64_t)P);
 #pragma unroll
     for (int i = 0; i < NA; ++i) stash[i * WAVE + l] = a0[i];
-    leaf_acc<T, NT, SCALE, W>(U, X, sg, Uout, I, R, F, 2 * b + 1, a0);
+    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, 2 * b + 1, a0);
     write_tiles<NT, W>(a0, tree + (P2 + 2 * b + 1) * (int64_t)P);
 #pragma unroll
     for (int i = 0; i < NA; ++i) a0[i] += stash[i * WAVE + l];
@@ -1735,9 +1737,9 @@ __device__ __forceinline__ void leaf_block(const T *U, const double *X,
   }
 }
 
-template <typename T, int NT, bool SCALE, bool PAIR>
+template <typename T, int NT, bool SCALE, bool PAIR, typename XT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_tree_build_w(const T *U, const double *X, const double *sigma, T *Uout,
+k_tree_build_w(const T *U, const XT *X, const double *sigma, T *Uout,
                int64_t I, int R, int F, int64_t P2, double *tree, double *G) {
   const int l = lane_id();
   double sg[NT];
@@ -1752,10 +1754,10 @@ k_tree_build_w(const T *U, const double *X, const double *sigma, T *Uout,
   const int w = threadIdx.x / WAVE;
   double4_t *st = stash + (PAIR ? w * NAMAX * WAVE : 0);
   switch (w) {
-    case 0: leaf_block<T, NT, SCALE, PAIR, 0>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    case 1: leaf_block<T, NT, SCALE, PAIR, 1>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    case 2: leaf_block<T, NT, SCALE, PAIR, 2>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    default: leaf_block<T, NT, SCALE, PAIR, 3>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 0: leaf_block<T, NT, SCALE, PAIR, 0, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 1: leaf_block<T, NT, SCALE, PAIR, 1, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 2: leaf_block<T, NT, SCALE, PAIR, 2, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    default: leaf_block<T, NT, SCALE, PAIR, 3, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
   }
 }
 
@@ -1864,8 +1866,8 @@ int tree_leaf_shift(int R, int64_t P2) {
   return lb;
 }
 
-template <typename T, bool SCALE>
-void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
+template <typename T, bool SCALE, typename XT = double>
+void tree_build(const T *U, const XT *X, const double *sigma, T *Uout,
                 int64_t I, int R, int F, int64_t P2, double *tree, double *G,
                 hipStream_t s) {
   const int nt = (R + 15) / 16;
@@ -1874,17 +1876,17 @@ void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
   const size_t lds = ((size_t)1 << lb) * sts_packed(R) * 8;
   const dim3 g((unsigned)(P2 >> lb)), b(256);
   switch (nt) {
-    case 1: hipLaunchKernelGGL((k_tree_build<T, 1, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
-    case 2: hipLaunchKernelGGL((k_tree_build<T, 2, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
-    case 3: hipLaunchKernelGGL((k_tree_build<T, 3, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
-    case 4: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 1: hipLaunchKernelGGL((k_tree_build<T, 1, SCALE, XT>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 2: hipLaunchKernelGGL((k_tree_build<T, 2, SCALE, XT>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 3: hipLaunchKernelGGL((k_tree_build<T, 3, SCALE, XT>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
+    case 4: hipLaunchKernelGGL((k_tree_build<T, 4, SCALE, XT>), g, b, lds, s, U, X, sigma, Uout, I, R, F, P2, lb, tree, G); break;
 #define CPR_TBW(NT)                                                         \
   if (lb)                                                                   \
-    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, true>), g, b, 0, s, U, \
-                       X, sigma, Uout, I, R, F, P2, tree, G);               \
+    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, true, XT>), g, b, 0, s, \
+                       U, X, sigma, Uout, I, R, F, P2, tree, G);            \
   else                                                                      \
-    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, false>), g, b, 0, s,   \
-                       U, X, sigma, Uout, I, R, F, P2, tree, G)
+    hipLaunchKernelGGL((k_tree_build_w<T, NT, SCALE, false, XT>), g, b, 0,  \
+                       s, U, X, sigma, Uout, I, R, F, P2, tree, G)
     case 5: CPR_TBW(5); break;
     case 6: CPR_TBW(6); break;
     case 7: CPR_TBW(7); break;
@@ -1908,20 +1910,29 @@ void tree_build(const T *U, const double *X, const double *sigma, T *Uout,
 template <typename T>
 void sts_build(const T *U, int64_t I, int R, int F, int64_t P2, double *tree,
                hipStream_t s) {
-  tree_build<T, false>(U, nullptr, nullptr, nullptr, I, R, F, P2, tree,
-                       nullptr, s);
+  tree_build<T, false>(U, static_cast<const double *>(nullptr), nullptr,
+                       nullptr, I, R, F, P2, tree, nullptr, s);
 }
 
 template <typename T>
-void sts_build_scaled(const double *X, const double *sigma, T *U, int64_t I,
-                      int R, int F, int64_t P2, double *tree, double *G,
-                      hipStream_t s) {
-  tree_build<T, true>(nullptr, X, sigma, U, I, R, F, P2, tree, P2 >= 2 ? G : nullptr, s);
+void sts_build_scaled(const void *X, bool x32, const double *sigma, T *U,
+                      int64_t I, int R, int F, int64_t P2, double *tree,
+                      double *G, hipStream_t s) {
+  double *Gr = P2 >= 2 ? G : nullptr;
+  if constexpr (std::is_same<T, float>::value) {
+    if (x32) {
+      tree_build<T, true, float>(nullptr, static_cast<const float *>(X), sigma,
+                                 U, I, R, F, P2, tree, Gr, s);
+      return;
+    }
+  }
+  tree_build<T, true, double>(nullptr, static_cast<const double *>(X), sigma,
+                              U, I, R, F, P2, tree, Gr, s);
 }
-template void sts_build_scaled<float>(const double *, const double *, float *,
-                                      int64_t, int, int, int64_t, double *,
-                                      double *, hipStream_t);
-template void sts_build_scaled<double>(const double *, const double *,
+template void sts_build_scaled<float>(const void *, bool, const double *,
+                                      float *, int64_t, int, int, int64_t,
+                                      double *, double *, hipStream_t);
+template void sts_build_scaled<double>(const void *, bool, const double *,
                                        double *, int64_t, int, int, int64_t,
                                        double *, double *, hipStream_t);
 template void sts_build<float>(const float *, int64_t, int, int, int64_t,
