@@ -110,7 +110,7 @@ typedef enum {
                           per row instead of one)                          */
   CP_REFINE_OFF = 2    /* X = M G^+ alone: FP64 MFMA in CP_FP64; in the
                           FP32 forms FP32 MFMA (G^+ rounded to FP32, FP32
-                          accumulation, X stored FP64), whose rounding is
+                          accumulation, X kept in FP32), whose rounding is
                           of the order of what M already carries from the
                           FP32 MTTKRP                                      */
 } cp_solve_refine;
