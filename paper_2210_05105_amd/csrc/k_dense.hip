@@ -1036,27 +1036,43 @@ k_solve(const T *M, int64_t I, int R, const double *G, const double *Gp,
 // FP32 already; FP32 accumulation over the R terms of an entry), X written
 // in FP32, column sums of X^2 in FP64.  Twice the FP32 MFMA rate of the FP64
 // MFMA, and a relative error of the order of M's own FP32 rounding.  The D
-// layout puts X[row0 + l % 16][16 t + 4 (l / 16) + v] in lane l, element v:
-// four consecutive columns of one row per lane.
-template <int NT>
-__global__ void __launch_bounds__(SV_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+// layout puts X[row0 + l % 16][16 t + 4 (l / 16) + v] in lane l, element v.
+// Eight waves share the staged G^+.  Only the KS - D = (R + 3) / 4 k-steps
+// that hold columns below R are multiplied.  Each wave stages its 16 X rows in LDS and
+// writes them as one contiguous span (16 R floats, 16-byte stores when R is a
+// multiple of 4), so every output line is written whole.  Each lane keeps the
+// FP64 sums of squares of its 4 NT columns over the tiles it computed; they
+// are reduced over the 16 rows of a wave and the block's waves once, at the
+// end (a fixed order for a given grid).
+constexpr int SF_THREADS = 512;
+
+template <int NT, int D>
+__global__ void __launch_bounds__(SF_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 k_solve_f32(const float *M, int64_t I, int R, const double *Gp, float *X,
             double *partial, int64_t *rows_out) {
-  constexpr int KS = 4 * NT;
+  constexpr int KS = 4 * NT - D;  // k-steps with a column below R
   constexpr int RP = 16 * NT;
-  constexpr int RS = RP + 4;  // LDS row stride (floats)
+  constexpr int RS = RP + 4;  // LDS row stride of G^+ and of the X tiles
+  constexpr int NW = SF_THREADS / WAVE;
   __shared__ float sG[RP * RS];
-  __shared__ double red[SV_THREADS / WAVE][MAXR];
+  __shared__ float sX[NW][16 * RS];
+  __shared__ double red[NW][MAXR];
   const int l = lane_id(), w = threadIdx.x / WAVE;
-  for (int e = threadIdx.x; e < RP * RP; e += SV_THREADS) {
+  for (int e = threadIdx.x; e < RP * RP; e += SF_THREADS) {
     const int a = e / RP, b = e % RP;
     sG[a * RS + b] = (a < R && b < R) ? (float)Gp[a * R + b] : 0.0f;
   }
-  for (int c = l; c < MAXR; c += WAVE) red[w][c] = 0.0;
   __syncthreads();
+  const bool vec = (R & 3) == 0;
+  float *xs = sX[w];
+  double sq[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sq[t][v] = 0.0;
   int nrows = 0;
   const int64_t ntiles = (I + 15) / 16;
-  const int64_t tstep = (int64_t)gridDim.x * (SV_THREADS / WAVE);
+  const int64_t tstep = (int64_t)gridDim.x * NW;
   float raw[KS];
   auto load_tile = [&](int64_t tl) {
     const int64_t rr = tl * 16 + (l % 16);
@@ -1067,10 +1083,11 @@ k_solve_f32(const float *M, int64_t I, int R, const double *Gp, float *X,
       raw[ks] = mrow[k < R ? k : R - 1];
     }
   };
-  int64_t tile = (int64_t)blockIdx.x * (SV_THREADS / WAVE) + w;
+  int64_t tile = (int64_t)blockIdx.x * NW + w;
   if (tile < ntiles) load_tile(tile);
   for (; tile < ntiles; tile += tstep) {
-    const int64_t row = tile * 16 + (l % 16);
+    const int64_t row0 = tile * 16;
+    const int64_t row = row0 + (l % 16);
     float mf[KS];
     bool nz = false;
 #pragma unroll
@@ -1088,6 +1105,7 @@ k_solve_f32(const float *M, int64_t I, int R, const double *Gp, float *X,
     asm volatile("" ::: "memory");
     const int lz = opaque_lane();
     const float *gA = sG + (lz / 16) * RS + (lz % 16);
+    const bool live = row < I;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       float4_t acc = float4_t{0, 0, 0, 0};
@@ -1095,46 +1113,58 @@ k_solve_f32(const float *M, int64_t I, int R, const double *Gp, float *X,
       for (int ks = 0; ks < KS; ++ks)
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
             gA[4 * ks * RS + 16 * t], mf[ks], acc, 0, 0, 0);
-      const int c0 = 16 * t + 4 * (l / 16);
-      double x[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) x[v] = (double)acc[v];
-      if (row < I) {
-        float *dst = X + row * R + c0;
-        if (c0 + 3 < R && (R & 3) == 0) {
-          *reinterpret_cast<float4 *>(dst) =
-              make_float4(acc[0], acc[1], acc[2], acc[3]);
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (c0 + v < R) dst[v] = acc[v];
-        }
-      }
-      // this tile's column sums of X^2: the 16 row lanes (shuffle tree),
-      // added to the wave's row of `red` in tile order
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        double q = row < I ? x[v] * x[v] : 0.0;
-        for (int o = 1; o < 16; o <<= 1) q += __shfl_xor(q, o, WAVE);
-        if ((l % 16) == 0 && c0 + v < R) red[w][c0 + v] += q;
+        const double x = (double)acc[v];
+        sq[t][v] += live ? x * x : 0.0;
       }
+      *reinterpret_cast<float4_t *>(xs + (l % 16) * RS + 16 * t + 4 * (l / 16)) = acc;
       __builtin_amdgcn_sched_barrier(0);
     }
+    wave_lds_sync();  // the tile's X rows are in LDS
+    const int nv = I - row0 < 16 ? (int)(I - row0) : 16;
+    float *dst = X + row0 * R;
+    if (vec) {  // nv R / 4 chunks of 4 floats, each inside one row
+      const int nch = nv * R / 4;
+      for (int q = l; q < nch; q += WAVE) {
+        const int e = 4 * q, r = e / R, c = e - r * R;
+        *reinterpret_cast<float4_t *>(dst + e) =
+            *reinterpret_cast<const float4_t *>(xs + r * RS + c);
+      }
+    } else {
+      const int ne = nv * R;
+      for (int e = l; e < ne; e += WAVE) {
+        const int r = e / R, c = e - r * R;
+        dst[e] = xs[r * RS + c];
+      }
+    }
+    wave_lds_sync();  // reads done before the next tile's LDS stores
   }
+  // column sums: lane l holds columns 16 t + 4 (l / 16) + v for the rows
+  // l % 16 of its tiles; sum over the 16 row lanes, then over the waves
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double q = sq[t][v];
+      for (int o = 1; o < 16; o <<= 1) q += __shfl_xor(q, o, WAVE);
+      const int c = 16 * t + 4 * (l / 16) + v;
+      if ((l % 16) == 0 && c < MAXR) red[w][c] = q;
+    }
   if (rows_out) {
-    __shared__ int cnt[SV_THREADS / WAVE];
+    __shared__ int cnt[NW];
     if (l == 0) cnt[w] = nrows;
     __syncthreads();
     if (threadIdx.x == 0) {
       int n = 0;
-      for (int q = 0; q < SV_THREADS / WAVE; ++q) n += cnt[q];
+      for (int q = 0; q < NW; ++q) n += cnt[q];
       if (n) atomicAdd((unsigned long long *)rows_out, (unsigned long long)n);
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < R; c += SV_THREADS) {
+  for (int c = threadIdx.x; c < R; c += SF_THREADS) {
     double v = 0;
-    for (int q = 0; q < SV_THREADS / WAVE; ++q) v += red[q][c];
+    for (int q = 0; q < NW; ++q) v += red[q][c];
     partial[(int64_t)blockIdx.x * R + c] = v;
   }
 }
@@ -1358,14 +1388,22 @@ template <typename T, bool RF>
 void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
                    const double *Gp, void *Xv, double *partial, int nblk,
                    int64_t *rows_out, hipStream_t s) {
-  const dim3 g(nblk), b(SV_THREADS);
+  const dim3 g(nblk), b(SV_THREADS), bf(SF_THREADS);
   constexpr bool F32 = std::is_same<T, float>::value && !RF;
+  const int dk = 4 * ((R + 15) / 16) - (R + 3) / 4;  // all-zero k-steps
+#define CPR_SOLVE_F32(NT, D)                                                 \
+  hipLaunchKernelGGL((k_solve_f32<NT, D>), g, bf, 0, s,                      \
+                     reinterpret_cast<const float *>(M), I, R, Gp,           \
+                     static_cast<float *>(Xv), partial, rows_out)
 #define CPR_SOLVE(NT)                                                        \
-  if constexpr (F32)                                                         \
-    hipLaunchKernelGGL((k_solve_f32<NT>), g, b, 0, s,                        \
-                       reinterpret_cast<const float *>(M), I, R, Gp,         \
-                       static_cast<float *>(Xv), partial, rows_out);         \
-  else                                                                       \
+  if constexpr (F32) {                                                       \
+    switch (dk) {                                                            \
+      case 0: CPR_SOLVE_F32(NT, 0); break;                                   \
+      case 1: CPR_SOLVE_F32(NT, 1); break;                                   \
+      case 2: CPR_SOLVE_F32(NT, 2); break;                                   \
+      default: CPR_SOLVE_F32(NT, 3); break;                                  \
+    }                                                                        \
+  } else                                                                     \
     hipLaunchKernelGGL((k_solve<T, NT, RF>), g, b, 0, s, M, I, R, Gfull, Gp, \
                        static_cast<double *>(Xv), partial, rows_out)
   switch ((R + 15) / 16) {
@@ -1379,6 +1417,7 @@ void solve_rows_nt(const T *M, int64_t I, int R, const double *Gfull,
     default: CPR_SOLVE(8); break;
   }
 #undef CPR_SOLVE
+#undef CPR_SOLVE_F32
   CPR_LAUNCH_CHECK();
 }
 

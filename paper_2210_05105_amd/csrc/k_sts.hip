@@ -283,14 +283,14 @@ __device__ __forceinline__ void bfrag_entry(int f, int ln, int &k, int &c,
   off = ks / 4 < t;
 }
 
-template <int NT>
+template <int NT, int NTH = ST>
 __device__ __forceinline__ void stage_bfrag(double *dst, const double *A,
                                             int R) {
-  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + ST - 1) / ST;
+  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + NTH - 1) / NTH;
   double x[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) {  // all loads first (clamped), then masked
-    const int e = q * ST + threadIdx.x;
+    const int e = q * NTH + threadIdx.x;
     int k, c;
     bool off;
     bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
@@ -298,7 +298,7 @@ __device__ __forceinline__ void stage_bfrag(double *dst, const double *A,
   }
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
-    const int e = q * ST + threadIdx.x;
+    const int e = q * NTH + threadIdx.x;
     int k, c;
     bool off;
     bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
@@ -365,12 +365,6 @@ __device__ __forceinline__ double tile_mass_t(const double (&xA)[4 * NT],
   return s;
 }
 
-// Order one wave's LDS writes before its reads of other lanes' data.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // LDS row stride of a staged 16-row tile: RP + 1 doubles, so the 16 rows
 // of a fragment read fall in different banks
@@ -1484,6 +1478,166 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
   }
 }
 
+// One level, wide ranks, at depths where each node holds many slots: a
+// block takes a run of consecutive groups of LQ_GROUP slots (16 per wave).
+// Slots are ordered by node, so a group meets few distinct nodes, and
+// consecutive groups mostly continue the previous group's node.  For each node the
+// product G_{>k} (*) G^{left child} is formed once in LDS, in fragment order
+// (kept while the next group stays on that node), and the waves holding
+// slots at that node take their masses from LDS: the same FP64 products and
+// MFMA sums as k_sts_level_w, so the same masses, without every wave
+// streaming the node from global memory tile by tile.  Placement as in
+// k_sts_level_w.
+constexpr int LQ_THREADS = 256;
+constexpr int LQ_GROUP = 16 * (LQ_THREADS / WAVE);
+constexpr int LQ_BLOCKS = 512;    // two blocks per CU
+constexpr int64_t LQ_MIN = 512;   // slots per node on average to use it
+
+// sQ = G_{>k} (*) G^node in the fragment order of stage_bfrag (off-diagonal
+// blocks doubled, zeros beyond R), in chunks of CH entries per thread: the
+// chunk's loads first, then its products.  Block-wide; a barrier must follow.
+template <int NT, int NTH>
+__device__ __forceinline__ void form_q(double *sQ, const double *Gg,
+                                       const double *nd, int R) {
+  constexpr int RP = 16 * NT;
+  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + NTH - 1) / NTH;
+  constexpr int CH = 8;
+#pragma unroll
+  for (int q0 = 0; q0 < NS; q0 += CH) {
+    double g[CH], x[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int e = (q0 + j) * NTH + threadIdx.x;
+      int k, c;
+      bool off;
+      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+      g[j] = Gg[(k < R ? k : R - 1) * R + (c < R ? c : R - 1)];
+      x[j] = nd[k <= c ? packed_index(k, c, RP) : packed_index(c, k, RP)];
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int e = (q0 + j) * NTH + threadIdx.x;
+      int k, c;
+      bool off;
+      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+      const double gv = (off ? 2.0 : 1.0) * g[j] * ((k < R && c < R) ? 1.0 : 0.0);
+      if (q0 + j < NS && e < NE) sQ[e] = x[j] * gv;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one chunk's loads at a time
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(LQ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
+              StsWork w, SlotBuf in, SlotBuf out) {
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  constexpr int NE = bfrag_count<NT>() * WAVE;
+  __shared__ double sQ[NE];  // G_{>k} (*) G^qnode, fragment order
+  __shared__ int32_t sh_s[LQ_GROUP], sh_v[LQ_GROUP], sh_beg[LQ_GROUP],
+      sh_end[LQ_GROUP], sh_r[LQ_GROUP];
+  __shared__ double sh_t[LQ_GROUP], sh_m[LQ_GROUP];
+  const int l = lane_id(), wv = threadIdx.x / WAVE;
+  // a contiguous run of groups per block, so consecutive groups share nodes
+  const int64_t ngrp = (J + LQ_GROUP - 1) / LQ_GROUP;
+  const int64_t gpb = (ngrp + gridDim.x - 1) / gridDim.x;
+  const int64_t g0 = (int64_t)blockIdx.x * gpb;
+  const int64_t g1 = g0 + gpb < ngrp ? g0 + gpb : ngrp;
+  int32_t qnode = -1;  // the node whose product sQ holds (block-uniform)
+  for (int64_t grp = g0; grp < g1; ++grp) {
+    const int64_t pb = grp * LQ_GROUP;
+    const int64_t p = pb + 16 * wv + l;
+    const bool act = l < 16 && p < J;
+    const int64_t pc = p < J ? p : J - 1;
+    const int32_t s = in.s[pc];
+    const int32_t v = in.v[pc];
+    double t = in.t[pc], m = in.m[pc];
+    const int32_t par = v > 1 ? v >> 1 : 1;
+    const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
+    double xA[4 * NT];
+    load_hfrag_direct<NT>(w.h, s, xA);
+    const int32_t beg = v == 1 ? pbg : (v & 1) ? pbg + nl : pbg;
+    const int32_t end = v == 1 ? pen : (v & 1) ? pen : pbg + nl;
+    if (act && p == beg) {
+      w.sbeg[v] = beg;
+      w.send[v] = end;
+    }
+    if (l < 16) sh_v[16 * wv + l] = act ? v : INT32_MAX;  // ascending
+    __syncthreads();
+    double mL = 0.0;
+    int32_t cur = sh_v[0];
+    while (cur != INT32_MAX) {  // the group's distinct nodes, in order
+      // first slot past cur's run
+      int lo = 0, hi = LQ_GROUP;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sh_v[mid] <= cur) lo = mid + 1; else hi = mid;
+      }
+      const int32_t nxt = lo < LQ_GROUP ? sh_v[lo] : INT32_MAX;
+      if (cur != qnode) {
+        form_q<NT, LQ_THREADS>(sQ, Gg, tree + (int64_t)(2 * cur) * P, R);
+        qnode = cur;
+        __syncthreads();  // sQ formed
+      }
+      const uint64_t here = __ballot(act && v == cur);
+      if (here) {
+        const double x = tile_mass_s<NT>(xA, sQ);
+        if ((here >> l) & 1ull) mL = x;
+      }
+      if (nxt != INT32_MAX) __syncthreads();  // sQ read before it changes
+      cur = nxt;
+    }
+    const bool right = mL <= 0 || (t >= mL && m - mL > 0);
+    if (right) {
+      t -= (mL > 0 ? mL : 0.0);
+      m -= mL;
+    } else {
+      m = mL;
+    }
+    if (l < 16) {
+      const int i = 16 * wv + l;
+      sh_s[i] = s;
+      sh_beg[i] = beg;
+      sh_end[i] = end;
+      sh_t[i] = t;
+      sh_m[i] = m;
+      sh_r[i] = right ? 1 : 0;
+    }
+    __syncthreads();  // also: every wave's sQ reads are done
+    if (wv == 0) {  // placement of the group's 64 slots
+      const bool a2 = pb + l < J;
+      const int32_t v2 = sh_v[l], b2 = sh_beg[l], e2 = sh_end[l];
+      const bool r2 = sh_r[l] != 0;
+      const int32_t vp = __shfl_up(v2, 1, WAVE);
+      const bool lead = a2 && (l == 0 || vp != v2);
+      const uint64_t leads = __ballot(lead), am = __ballot(a2);
+      const uint64_t rm = __ballot(a2 && r2);
+      const uint64_t upto = (2ull << l) - 1;
+      const uint64_t below = upto >> 1;
+      const uint64_t ldb = leads & upto;
+      const int myld = ldb ? 63 - __clzll((long long)ldb) : 0;
+      const uint64_t nxl = leads & ~upto;
+      const uint64_t gend = nxl ? ((1ull << __ffsll((long long)nxl) - 1) - 1) : ~0ull;
+      const uint64_t grpm = am & gend & ~((1ull << myld) - 1);
+      const uint64_t gL = grpm & ~rm, gR = grpm & rm;
+      int32_t bl = 0, br = 0;
+      if (lead && gL) bl = atomicAdd(&w.lc[cslot(v2)], (int32_t)__popcll(gL));
+      if (lead && gR) br = atomicAdd(&w.rc[cslot(v2)], (int32_t)__popcll(gR));
+      bl = __shfl(bl, myld, WAVE);
+      br = __shfl(br, myld, WAVE);
+      const int32_t pos = r2 ? e2 - 1 - (br + (int32_t)__popcll(gR & below))
+                             : b2 + bl + (int32_t)__popcll(gL & below);
+      if (a2) {
+        out.s[pos] = sh_s[l];
+        out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
+        out.t[pos] = sh_t[l];
+        out.m[pos] = sh_m[l];
+      }
+    }
+    __syncthreads();  // sh_* read before the next group writes them
+  }
+}
+
 // Leaf, wide ranks (as k_sts_leaf): one wave per 16 slots, one leaf row of
 // every slot per pass, the next row's values in flight during the pass.
 template <typename T, int NT>
@@ -1816,10 +1970,20 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
       CPR_LAUNCH_CHECK();
     }
     for (int64_t n = n0; n < P2; n <<= 1) {
-      if constexpr (WIDE)
-        hipLaunchKernelGGL((k_sts_level_w<NT>), gl, b, 0, st, tree, Gg, R, J,
-                           w, w.slot[cur], w.slot[cur ^ 1]);
-      else
+      if constexpr (WIDE) {
+        // n nodes at this depth: with LQ_MIN slots per node on average, a
+        // slot group meets about two nodes and the LDS-staged form is used
+        if (n * LQ_MIN <= J) {
+          const int64_t ng = (J + LQ_GROUP - 1) / LQ_GROUP;
+          hipLaunchKernelGGL((k_sts_level_q<NT>),
+                             dim3((unsigned)std::min<int64_t>(ng, LQ_BLOCKS)),
+                             dim3(LQ_THREADS), 0, st, tree, Gg, R, J, w,
+                             w.slot[cur], w.slot[cur ^ 1]);
+        } else {
+          hipLaunchKernelGGL((k_sts_level_w<NT>), gl, b, 0, st, tree, Gg, R,
+                             J, w, w.slot[cur], w.slot[cur ^ 1]);
+        }
+      } else
         hipLaunchKernelGGL((k_sts_level<NT>), gl, b, 0, st, tree, Gg, R, J, w,
                            w.slot[cur], w.slot[cur ^ 1]);
       CPR_LAUNCH_CHECK();

@@ -75,6 +75,24 @@ def test_mixed_mode_solves_teacher_forced(dev, sampler, R, leaf):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("R", [6, 16, 25, 75])
+def test_fp32_row_solve_any_rank(dev, prec, R):
+    """The FP32 row solve at ranks that leave 2, 0, 1 and 1 all-zero k-steps
+    of the padded product, with row lengths that are not a multiple of 4
+    (element-wise output) or are (16-byte output), on modes whose row counts
+    leave a partial last 16-row tile: U_j, sigma and G_j against the oracle,
+    teacher-forced."""
+    T = tg.zipf_tensor(87, (2001, 1503, 405), 60_000, s=1.1)
+    J = 1024
+    ctx = make_ctx(dev, T, R, "arls", prec, J)
+    _, runi = init_ctx(ctx, T.dims, R, 88, fp32=True)
+    for j in range(T.N):
+        u = tg.uniform_block(runi, J, T.N)
+        check_mode_solve(ctx, T, j, u, J, "arls", 1e-4)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
 def test_error_of_each_result_against_fp64(dev, prec):
     """One ARLS mode solve in reduced precision: G_k, G^+, M, U_j and the fit
     against an FP64 recomputation from the same stored factors and draws
