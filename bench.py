@@ -32,9 +32,10 @@ import tensorgen as tg  # noqa: E402
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 FP64_PEAK_TFS = 78.6      # MI355X FP64 vector / matrix
 
-# per workload: precision and STS leaf size when not given
-DEFAULTS = {"planted": ("fp64", 16), "zipf3": ("fp32", 16),
-            "zipf4": ("mixed", 16), "zipf3xl": ("mixed", 32),
+# per workload: precision and STS leaf size when not given (0: the library
+# chooses it per tree factor)
+DEFAULTS = {"planted": ("fp64", 0), "zipf3": ("fp32", 0),
+            "zipf4": ("mixed", 0), "zipf3xl": ("mixed", 0),
             "batch3": ("mixed", 16)}
 DEVICE_GENERATED = ("zipf4", "zipf3xl", "batch3")
 BATCH_RANKS = (8, 16, 32, 64, 128)   # batched restarts: ranks drawn from
@@ -83,16 +84,17 @@ def sts_flops_per_solve(dims, j, R, J, F):
     """Algorithmic FP64 FLOPs of the STS-CP draws of one mode-j solve.
 
     First factor (h = 1): row masses U[i] G_{>k} U[i]^T, 2R^2 + 2R per row.
-    Each later factor, per draw: the root and one left-child mass per level,
-    <(h h^T) (*) G_{>k}, G^node> at 3 FLOPs per packed entry (P = R(R+1)/2),
-    then F leaf rows at R + 2R^2 each.  Per draw: h^T G^+ h, 2R^2 + R.
+    Each later factor k, per draw: the root and one left-child mass per
+    level, <(h h^T) (*) G_{>k}, G^node> at 3 FLOPs per packed entry
+    (P = R(R+1)/2), then F[k] leaf rows at R + 2R^2 each.  Per draw:
+    h^T G^+ h, 2R^2 + R.
     """
     P = R * (R + 1) // 2
     modes = [k for k in range(len(dims)) if k != j]
     fl = dims[modes[0]] * (2 * R * R + 2 * R)
     for k in modes[1:]:
-        depth = math.ceil(math.log2(max(1, -(-dims[k] // F))))
-        fl += J * ((depth + 1) * 3 * P + F * (2 * R * R + R))
+        depth = math.ceil(math.log2(max(1, -(-dims[k] // F[k]))))
+        fl += J * ((depth + 1) * 3 * P + F[k] * (2 * R * R + R))
     return fl + J * (2 * R * R + R)
 
 
@@ -579,6 +581,8 @@ def main():
         ph = ctx.profile_read()
         ctx.profile(False)
     sweeps_per_s = a.steps / dt
+    # rows per leaf of each factor's tree (0: no tree)
+    leaves = [ctx.sts_leaf(k)[0] if sampler == "sts" else 0 for k in range(N)]
 
     # ---- roofline of the dominant kernel and the sampled MTTKRP
     solves = max(cnt["solves"], 1)
@@ -604,7 +608,7 @@ def main():
                       distinct_columns_per_solve=cnt["unique"] / solves,
                       rows_out_per_solve=cnt["rows"] / solves)
         if sampler == "sts" and ph.get("sample", (0, 0))[1]:
-            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaf)
+            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaves)
                           for j in range(N)])
             ms_s = per_launch("sample")
             ach = fl / (ms_s * 1e-3) / 1e12
@@ -614,7 +618,7 @@ def main():
         dom = max(ph, key=lambda k: ph[k][0])
         ms_dom = per_launch(dom)
         if dom == "sample" and sampler == "sts":
-            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaf)
+            fl = np.mean([sts_flops_per_solve(dims, j, R, J, leaves)
                           for j in range(N)])
             ach = fl / (ms_dom * 1e-3) / 1e12
             roof = dict(kernel="sts_draw", bound="mfma", achieved=ach,
@@ -650,7 +654,7 @@ def main():
         "config": {"workload": a.workload, "dims": list(dims), "nnz": nnz,
                    "R": R, "J": J, "sampler": sampler,
                    "precision": precision, "sweeps_timed": a.steps,
-                   "sts_leaf": leaf, "parallelism": "single-gpu",
+                   "sts_leaf": leaves, "parallelism": "single-gpu",
                    "autotuned": tuned},
         "fit": fit, "init_s": t_init,
         "compare": compare,

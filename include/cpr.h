@@ -82,7 +82,10 @@ typedef struct {
   int32_t R;          /* target rank, 1 <= R <= 128                            */
   int32_t sampler;    /* cp_sampler                                            */
   int32_t precision;  /* cp_precision                                          */
-  int32_t sts_leaf;   /* STS-CP tree leaf size in rows (16, 32 or 64); 0: 16  */
+  int32_t sts_leaf;   /* STS-CP tree leaf size in rows (16, 32 or 64) for
+                         every tree factor; 0: per factor, from its rows,
+                         the draws from it per sweep and max_J (see
+                         cp_sts_leaf)                                        */
   int64_t max_J;      /* largest J any cp_sample will use, <= 2^24 (sizes    
                          workspaces); ignored by CP_SAMPLER_EXACT             */
   int32_t bucket_rows;  /* output rows per bucket of the sampled MTTKRP's
@@ -289,6 +292,22 @@ cp_status cp_counters(cp_ctx *ctx, int64_t *out, int32_t reset);
 /* Index statistics for mode (host outputs): nonempty columns, longest column. */
 cp_status cp_index_stats(cp_ctx *ctx, int32_t mode, int64_t *n_cols,
                          int64_t *max_col);
+
+/*
+ * cp_sts_leaf - the STS-CP tree of factor `mode` (Appendix B: a binary tree
+ * over the factor's rows whose leaves hold F consecutive rows each; a draw
+ * descends it, then scans one leaf's rows).  Host outputs (either may be
+ * null): *leaf_rows = F, *leaves = the number of leaves (a power of two);
+ * both 0 if the factor has no tree (another sampler, or a factor that is
+ * always drawn first).  With cp_config.sts_leaf = 0, F is chosen per factor:
+ * the tree is rebuilt once per sweep and drawn from d times (every other
+ * mode's solve but those that draw it first), and F = 16, 32 or 64 nearest
+ * to sqrt(94 I / (d max_J)) balances the build's memory traffic (about
+ * three node Grams per leaf) against the leaf scans (F quadratic forms per
+ * sample).
+ */
+cp_status cp_sts_leaf(cp_ctx *ctx, int32_t mode, int32_t *leaf_rows,
+                      int64_t *leaves);
 
 /*
  * Batched restarts: B independent decompositions of one tensor (Alg. 1 run

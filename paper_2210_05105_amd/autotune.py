@@ -3,8 +3,9 @@
 Parameters are chosen by timing whole ALS sweeps on the caller's own tensor
 (random N(0,1) factors, seeded uniforms), one candidate at a time:
 
-- ``sts_leaf``: rows per STS-CP tree leaf, F in {16, 32, 64} (tree depth and
-  tree bytes against the rows each draw scans in its leaf);
+- ``sts_leaf``: rows per STS-CP tree leaf, the library's per-factor choice
+  (0) or one F in {16, 32, 64} for every tree (tree depth and tree bytes
+  against the rows each draw scans in its leaf);
 - ``bucket_rows``: output rows per bucket of the sampled MTTKRP's
   row-ordered placement, B in {64, 128, 256} (placement atomics against
   split buckets to combine);
@@ -24,7 +25,7 @@ import json
 import os
 import time
 
-LEAVES = (16, 32, 64)
+LEAVES = (0, 16, 32, 64)
 BUCKETS = (64, 128, 256)
 STREAMS = (1, 2, 4, 8)
 

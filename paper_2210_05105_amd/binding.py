@@ -95,6 +95,7 @@ def load_library(path=None):
         "cp_profile_phases": [P, C.c_uint32],
         "cp_profile_read": [P, P, P],
         "cp_index_stats": [P, I32, C.POINTER(I64), C.POINTER(I64)],
+        "cp_sts_leaf": [P, I32, C.POINTER(I32), C.POINTER(I64)],
         "cp_counters": [P, P, I32],
         "cp_pinv": [P, I32, P, P],
         "cp_batch_init": [C.POINTER(_Tensor), I32, P, C.POINTER(_Config),
@@ -348,6 +349,13 @@ class Context:
         self._check(self.lib.cp_index_stats(self._h, mode, C.byref(a),
                                             C.byref(b)))
         return a.value, b.value
+
+    def sts_leaf(self, mode):
+        """(rows per leaf, leaves) of mode's STS-CP tree; (0, 0) if none."""
+        f, n = C.c_int32(0), C.c_int64(0)
+        self._check(self.lib.cp_sts_leaf(self._h, mode, C.byref(f),
+                                         C.byref(n)))
+        return f.value, n.value
 
 
 class Batch:

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <functional>
 #include <cstring>
 #include <mutex>
@@ -25,7 +26,8 @@ struct ProfEv {
 }  // namespace
 
 struct cp_ctx {
-  int N = 0, R = 0, sampler = 0, precision = 0, F = 16;
+  int N = 0, R = 0, sampler = 0, precision = 0, F = 0;
+  int Fk[MAXN] = {};  // STS rows per leaf of each mode's tree
   int gram_mode = GRAM_F64;  // MFMA form of the factor Grams
   bool f64 = true;
   int64_t nnz = 0, max_J = 0;
@@ -173,6 +175,7 @@ ModeList make_ml(cp_ctx *c, int j) {
     ml.last[q] = c->last[k];
     ml.tree[q] = c->tree[k];
     ml.P2[q] = c->P2[k];
+    ml.F[q] = c->Fk[k];
     ml.Ggt[q] = c->ggt ? c->ggt + (int64_t)q * c->R * c->R : nullptr;
   }
   return ml;
@@ -258,6 +261,29 @@ void check_factors(cp_ctx *c) {
 // some j >= 2 exists.
 bool sts_tree_factor(int N, int k) { return k >= 2 || (k == 1 && N >= 3); }
 
+// Mode solves of one sweep that draw factor k from its tree: every j != k
+// for k >= 2; j >= 2 for k = 1 (mode 1 is drawn first when j = 0).
+int sts_draws_per_sweep(int N, int k) {
+  return k >= 2 ? N - 1 : k == 1 ? N - 2 : 0;
+}
+
+// Leaf rows F of a tree factor of I rows drawn d times per sweep with J
+// samples, when the configuration leaves it open.  Per sweep the tree is
+// built once, about three node Grams of memory traffic per leaf (the leaf,
+// its share of the nodes above, their re-reads), and each draw scans F leaf
+// rows per sample, one FP64 quadratic form per row.  Node bytes and form
+// work both grow as R^2, so build + draws ~ a I / F + b d J F, minimal at
+// F = sqrt((a / b) I / (d J)); a / b ~ 94 is the ratio of the sampler's
+// MFMA rate (about 55 TFLOP/s on the symmetric forms) to the build's
+// memory rate (about 3.5 TB/s) per node entry.  Rounded to 16, 32 or 64 at
+// the geometric midpoints.
+int auto_leaf(int64_t I, int d, int64_t J) {
+  if (d <= 0) return 16;
+  const double f = std::sqrt(94.0 * (double)I /
+                             ((double)d * (double)std::max<int64_t>(J, 1)));
+  return f < 22.6 ? 16 : f < 45.3 ? 32 : 64;
+}
+
 template <typename T>
 void rebuild_sampler(cp_ctx *c, int k) {
   PhaseScope ps(c, PH_SAMPLER_BUILD);
@@ -272,7 +298,7 @@ void rebuild_sampler(cp_ctx *c, int k) {
     arls_build<T>(U, c->dims[k], c->R, c->Gp1, c->lev[k], c->cdf[k],
                   c->coarse[k], c->Zd[k], c->last[k], c->tmp, c->d_err, c->s);
   } else if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, k)) {
-    sts_build<T>(U, c->dims[k], c->R, c->F, c->P2[k], c->tree[k], c->s);
+    sts_build<T>(U, c->dims[k], c->R, c->Fk[k], c->P2[k], c->tree[k], c->s);
   }
 }
 
@@ -306,7 +332,7 @@ void do_sample(cp_ctx *c, int mode, int64_t J, const double *uni) {
   {
     PhaseScope ps(c, PH_SAMPLE);
     if (sts) {
-      sts_draw<T>(ml, J, c->R, c->F, uni, c->Gp, c->trace, c->sidx, c->prob,
+      sts_draw<T>(ml, J, c->R, uni, c->Gp, c->trace, c->sidx, c->prob,
                   static_cast<T *>(c->h), c->sw, c->d_err, c->s);
     } else {
       arls_draw<T>(ml, J, c->R, uni, c->sidx, c->prob, static_cast<T *>(c->h),
@@ -394,7 +420,7 @@ void do_solve(cp_ctx *c, int mode) {
   if (c->sampler == CP_SAMPLER_STS && sts_tree_factor(c->N, mode) &&
       c->P2[mode] >= 2) {
     PhaseScope ps(c, PH_SAMPLER_BUILD);  // the tree's root is the Gram
-    sts_build_scaled<T>(c->X, c->x32, c->sigma, U, I, c->R, c->F,
+    sts_build_scaled<T>(c->X, c->x32, c->sigma, U, I, c->R, c->Fk[mode],
                         c->P2[mode], c->tree[mode], c->G[mode], c->s);
   } else {
     {
@@ -439,7 +465,10 @@ void set_config(cp_ctx *c, int N, const int64_t *dims, const cp_config *cfg) {
   c->R = cfg->R;
   c->sampler = cfg->sampler;
   c->precision = cfg->precision;
-  c->F = cfg->sts_leaf ? cfg->sts_leaf : 16;
+  c->F = cfg->sts_leaf;
+  for (int k = 0; k < N; ++k)
+    c->Fk[k] = c->F ? c->F : auto_leaf(dims[k], sts_draws_per_sweep(N, k),
+                                       cfg->max_J);
   c->f64 = (c->precision == CP_FP64);
   c->gram_mode = c->precision == CP_FP64   ? GRAM_F64
                  : c->precision == CP_FP32 ? GRAM_F32
@@ -532,7 +561,7 @@ void init_state(cp_ctx *c) {
       dalloc(c, &c->Zd[k], 8);
       dalloc(c, &c->last[k], 8);
     } else if (c->sampler == CP_SAMPLER_STS) {
-      c->P2[k] = next_pow2((I + c->F - 1) / c->F);
+      c->P2[k] = next_pow2((I + c->Fk[k] - 1) / c->Fk[k]);
       if (sts_tree_factor(N, k))
         dalloc(c, &c->tree[k], (size_t)2 * c->P2[k] * sts_packed(R) * 8);
     }
@@ -554,7 +583,8 @@ void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
     int64_t mI = 0, mP2 = 1;
     for (int k = 0; k < N; ++k) {
       mI = std::max(mI, c->dims[k]);
-      mP2 = std::max(mP2, next_pow2((c->dims[k] + c->F - 1) / c->F));
+      if (sts_tree_factor(N, k))
+        mP2 = std::max(mP2, next_pow2((c->dims[k] + c->Fk[k] - 1) / c->Fk[k]));
     }
     dalloc(c, &c->sw.lev, sts_first_rows(mI) * 8);
     dalloc(c, &c->sw.sub, sts_first_sums(mI) * 8);
@@ -1219,6 +1249,18 @@ cp_status cp_index_stats(cp_ctx *c, int32_t mode, int64_t *n_cols,
     check_mode(c, mode);
     if (n_cols) *n_cols = c->ix[mode].n_cols;
     if (max_col) *max_col = c->ix[mode].max_col;
+  });
+}
+
+cp_status cp_sts_leaf(cp_ctx *c, int32_t mode, int32_t *leaf_rows,
+                      int64_t *leaves) {
+  if (!c || !c->N) return CP_EINVAL;
+  return guard(c, [&] {
+    check_mode(c, mode);
+    const bool tree = c->sampler == CP_SAMPLER_STS &&
+                      sts_tree_factor(c->N, mode);
+    if (leaf_rows) *leaf_rows = tree ? c->Fk[mode] : 0;
+    if (leaves) *leaves = tree ? c->P2[mode] : 0;
   });
 }
 

@@ -48,6 +48,7 @@ struct ModeList {
   const int64_t *last[MAXN];  // ARLS last row of positive mass
   const double *tree[MAXN];   // STS trees
   int64_t P2[MAXN];           // STS leaves (power of two)
+  int F[MAXN];                // STS rows per leaf
   const double *Ggt[MAXN];    // STS G_{>k} per sampled position (R x R)
 };
 
@@ -195,7 +196,7 @@ struct StsWork {
                          // top-stage block
 };
 template <typename T>
-void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,
+void sts_draw(const ModeList &ml, int64_t J, int R, const double *uni,
               const double *Gp, const double *trace, int32_t *sidx,
               double *prob, T *h, const StsWork &w, uint32_t *err,
               hipStream_t s);
@@ -304,6 +305,13 @@ __device__ __forceinline__ int opaque_lane() {
   int z;
   asm volatile("v_mov_b32 %0, 0" : "=v"(z));
   return lane_id() + z;
+}
+
+// Factor of column r in the renormalisation U = X diag(sigma)^-1: 1 / sigma_r,
+// or 0 for a zero (or non-finite) sigma_r, so a zero column stays zero.  The
+// kernels multiply by it (one rounding more than a division, within an ulp).
+__device__ __forceinline__ double inv_or_zero(double s) {
+  return s > 0 ? 1.0 / s : 0.0;
 }
 
 // Order one wave's LDS writes before its reads of other lanes' data.

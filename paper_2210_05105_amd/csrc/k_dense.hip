@@ -68,9 +68,9 @@ k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
       else v[q] = (double)U[(c0 + rc) * R + ccc];
     }
   };
-  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS per entry
+  __shared__ double ssg[SCALE ? MAXR : 1];  // 1 / sigma, read per entry
   if constexpr (SCALE)
-    for (int c = threadIdx.x; c < R; c += GR_THREADS) ssg[c] = sigma[c];
+    for (int c = threadIdx.x; c < R; c += GR_THREADS) ssg[c] = inv_or_zero(sigma[c]);
   if (r0 < r1) load(r0);
   for (int64_t c0 = r0; c0 < r1; c0 += RC) {
     const int nrow = (int)std::min<int64_t>(RC, r1 - c0);
@@ -82,8 +82,7 @@ k_gram_partial(const T *U, const double *X, const double *sigma, T *Uout,
       const bool in = rr < nrow && cc < R;
       double x = v[q];
       if constexpr (SCALE) {
-        const double sg = ssg[cc < R ? cc : R - 1];
-        const T u = (T)(sg > 0 ? x / sg : 0.0);
+        const T u = (T)(x * ssg[cc < R ? cc : R - 1]);
         if (in) Uout[(c0 + rr) * R + cc] = u;
         x = (double)u;
       }
@@ -168,7 +167,7 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
   constexpr int LDS_BYTES = MODE == GRAM_F32 ? GL_RC * (MAXR + 4) * 4
                                              : 2 * MAXR * GL_CS * 2;
   __shared__ __align__(16) char lds_raw[LDS_BYTES];
-  __shared__ double ssg[SCALE ? MAXR : 1];  // sigma, read from LDS
+  __shared__ double ssg[SCALE ? MAXR : 1];  // 1 / sigma, read from LDS
   float *ldsf = reinterpret_cast<float *>(lds_raw);  // F32: GL_RC x RS
   short *hiT = reinterpret_cast<short *>(lds_raw);   // BF16: Rp x GL_CS
   short *loT = hiT + MAXR * GL_CS;
@@ -197,7 +196,7 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
   for (int e = threadIdx.x; e < LDS_BYTES / 4; e += GL_THREADS)
     reinterpret_cast<uint32_t *>(lds_raw)[e] = 0u;
   if constexpr (SCALE)
-    for (int c = threadIdx.x; c < R; c += GL_THREADS) ssg[c] = sigma[c];
+    for (int c = threadIdx.x; c < R; c += GL_THREADS) ssg[c] = inv_or_zero(sigma[c]);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = std::min<int64_t>(I, r0 + rows_per_blk);
   const float rinv = 1.0f / (float)R;
@@ -235,8 +234,7 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
         const int rr = (int)(((float)f + 0.5f) * rinv), cc = f - rr * R;
         float x;
         if constexpr (SCALE) {
-          const double sg = ssg[cc];
-          x = (float)(sg > 0 ? (double)v[q] / sg : 0.0);
+          x = (float)((double)v[q] * ssg[cc]);
           Uout[c0 * R + f] = x;
         } else {
           x = v[q];
@@ -1193,8 +1191,7 @@ __global__ void k_scale_cols(const double *X, int64_t n, int R,
                              const double *sigma, T *U) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  double sg = sigma[e % R];
-  U[e] = (T)(sg > 0 ? X[e] / sg : 0.0);
+  U[e] = (T)(X[e] * inv_or_zero(sigma[e % R]));
 }
 
 template <typename T>

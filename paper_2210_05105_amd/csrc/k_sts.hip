@@ -126,7 +126,7 @@ k_tree_build(const T *U, const XT *X, const double *sigma, T *Uout,
 #pragma unroll
     for (int ta = 0; ta < NT; ++ta) {
       const int ca = ta * 16 + (l % 16);
-      sg[ta] = sigma[ca < R ? ca : R - 1];
+      sg[ta] = inv_or_zero(sigma[ca < R ? ca : R - 1]);  // 1 / sigma
     }
   }
   for (int lf = w; lf < LB; lf += 4) {
@@ -160,7 +160,7 @@ k_tree_build(const T *U, const XT *X, const double *sigma, T *Uout,
           const int ca = ta * 16 + (l % 16);
           double x = col[q][ta];
           if constexpr (SCALE) {
-            const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
+            const T u = (T)(x * sg[ta]);
             if (r < I && ca < R) Uout[r * R + ca] = u;
             x = (double)u;
           }
@@ -1790,7 +1790,7 @@ __device__ __forceinline__ void leaf_acc(const T *U, const XT *X,
           const int ca = ta * 16 + (l % 16);
           double x = col[qq][ta];
           if constexpr (SCALE) {
-            const T u = (T)(sg[ta] > 0 ? x / sg[ta] : 0.0);
+            const T u = (T)(x * sg[ta]);
             if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
             x = (double)u;
           }
@@ -1900,7 +1900,7 @@ k_tree_build_w(const T *U, const XT *X, const double *sigma, T *Uout,
 #pragma unroll
   for (int ta = 0; ta < NT; ++ta) {
     const int ca = ta * 16 + (l % 16);
-    sg[ta] = SCALE ? sigma[ca < R ? ca : R - 1] : 1.0;
+    sg[ta] = SCALE ? inv_or_zero(sigma[ca < R ? ca : R - 1]) : 1.0;  // 1 / sigma
   }
   constexpr int NAMAX = (NT * (NT + 1) / 2 + 3) / 4;
   __shared__ double4_t stash[PAIR ? 4 * NAMAX * WAVE : 1];
@@ -1916,7 +1916,7 @@ k_tree_build_w(const T *U, const XT *X, const double *sigma, T *Uout,
 }
 
 template <typename T, int NT>
-void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
+void draw_nt(const ModeList &ml, int64_t J, int R, const double *uni,
              const double *Gp, const double *trace, int32_t *sidx,
              double *prob, T *h, const StsWork &w, uint32_t *err,
              hipStream_t st) {
@@ -1990,6 +1990,7 @@ void draw_nt(const ModeList &ml, int64_t J, int R, int F, const double *uni,
       cur ^= 1;
     }
     const T *Uq = static_cast<const T *>(ml.U[q]);
+    const int F = ml.F[q];
     if constexpr (WIDE) {
       hipLaunchKernelGGL((k_sts_leaf_w<T, NT>), gl, b, 0, st, Uq, ml.I[q], R,
                          F, P2, Gg, J, w, w.slot[cur], q, nq, sidx, err);
@@ -2105,26 +2106,26 @@ template void sts_build<double>(const double *, int64_t, int, int, int64_t,
                                 double *, hipStream_t);
 
 template <typename T>
-void sts_draw(const ModeList &ml, int64_t J, int R, int F, const double *uni,
+void sts_draw(const ModeList &ml, int64_t J, int R, const double *uni,
               const double *Gp, const double *trace, int32_t *sidx,
               double *prob, T *h, const StsWork &w, uint32_t *err,
               hipStream_t s) {
   switch ((R + 15) / 16) {
-    case 1: draw_nt<T, 1>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 2: draw_nt<T, 2>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 3: draw_nt<T, 3>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 4: draw_nt<T, 4>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 5: draw_nt<T, 5>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 6: draw_nt<T, 6>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    case 7: draw_nt<T, 7>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
-    default: draw_nt<T, 8>(ml, J, R, F, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 1: draw_nt<T, 1>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 2: draw_nt<T, 2>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 3: draw_nt<T, 3>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 4: draw_nt<T, 4>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 5: draw_nt<T, 5>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 6: draw_nt<T, 6>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    case 7: draw_nt<T, 7>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
+    default: draw_nt<T, 8>(ml, J, R, uni, Gp, trace, sidx, prob, h, w, err, s); break;
   }
 }
-template void sts_draw<float>(const ModeList &, int64_t, int, int,
+template void sts_draw<float>(const ModeList &, int64_t, int,
                               const double *, const double *, const double *,
                               int32_t *, double *, float *, const StsWork &,
                               uint32_t *, hipStream_t);
-template void sts_draw<double>(const ModeList &, int64_t, int, int,
+template void sts_draw<double>(const ModeList &, int64_t, int,
                                const double *, const double *, const double *,
                                int32_t *, double *, double *,
                                const StsWork &, uint32_t *, hipStream_t);

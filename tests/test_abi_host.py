@@ -136,4 +136,4 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert at._load(str(path)) == {}
     at._store(str(path), {"k": {"sts_leaf": 32, "bucket_rows": 128}})
     assert at._load(str(path))["k"]["sts_leaf"] == 32
-    assert at.LEAVES == (16, 32, 64) and 128 in at.BUCKETS
+    assert at.LEAVES == (0, 16, 32, 64) and 128 in at.BUCKETS

@@ -140,12 +140,39 @@ def test_sts_wide_rank_fp32_deep_tree(dev):
     T, _ = tg.tiny_tensor(50, (30, 320_000, 24), 600_000, rank=3,
                           noise_var=0.01, dtype=np.float32)
     R, J = 100, 1536
-    ctx = make_ctx(dev, T, R, "sts", "fp32", J)
+    ctx = make_ctx(dev, T, R, "sts", "fp32", J, 16)
     _, runi = init_ctx(ctx, T.dims, R, 51, fp32=True)
     acc = 0
     for j in (2, 0, 1):
         u = tg.uniform_block(runi, J, 3)
         acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-4)
+    assert acc <= 2
+    ctx.close()
+
+
+def test_sts_leaf_per_factor(dev):
+    """With sts_leaf = 0 each tree factor gets its own leaf size: F nearest
+    to sqrt(94 I / (d J)) among 16, 32, 64, d = draws from the tree per
+    sweep (mode 1: one, mode 2: two).  Here mode 1 (40,000 rows) gets 64-row
+    leaves and mode 2 (2,000 rows) 16-row leaves in one context; the draws
+    from both trees follow the oracle."""
+    T, _ = tg.tiny_tensor(57, (300, 40_000, 2000), 80_000, rank=3,
+                          noise_var=0.01)
+    R, J = 24, 512
+    ctx = make_ctx(dev, T, R, "sts", "fp64", J)
+    for k, d in ((1, 1), (2, 2)):
+        f = np.sqrt(94.0 * T.dims[k] / (d * J))
+        want = 16 if f < 22.6 else 32 if f < 45.3 else 64
+        F, n = ctx.sts_leaf(k)
+        assert F == want, (k, F, want)
+        assert n == 1 << int(np.ceil(np.log2(-(-T.dims[k] // F)))), (k, n)
+    assert ctx.sts_leaf(0) == (0, 0)  # always drawn first: no tree
+    assert ctx.sts_leaf(1)[0] == 64 and ctx.sts_leaf(2)[0] == 16
+    _, runi = init_ctx(ctx, T.dims, R, 58)
+    acc = 0
+    for j in (2, 0, 1):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, "sts", 1e-10)
     assert acc <= 2
     ctx.close()
 
