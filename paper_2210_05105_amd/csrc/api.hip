@@ -595,6 +595,7 @@ void init_workspace(cp_ctx *c, cp_ctx *own, int Rws) {
       dalloc(c, &c->sw.slot[b].v, Js * 4);
       dalloc(c, &c->sw.slot[b].t, Js * 8);
       dalloc(c, &c->sw.slot[b].m, Js * 8);
+      dalloc(c, &c->sw.slot[b].z, Js * 8);
     }
     dalloc(c, &c->sw.lc, sts_counters(mP2) * 4);
     dalloc(c, &c->sw.rc, sts_counters(mP2) * 4);

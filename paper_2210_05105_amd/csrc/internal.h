@@ -184,6 +184,7 @@ struct SlotBuf {
   int32_t *v;  // current node (heap index)
   double *t;   // target inside the node
   double *m;   // mass of the node
+  double *z;   // mass of the root (the sample's total for this factor)
 };
 struct StsWork {
   double *h;             // J x sts_pad(R): product of the rows drawn so far

@@ -244,6 +244,18 @@ k_tree_up(double *tree, int64_t first, int G, int P, double *Gm, int R,
 // ---------------------------------------------------------------------------
 constexpr int ST = 256;
 
+// Descent: a sample goes right when its target t lies beyond the left
+// child's mass mL and the right child's mass m - mL is positive.  That
+// difference is formed, not computed from the right child's Gram, so where
+// the right subtree is empty it is only the rounding of the masses above
+// (a few ulps of the root mass z).  A right child below STS_RTOL z counts
+// as empty: the law moves by less than that fraction of the total.
+constexpr double STS_RTOL = 1e-13;
+__device__ __forceinline__ bool goes_right(double t, double m, double mL,
+                                           double z) {
+  return mL <= 0 || (t >= mL && m - mL > STS_RTOL * z);
+}
+
 // R x R row-major matrix into LDS as RP x RP with zeros beyond R (block-wide;
 // a barrier must follow)
 template <int RP>
@@ -652,6 +664,7 @@ k_sts_root(const double *tree, const double *Gg, int64_t P2, int R,
   out.v[g] = 1;
   out.t[g] = u * Z;
   out.m[g] = Z;
+  out.z[g] = Z;
 }
 
 // Top of a tree factor (trees of at least 2 TOP_N leaves): instead of the
@@ -797,6 +810,7 @@ k_sts_top(const double *tree, const double *Gg, int64_t P2, int R,
       out.v[g] = TOP_N + pick;
       out.t[g] = t;
       out.m[g] = mv;
+      out.z[g] = Z;
       atomicAdd(&scnt[pick], 1);
     }
   }
@@ -827,7 +841,7 @@ k_sts_top_place(int64_t J, StsWork w, SlotBuf in, SlotBuf out,
   const bool a = g < J;
   const int64_t gc = a ? g : J - 1;
   const int32_t s = in.s[gc], v = in.v[gc];
-  const double t = in.t[gc], m = in.m[gc];
+  const double t = in.t[gc], m = in.m[gc], z = in.z[gc];
   int32_t tot[TOP_N], pre[TOP_N];
 #pragma unroll
   for (int i = 0; i < TOP_N; ++i) tot[i] = pre[i] = 0;
@@ -888,6 +902,7 @@ k_sts_top_place(int64_t J, StsWork w, SlotBuf in, SlotBuf out,
     out.v[pos] = v;
     out.t[pos] = t;
     out.m[pos] = m;
+    out.z[pos] = z;
   }
 }
 
@@ -903,7 +918,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
             StsWork w, SlotBuf in, SlotBuf out) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
   __shared__ int32_t sh_s[64], sh_v[64], sh_beg[64], sh_end[64];
-  __shared__ double sh_t[64], sh_m[64];
+  __shared__ double sh_t[64], sh_m[64], sh_z[64];
   __shared__ int32_t sh_r[64];
   __shared__ double sG[bfrag_count<NT>() * WAVE];  // G_{>k}, zeros beyond R
   __shared__ double sH[ST / WAVE][16 * tile_stride<NT>()];
@@ -918,6 +933,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
   const int32_t s = in.s[pc];
   const int32_t v = in.v[pc];
   double t = in.t[pc], m = in.m[pc];
+  const double z = in.z[pc];
   stage_bfrag<NT>(sG, Gg, R);
   // slot range of node v: the root's, or the parent's split at its left count
   const int32_t par = v > 1 ? v >> 1 : 1;
@@ -967,7 +983,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
       load_node(v0);
     }
   }
-  const bool right = mL <= 0 || (t >= mL && m - mL > 0);
+  const bool right = goes_right(t, m, mL, z);
   if (right) {
     t -= (mL > 0 ? mL : 0.0);
     m -= mL;
@@ -982,6 +998,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
     sh_end[i] = end;
     sh_t[i] = t;
     sh_m[i] = m;
+    sh_z[i] = z;
     sh_r[i] = right ? 1 : 0;
   }
   __syncthreads();
@@ -1018,6 +1035,7 @@ k_sts_level(const double *tree, const double *Gg, int R, int64_t J,
     out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
     out.t[pos] = sh_t[l];
     out.m[pos] = sh_m[l];
+    out.z[pos] = sh_z[l];
   }
 }
 
@@ -1381,6 +1399,7 @@ k_sts_root_w(const double *tree, const double *Gg, int64_t P2, int R,
   out.v[g] = 1;
   out.t[g] = u * Z;
   out.m[g] = Z;
+  out.z[g] = Z;
 }
 
 // One level, wide ranks (as k_sts_level; the mass of each distinct node's
@@ -1391,7 +1410,7 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
               StsWork w, SlotBuf in, SlotBuf out) {
   constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
   __shared__ int32_t sh_s[64], sh_v[64], sh_beg[64], sh_end[64];
-  __shared__ double sh_t[64], sh_m[64];
+  __shared__ double sh_t[64], sh_m[64], sh_z[64];
   __shared__ int32_t sh_r[64];
   __shared__ double sG[bfrag_count<NT>() * WAVE];  // G_{>k}, zeros beyond R
   const int64_t pb = (int64_t)blockIdx.x * 64;
@@ -1403,6 +1422,7 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
   const int32_t s = in.s[pc];
   const int32_t v = in.v[pc];
   double t = in.t[pc], m = in.m[pc];
+  const double z = in.z[pc];
   stage_bfrag<NT>(sG, Gg, R);
   const int32_t par = v > 1 ? v >> 1 : 1;
   const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
@@ -1428,7 +1448,7 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
     if ((grp >> l) & 1ull) mL = x;
     rem &= ~grp;
   }
-  const bool right = mL <= 0 || (t >= mL && m - mL > 0);
+  const bool right = goes_right(t, m, mL, z);
   if (right) {
     t -= (mL > 0 ? mL : 0.0);
     m -= mL;
@@ -1443,6 +1463,7 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
     sh_end[i] = end;
     sh_t[i] = t;
     sh_m[i] = m;
+    sh_z[i] = z;
     sh_r[i] = right ? 1 : 0;
   }
   __syncthreads();
@@ -1475,6 +1496,7 @@ k_sts_level_w(const double *tree, const double *Gg, int R, int64_t J,
     out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
     out.t[pos] = sh_t[l];
     out.m[pos] = sh_m[l];
+    out.z[pos] = sh_z[l];
   }
 }
 
@@ -1536,7 +1558,7 @@ k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
   __shared__ double sQ[NE];  // G_{>k} (*) G^qnode, fragment order
   __shared__ int32_t sh_s[LQ_GROUP], sh_v[LQ_GROUP], sh_beg[LQ_GROUP],
       sh_end[LQ_GROUP], sh_r[LQ_GROUP];
-  __shared__ double sh_t[LQ_GROUP], sh_m[LQ_GROUP];
+  __shared__ double sh_t[LQ_GROUP], sh_m[LQ_GROUP], sh_z[LQ_GROUP];
   const int l = lane_id(), wv = threadIdx.x / WAVE;
   // a contiguous run of groups per block, so consecutive groups share nodes
   const int64_t ngrp = (J + LQ_GROUP - 1) / LQ_GROUP;
@@ -1552,6 +1574,7 @@ k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
     const int32_t s = in.s[pc];
     const int32_t v = in.v[pc];
     double t = in.t[pc], m = in.m[pc];
+    const double z = in.z[pc];
     const int32_t par = v > 1 ? v >> 1 : 1;
     const int32_t pbg = w.sbeg[par], pen = w.send[par], nl = w.lc[cslot(par)];
     double xA[4 * NT];
@@ -1587,7 +1610,7 @@ k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
       if (nxt != INT32_MAX) __syncthreads();  // sQ read before it changes
       cur = nxt;
     }
-    const bool right = mL <= 0 || (t >= mL && m - mL > 0);
+    const bool right = goes_right(t, m, mL, z);
     if (right) {
       t -= (mL > 0 ? mL : 0.0);
       m -= mL;
@@ -1601,6 +1624,7 @@ k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
       sh_end[i] = end;
       sh_t[i] = t;
       sh_m[i] = m;
+      sh_z[i] = z;
       sh_r[i] = right ? 1 : 0;
     }
     __syncthreads();  // also: every wave's sQ reads are done
@@ -1632,6 +1656,7 @@ k_sts_level_q(const double *tree, const double *Gg, int R, int64_t J,
         out.v[pos] = 2 * v2 + (r2 ? 1 : 0);
         out.t[pos] = sh_t[l];
         out.m[pos] = sh_m[l];
+        out.z[pos] = sh_z[l];
       }
     }
     __syncthreads();  // sh_* read before the next group writes them
@@ -1751,9 +1776,21 @@ k_sts_final_w(int R, int64_t J, const double *hbuf, const double *Gp,
 // Gram split over the 4 waves (tile i to wave i % 4); every wave reads the
 // leaves' rows, wave 0 writes the renormalised factor (SCALE).  Nodes above
 // the parents come from k_tree_up.
-template <typename T, int NT, bool SCALE, int W, typename XT>
+// Rows of U staged by wave 0 of the build (SCALE): 16 rows, stride RP + one
+// 16-byte chunk, so each k-block's rows go out as one contiguous span.
+template <typename T, int NT>
+constexpr int ustage_stride() { return 16 * NT + 16 / (int)sizeof(T); }
+// staged only where two blocks (the leaf stash and the rows) still fit a CU
+template <typename T, int NT, bool PAIR>
+constexpr bool ustage_fits() {
+  return 2 * ((PAIR ? 4 * ((NT * (NT + 1) / 2 + 3) / 4) * WAVE * 32 : 32) +
+              16 * ustage_stride<T, NT>() * (int)sizeof(T)) <= 160 * 1024;
+}
+
+template <typename T, int NT, bool SCALE, int W, typename XT, bool STAGE>
 __device__ __forceinline__ void leaf_acc(const T *U, const XT *X,
                                          const double (&sg)[NT], T *Uout,
+                                         T *ubuf,
                                          int64_t I, int R, int F, int64_t leaf,
                                          double4_t (&acc)[(NT * (NT + 1) / 2 - W + 3) / 4 > 0
                                                               ? (NT * (NT + 1) / 2 - W + 3) / 4
@@ -1791,7 +1828,12 @@ __device__ __forceinline__ void leaf_acc(const T *U, const XT *X,
           double x = col[qq][ta];
           if constexpr (SCALE) {
             const T u = (T)(x * sg[ta]);
-            if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
+            if constexpr (STAGE) {
+              if (W == 0 && ca < R)
+                ubuf[(4 * (q0 + qq) + l / 16) * ustage_stride<T, NT>() + ca] = u;
+            } else {
+              if (W == 0 && r < I && ca < R) Uout[r * R + ca] = u;
+            }
             x = (double)u;
           }
           col[qq][ta] = x * (ca < R ? rm : 0.0);
@@ -1809,6 +1851,27 @@ __device__ __forceinline__ void leaf_acc(const T *U, const XT *X,
                   col[qq][ta], col[qq][tb], acc[i / 4], 0, 0, 0);
           }
       __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (SCALE && STAGE && W == 0) {  // the 16 staged rows, contiguous
+      constexpr int US = ustage_stride<T, NT>(), VW = 16 / (int)sizeof(T);
+      wave_lds_sync();
+      const int64_t r0 = rbase + k0;
+      const int nv = I - r0 < 16 ? (int)(I - r0) : 16;
+      T *dst = Uout + r0 * R;
+      if (nv > 0 && R % VW == 0) {
+        typedef T vec_t __attribute__((ext_vector_type(VW)));
+        for (int q = l; q < nv * R / VW; q += WAVE) {
+          const int e = VW * q, rr = e / R, c = e - rr * R;
+          *reinterpret_cast<vec_t *>(dst + e) =
+              *reinterpret_cast<const vec_t *>(ubuf + rr * US + c);
+        }
+      } else if (nv > 0) {
+        for (int e = l; e < nv * R; e += WAVE) {
+          const int rr = e / R;
+          dst[e] = ubuf[rr * US + (e - rr * R)];
+        }
+      }
+      wave_lds_sync();  // read before the next k-block's rows are staged
     }
   }
 }
@@ -1866,6 +1929,7 @@ __device__ __forceinline__ void write_full(const double4_t (&acc)[NA],
 template <typename T, int NT, bool SCALE, bool PAIR, int W, typename XT>
 __device__ __forceinline__ void leaf_block(const T *U, const XT *X,
                                            const double (&sg)[NT], T *Uout,
+                                           T *ubuf,
                                            int64_t I, int R, int F, int64_t P2,
                                            int64_t b, double *tree, double *G,
                                            double4_t *stash) {
@@ -1875,14 +1939,14 @@ __device__ __forceinline__ void leaf_block(const T *U, const XT *X,
   const int l = lane_id();
   double4_t a0[NA];
   if constexpr (!PAIR) {
-    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, b, a0);
+    leaf_acc<T, NT, SCALE, W, XT, ustage_fits<T, NT, PAIR>()>(U, X, sg, Uout, ubuf, I, R, F, b, a0);
     write_tiles<NT, W>(a0, tree + (P2 + b) * (int64_t)P);
   } else {
-    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, 2 * b, a0);
+    leaf_acc<T, NT, SCALE, W, XT, ustage_fits<T, NT, PAIR>()>(U, X, sg, Uout, ubuf, I, R, F, 2 * b, a0);
     write_tiles<NT, W>(a0, tree + (P2 + 2 * b) * (int64_t)P);
 #pragma unroll
     for (int i = 0; i < NA; ++i) stash[i * WAVE + l] = a0[i];
-    leaf_acc<T, NT, SCALE, W, XT>(U, X, sg, Uout, I, R, F, 2 * b + 1, a0);
+    leaf_acc<T, NT, SCALE, W, XT, ustage_fits<T, NT, PAIR>()>(U, X, sg, Uout, ubuf, I, R, F, 2 * b + 1, a0);
     write_tiles<NT, W>(a0, tree + (P2 + 2 * b + 1) * (int64_t)P);
 #pragma unroll
     for (int i = 0; i < NA; ++i) a0[i] += stash[i * WAVE + l];
@@ -1904,14 +1968,16 @@ k_tree_build_w(const T *U, const XT *X, const double *sigma, T *Uout,
   }
   constexpr int NAMAX = (NT * (NT + 1) / 2 + 3) / 4;
   __shared__ double4_t stash[PAIR ? 4 * NAMAX * WAVE : 1];
+  __shared__ __align__(16)
+      T ubuf[SCALE && ustage_fits<T, NT, PAIR>() ? 16 * ustage_stride<T, NT>() : 1];
   const int64_t b = blockIdx.x;
   const int w = threadIdx.x / WAVE;
   double4_t *st = stash + (PAIR ? w * NAMAX * WAVE : 0);
   switch (w) {
-    case 0: leaf_block<T, NT, SCALE, PAIR, 0, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    case 1: leaf_block<T, NT, SCALE, PAIR, 1, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    case 2: leaf_block<T, NT, SCALE, PAIR, 2, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
-    default: leaf_block<T, NT, SCALE, PAIR, 3, XT>(U, X, sg, Uout, I, R, F, P2, b, tree, G, st); break;
+    case 0: leaf_block<T, NT, SCALE, PAIR, 0, XT>(U, X, sg, Uout, ubuf, I, R, F, P2, b, tree, G, st); break;
+    case 1: leaf_block<T, NT, SCALE, PAIR, 1, XT>(U, X, sg, Uout, ubuf, I, R, F, P2, b, tree, G, st); break;
+    case 2: leaf_block<T, NT, SCALE, PAIR, 2, XT>(U, X, sg, Uout, ubuf, I, R, F, P2, b, tree, G, st); break;
+    default: leaf_block<T, NT, SCALE, PAIR, 3, XT>(U, X, sg, Uout, ubuf, I, R, F, P2, b, tree, G, st); break;
   }
 }
 
