@@ -1360,14 +1360,47 @@ k_sts_mass_w(const T *U, int64_t I, int R, const double *Gg, int gshift,
   if (threadIdx.x == 0) grp[blockIdx.x] = gs;
 }
 
+// sQ = G_{>k} (*) G^node in the fragment order of stage_bfrag (off-diagonal
+// blocks doubled, zeros beyond R), in chunks of CH entries per thread: the
+// chunk's loads first, then its products.  Block-wide; a barrier must follow.
+template <int NT, int NTH>
+__device__ __forceinline__ void form_q(double *sQ, const double *Gg,
+                                       const double *nd, int R) {
+  constexpr int RP = 16 * NT;
+  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + NTH - 1) / NTH;
+  constexpr int CH = 8;
+#pragma unroll
+  for (int q0 = 0; q0 < NS; q0 += CH) {
+    double g[CH], x[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int e = (q0 + j) * NTH + threadIdx.x;
+      int k, c;
+      bool off;
+      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+      g[j] = Gg[(k < R ? k : R - 1) * R + (c < R ? c : R - 1)];
+      x[j] = nd[k <= c ? packed_index(k, c, RP) : packed_index(c, k, RP)];
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int e = (q0 + j) * NTH + threadIdx.x;
+      int k, c;
+      bool off;
+      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
+      const double gv = (off ? 2.0 : 1.0) * g[j] * ((k < R && c < R) ? 1.0 : 0.0);
+      if (q0 + j < NS && e < NE) sQ[e] = x[j] * gv;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one chunk's loads at a time
+  }
+}
+
 // Root of a tree factor, wide ranks (as k_sts_root).
 template <int NT>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
 k_sts_root_w(const double *tree, const double *Gg, int64_t P2, int R,
              const double *uni, int q, int nq, int64_t J, StsWork w,
              SlotBuf out, uint32_t *err) {
-  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
-  __shared__ double sG[bfrag_count<NT>() * WAVE];
+  __shared__ double sQ[bfrag_count<NT>() * WAVE];  // G_{>k} (*) G^root
   const int64_t g0 = (int64_t)blockIdx.x * ST + threadIdx.x;
   for (int64_t i = g0; i < CTOP * CLINE + 2 * P2; i += (int64_t)gridDim.x * ST) {
     w.lc[i] = 0;
@@ -1377,29 +1410,35 @@ k_sts_root_w(const double *tree, const double *Gg, int64_t P2, int R,
     w.sbeg[1] = 0;
     w.send[1] = (int32_t)J;
   }
-  stage_bfrag<NT>(sG, Gg, R);
+  constexpr int RP = 16 * NT, P = RP * (RP + 1) / 2;
+  form_q<NT, ST>(sQ, Gg, tree + P, R);  // the product k_sts_level_q forms
   __syncthreads();
   const int l = lane_id();
-  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
-  if (p0 >= J) return;
-  const int64_t g = p0 + l;
-  const bool act = l < 16 && g < J;
-  const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
-  double xA[4 * NT];
-  load_hfrag_direct<NT>(w.h, s, xA);
-  const double Z = tile_mass_node<NT>(xA, tree + P, sG);
-  if (!act) return;
-  double u = uni[g * nq + q];
-  if (!(u >= 0.0 && u < 1.0)) {
-    atomicOr(err, ERR_UNIFORM);
-    u = 0.0;
+  // every block stages the product once and its waves take 16-slot tiles
+  const int64_t ntile = (J + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE;
+       tile < ntile; tile += (int64_t)gridDim.x * (ST / WAVE)) {
+    const int64_t p0 = tile * 16;
+    const int64_t g = p0 + l;
+    const bool act = l < 16 && g < J;
+    const int32_t s = (int32_t)(p0 + ((l % 16) < J - p0 ? (l % 16) : 0));
+    double xA[4 * NT];
+    load_hfrag_direct<NT>(w.h, s, xA);
+    const double Z = tile_mass_s<NT>(xA, sQ);
+    if (act) {
+      double u = uni[g * nq + q];
+      if (!(u >= 0.0 && u < 1.0)) {
+        atomicOr(err, ERR_UNIFORM);
+        u = 0.0;
+      }
+      if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
+      out.s[g] = (int32_t)g;
+      out.v[g] = 1;
+      out.t[g] = u * Z;
+      out.m[g] = Z;
+      out.z[g] = Z;
+    }
   }
-  if (!(Z > 0)) atomicOr(err, ERR_ZERO_MASS);
-  out.s[g] = (int32_t)g;
-  out.v[g] = 1;
-  out.t[g] = u * Z;
-  out.m[g] = Z;
-  out.z[g] = Z;
 }
 
 // One level, wide ranks (as k_sts_level; the mass of each distinct node's
@@ -1514,40 +1553,7 @@ constexpr int LQ_THREADS = 256;
 constexpr int LQ_GROUP = 16 * (LQ_THREADS / WAVE);
 constexpr int LQ_BLOCKS = 512;    // two blocks per CU
 constexpr int64_t LQ_MIN = 512;   // slots per node on average to use it
-
-// sQ = G_{>k} (*) G^node in the fragment order of stage_bfrag (off-diagonal
-// blocks doubled, zeros beyond R), in chunks of CH entries per thread: the
-// chunk's loads first, then its products.  Block-wide; a barrier must follow.
-template <int NT, int NTH>
-__device__ __forceinline__ void form_q(double *sQ, const double *Gg,
-                                       const double *nd, int R) {
-  constexpr int RP = 16 * NT;
-  constexpr int NE = bfrag_count<NT>() * WAVE, NS = (NE + NTH - 1) / NTH;
-  constexpr int CH = 8;
-#pragma unroll
-  for (int q0 = 0; q0 < NS; q0 += CH) {
-    double g[CH], x[CH];
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int e = (q0 + j) * NTH + threadIdx.x;
-      int k, c;
-      bool off;
-      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
-      g[j] = Gg[(k < R ? k : R - 1) * R + (c < R ? c : R - 1)];
-      x[j] = nd[k <= c ? packed_index(k, c, RP) : packed_index(c, k, RP)];
-    }
-#pragma unroll
-    for (int j = 0; j < CH; ++j) {
-      const int e = (q0 + j) * NTH + threadIdx.x;
-      int k, c;
-      bool off;
-      bfrag_entry<NT>((e < NE ? e : NE - 1) / WAVE, e % WAVE, k, c, off);
-      const double gv = (off ? 2.0 : 1.0) * g[j] * ((k < R && c < R) ? 1.0 : 0.0);
-      if (q0 + j < NS && e < NE) sQ[e] = x[j] * gv;
-    }
-    __builtin_amdgcn_sched_barrier(0);  // one chunk's loads at a time
-  }
-}
+constexpr int LP_BLOCKS = 512;    // persistent per-sample kernels: two per CU
 
 template <int NT>
 __global__ void __launch_bounds__(LQ_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
@@ -1748,25 +1754,29 @@ k_sts_final_w(int R, int64_t J, const double *hbuf, const double *Gp,
   stage_bfrag<NT>(sP, Gp, R);
   __syncthreads();
   const int l = lane_id();
-  const int64_t p0 = ((int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE) * 16;
-  if (p0 >= J) return;
-  const int n = J - p0 < 16 ? (int)(J - p0) : 16;
-  const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
-  double xA[4 * NT];
-  load_hfrag_direct<NT>(hbuf, s, xA);
-  const double mass = tile_mass_s<NT>(xA, sP);
-  if (l < n) prob[p0 + l] = mass / *trace;
-  const int ne = n * R;
-  double hv[RP / 4];
+  // G^+ staged once per block; its waves take 16-sample tiles
+  const int64_t ntile = (J + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * (ST / WAVE) + threadIdx.x / WAVE;
+       tile < ntile; tile += (int64_t)gridDim.x * (ST / WAVE)) {
+    const int64_t p0 = tile * 16;
+    const int n = J - p0 < 16 ? (int)(J - p0) : 16;
+    const int32_t s = (int32_t)(p0 + ((l % 16) < n ? (l % 16) : 0));
+    double xA[4 * NT];
+    load_hfrag_direct<NT>(hbuf, s, xA);
+    const double mass = tile_mass_s<NT>(xA, sP);
+    if (l < n) prob[p0 + l] = mass / *trace;
+    const int ne = n * R;
+    double hv[RP / 4];
 #pragma unroll
-  for (int it = 0; it < RP / 4; ++it) {
-    const int e = it * WAVE + l < ne ? it * WAVE + l : ne - 1;
-    hv[it] = hbuf[(p0 + e / R) * RP + e % R];
-  }
+    for (int it = 0; it < RP / 4; ++it) {
+      const int e = it * WAVE + l < ne ? it * WAVE + l : ne - 1;
+      hv[it] = hbuf[(p0 + e / R) * RP + e % R];
+    }
 #pragma unroll
-  for (int it = 0; it < RP / 4; ++it) {
-    const int e = it * WAVE + l;
-    if (e < ne) h_out[(p0 + e / R) * R + e % R] = (T)hv[it];
+    for (int it = 0; it < RP / 4; ++it) {
+      const int e = it * WAVE + l;
+      if (e < ne) h_out[(p0 + e / R) * R + e % R] = (T)hv[it];
+    }
   }
 }
 
@@ -1989,6 +1999,8 @@ void draw_nt(const ModeList &ml, int64_t J, int R, const double *uni,
   constexpr bool WIDE = NT >= WNT_MIN;
   const int nq = ml.n;
   const dim3 g(ceil_div(J, ST)), b(ST), gl(ceil_div(J, 16 * (ST / WAVE)));
+  // the kernels that stage one matrix per block and loop over sample tiles
+  const dim3 glp((unsigned)std::min<int64_t>(gl.x, LP_BLOCKS));
   const int64_t I0 = ml.I[0];
   const int gs = first_gshift(I0);
   double *grp = w.sub + first_nsub(I0);
@@ -2028,7 +2040,7 @@ void draw_nt(const ModeList &ml, int64_t J, int R, const double *uni,
     }
     if (!top) {
       if constexpr (WIDE)
-        hipLaunchKernelGGL((k_sts_root_w<NT>), gl, b, 0, st, tree, Gg, P2, R,
+        hipLaunchKernelGGL((k_sts_root_w<NT>), glp, b, 0, st, tree, Gg, P2, R,
                            uni, q, nq, J, w, w.slot[0], err);
       else
         hipLaunchKernelGGL((k_sts_root<NT>), gl, b, 0, st, tree, Gg, P2, R,
@@ -2073,7 +2085,7 @@ void draw_nt(const ModeList &ml, int64_t J, int R, const double *uni,
     CPR_LAUNCH_CHECK();
   }
   if constexpr (WIDE)
-    hipLaunchKernelGGL((k_sts_final_w<T, NT>), gl, b, 0, st, R, J, w.h, Gp,
+    hipLaunchKernelGGL((k_sts_final_w<T, NT>), glp, b, 0, st, R, J, w.h, Gp,
                        trace, prob, h);
   else
     hipLaunchKernelGGL((k_sts_final<T, NT>), gl, b, 0, st, R, J, w.h, Gp,
