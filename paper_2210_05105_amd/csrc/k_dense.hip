@@ -204,8 +204,10 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
   // row f / R, column f % R (the float quotient is exact to well under the
   // 0.5 / R margin for f < GL_RC * MAXR)
   using V = typename std::conditional<SCALE, XT, float>::type;
-  V v[GL_PE];
-  auto load = [&](int64_t c0) {
+  // two chunks of values in flight: while one is staged and multiplied, the
+  // next but one is being loaded
+  V va[GL_PE], vb[GL_PE];
+  auto load = [&](int64_t c0, V (&v)[GL_PE]) {
     const int nv = (int)std::min<int64_t>(GL_RC, r1 - c0) * R;
 #pragma unroll
     for (int q = 0; q < GL_PE; ++q) {
@@ -216,8 +218,7 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
       }
     }
   };
-  if (r0 < r1) load(r0);
-  for (int64_t c0 = r0; c0 < r1; c0 += GL_RC) {
+  auto step = [&](int64_t c0, V (&v)[GL_PE]) {
     const int nrow = (int)std::min<int64_t>(GL_RC, r1 - c0);
     const int nv = nrow * R;
     __syncthreads();  // the previous chunk's products are done
@@ -249,7 +250,7 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
       }
     }
     __syncthreads();
-    if (c0 + GL_RC < r1) load(c0 + GL_RC);
+    if (c0 + 2 * GL_RC < r1) load(c0 + 2 * GL_RC, v);
     if constexpr (MODE == GRAM_F32) {
 #pragma unroll 2
       for (int k0 = 0; k0 < GL_RC; k0 += 4) {
@@ -286,6 +287,12 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
       for (int vv = 0; vv < 4; ++vv) accd[i][vv] += (double)acc[i][vv];
       acc[i] = float4_t{0, 0, 0, 0};
     }
+  };
+  if (r0 < r1) load(r0, va);
+  if (r0 + GL_RC < r1) load(r0 + GL_RC, vb);
+  for (int64_t c0 = r0; c0 < r1; c0 += 2 * GL_RC) {
+    step(c0, va);
+    if (c0 + GL_RC < r1) step(c0 + GL_RC, vb);
   }
   double *out = partial + (int64_t)blockIdx.x * R * R;
 #pragma unroll
