@@ -525,14 +525,6 @@ def main():
     if a.workload == "batch3":
         return bench_batch(a, w, dev, precision, leaf)
     R, J, sampler = w["R"], w["J"], w["sampler"]
-    if a.autotune and a.workload in DEVICE_GENERATED and \
-            w["nnz"] >= 1_000_000_000:
-        print("bench.py --autotune is not available for the billion-nonzero "
-              "workload: its candidate contexts (leaf size 16: a 53 GB tree; "
-              "256-row buckets: 28 GB of split-bucket blocks) come within a "
-              "few GB of the HBM capacity, and a run there faulted the GPU; "
-              "see DESIGN.md (autotuner)", file=sys.stderr)
-        sys.exit(2)
     dims, N, idx_d, val_d, U0 = build_inputs(a, w, dev)
     nnz = int(idx_d.shape[0])
     tuned = None

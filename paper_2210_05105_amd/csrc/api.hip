@@ -71,7 +71,8 @@ struct cp_ctx {
   int bshift(int r) const {
     return bb_fixed >= 0 ? bb_fixed : bucket_shift(r, (int)tsize());
   }
-  int64_t *bk_start_bb[8][MAXN] = {};  // bucket regions per bucket shift
+  // bucket regions per bucket shift 0 .. BB_MAX (256-row buckets: 8)
+  int64_t *bk_start_bb[BB_MAX + 1][MAXN] = {};
   int sampled_mode = -1, mttkrp_mode = -1;
   int64_t cur_J = 0;
   bool factor_set[MAXN] = {};
@@ -244,7 +245,8 @@ cp_status guard(cp_ctx *c, F &&fn) {
 }
 
 bool valid_bucket_rows(int32_t b) {
-  return b == 0 || b == 16 || b == 32 || b == 64 || b == 128 || b == 256;
+  return b == 0 || b == 16 || b == 32 || b == 64 || b == 128 ||
+         b == (1 << BB_MAX);
 }
 
 void check_mode(cp_ctx *c, int mode) {
@@ -480,7 +482,7 @@ void set_config(cp_ctx *c, int N, const int64_t *dims, const cp_config *cfg) {
               (cfg->solve_refine == CP_REFINE_AUTO && c->f64);
   c->x32 = !c->f64 && !c->refine;
   c->bb_fixed = -1;
-  for (int b = 4; b <= 8; ++b)
+  for (int b = 4; b <= BB_MAX; ++b)
     if (cfg->bucket_rows == (1 << b)) c->bb_fixed = b;
   for (int k = 0; k < N; ++k) c->dims[k] = dims[k];
   c->max_I = 0;
@@ -533,6 +535,7 @@ void init_index(cp_ctx *c, const cp_tensor *t) {
 // per mode (built once per bucket size by the context owning the index).
 void ensure_bucket_regions(cp_ctx *c, int bb, int64_t *scratch,
                            void *scan_tmp) {
+  require(bb >= 0 && bb <= BB_MAX, CP_EINVAL, "bucket size out of range");
   if (c->bk_start_bb[bb][0]) return;
   for (int k = 0; k < c->N; ++k) {
     const int64_t nbk_k = (c->dims[k] + (1 << bb) - 1) >> bb;

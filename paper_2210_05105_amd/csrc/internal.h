@@ -14,6 +14,9 @@ namespace cpr {
 
 constexpr int WAVE = 64;
 constexpr int MAXN = 8;
+// largest bucket shift of the sampled MTTKRP: 256-row buckets (a bucket
+// record keeps row mod B in 8 bits)
+constexpr int BB_MAX = 8;
 constexpr int MAXR = 128;
 
 // Bits of the device error word (kernels atomicOr them in; synchronising

@@ -208,6 +208,26 @@ def test_mode_order_with_growing_bucket_count(dev):
     ctx.close()
 
 
+@pytest.mark.parametrize("sampler,prec,tol,B", [("arls", "fp32", 1e-4, 256),
+                                               ("sts", "fp64", 1e-10, 256),
+                                               ("arls", "fp64", 1e-10, 64)])
+def test_bucket_rows_caller_set(dev, sampler, prec, tol, B):
+    """Output-row buckets of the size the caller sets, up to 256 rows (the
+    largest: a record keeps row mod B in 8 bits, and each bucket size has
+    its own record regions in the context), for modes of 20,000, 6,000 and
+    300 rows; solves in the order 0, 2, 1, 0."""
+    T = tg.zipf_tensor(45, (20000, 6000, 300), 120_000, s=1.1)
+    R, J = 16, 6000
+    ctx = make_ctx(dev, T, R, sampler, prec, J, bucket_rows=B)
+    _, runi = init_ctx(ctx, T.dims, R, 22, fp32=(prec != "fp64"))
+    acc = 0
+    for j in (0, 2, 1, 0):
+        u = tg.uniform_block(runi, J, 3)
+        acc += check_mode_solve(ctx, T, j, u, J, sampler, tol)
+    assert acc <= 2
+    ctx.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_two_pass_record_placement(dev, prec, tol):
     """Modes with more than 256 output-row buckets place the sampled
