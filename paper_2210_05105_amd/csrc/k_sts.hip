@@ -1166,6 +1166,8 @@ k_sts_leaf(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
         if (t < pre) pick = r;
       }
     }
+    // the wave's 16 slots have all found their row: later rows change nothing
+    if (__ballot(pick < 0) == 0) break;
   }
   const bool act = l < n;
   if (pick < 0) {
@@ -1720,6 +1722,8 @@ k_sts_leaf_w(const T *U, int64_t I, int R, int F, int64_t P2, const double *Gg,
       lastpos = r;
       if (t < pre) pick = r;
     }
+    // the wave's 16 slots have all found their row: later rows change nothing
+    if (__ballot(pick < 0) == 0) break;
   }
   const bool act = l < n;
   if (pick < 0) {
