@@ -1309,16 +1309,17 @@ __device__ __forceinline__ void load_hfrag_direct(const double *hb, int32_t s,
   for (int ks = 0; ks < 4 * NT; ++ks) xA[ks] = row[4 * ks];
 }
 
-// First factor, wide ranks: as k_sts_mass with each wave's 16 factor rows
-// read straight into A fragments.
+// First factor, wide ranks: as k_sts_mass, but each wave takes whole
+// FIRST_SUB-row blocks (four 16-row tiles in order, the next tile's rows in
+// flight while one tile's masses are formed) and writes their sums, so the
+// block's waves meet only once, for the group sum; every sum is formed in
+// the same order as in k_sts_mass.
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
 k_sts_mass_w(const T *U, int64_t I, int R, const double *Gg, int gshift,
              double *lev, double *sub, double *grp, uint32_t *err) {
-  constexpr int KS = 4 * NT;
-  static_assert(FIRST_SUB == 16 * (ST / WAVE), "one row tile per wave");
+  constexpr int KS = 4 * NT, NTILE = FIRST_SUB / 16;
   __shared__ double sG[bfrag_count<NT>() * WAVE];
-  __shared__ double wsum[ST / WAVE];
   stage_bfrag<NT>(sG, Gg, R);
   __syncthreads();
   const int l = lane_id(), wv = threadIdx.x / WAVE;
@@ -1326,40 +1327,55 @@ k_sts_mass_w(const T *U, int64_t I, int R, const double *Gg, int gshift,
   const int64_t sb0 = (int64_t)blockIdx.x << gshift;
   const int64_t sb1 = sb0 + (int64_t(1) << gshift) < nsub
                           ? sb0 + (int64_t(1) << gshift) : nsub;
-  double gs = 0.0;
-  for (int64_t sb = sb0; sb < sb1; ++sb) {
-    const int64_t row0 = sb * FIRST_SUB + 16 * wv;
-    const int64_t r = row0 + (l % 16);
-    const double rm = r < I ? 1.0 : 0.0;
+  // this wave's tiles: block sb0 + wv + 4 i, tile tt; rows clamped, masked
+  T raw[KS];
+  auto load_tile = [&](int64_t sb, int tt) {
+    const int64_t r = sb * FIRST_SUB + 16 * tt + (l % 16);
     const T *src = U + (r < I ? r : I - 1) * R;
-    T raw[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {  // clamped loads first, then masked
+    for (int ks = 0; ks < KS; ++ks) {
       const int c = 4 * ks + l / 16;
       raw[ks] = src[c < R ? c : R - 1];
     }
-    double xA[KS];
+  };
+  // FP32 rows: the next tile is loaded while this one is multiplied (FP64
+  // rows would take twice the registers: loaded at the tile's start)
+  constexpr bool PF = sizeof(T) == 4 && NT <= 7;
+  const int64_t wsb0 = sb0 + wv;
+  if (PF && wsb0 < sb1) load_tile(wsb0, 0);
+  for (int64_t sb = wsb0; sb < sb1; sb += ST / WAVE) {
+    double x = 0.0;  // the block's sum, tile by tile
+#pragma unroll 1
+    for (int tt = 0; tt < NTILE; ++tt) {
+      const int64_t row0 = sb * FIRST_SUB + 16 * tt;
+      const int64_t r = row0 + (l % 16);
+      const double rm = r < I ? 1.0 : 0.0;
+      if (!PF) load_tile(sb, tt);
+      double xA[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      xA[ks] = (4 * ks + l / 16 < R) ? (double)raw[ks] * rm : 0.0;
-    double m = tile_mass_s<NT>(xA, sG);  // lanes 0..15: row row0 + l
-    if (l < 16 && r < I && !isfinite(m)) atomicOr(err, ERR_NONFINITE);
-    m = (l < 16 && r < I && m > 0) ? m : 0.0;
-    if (l < 16) lev[row0 + l] = m;  // rows past I (up to the allocation) get 0
+      for (int ks = 0; ks < KS; ++ks)
+        xA[ks] = (4 * ks + l / 16 < R) ? (double)raw[ks] * rm : 0.0;
+      if (PF) {
+        if (tt + 1 < NTILE) load_tile(sb, tt + 1);
+        else if (sb + ST / WAVE < sb1) load_tile(sb + ST / WAVE, 0);
+      }
+      double m = tile_mass_s<NT>(xA, sG);  // lanes 0..15: row row0 + l
+      if (l < 16 && r < I && !isfinite(m)) atomicOr(err, ERR_NONFINITE);
+      m = (l < 16 && r < I && m > 0) ? m : 0.0;
+      if (l < 16) lev[row0 + l] = m;  // rows past I (up to the allocation) get 0
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) m += __shfl_xor(m, o, WAVE);
-    if (l == 0) wsum[wv] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double x = 0.0;
-#pragma unroll
-      for (int q = 0; q < ST / WAVE; ++q) x += wsum[q];
-      sub[sb] = x;
-      gs += x;
+      for (int o = 1; o < 16; o <<= 1) m += __shfl_xor(m, o, WAVE);
+      x += m;
     }
-    __syncthreads();
+    if (l == 0) sub[sb] = x;
   }
-  if (threadIdx.x == 0) grp[blockIdx.x] = gs;
+  __threadfence_block();  // the waves' block sums, read back by thread 0
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gs = 0.0;
+    for (int64_t sb = sb0; sb < sb1; ++sb) gs += sub[sb];
+    grp[blockIdx.x] = gs;
+  }
 }
 
 // sQ = G_{>k} (*) G^node in the fragment order of stage_bfrag (off-diagonal
