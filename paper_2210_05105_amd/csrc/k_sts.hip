@@ -1310,10 +1310,9 @@ __device__ __forceinline__ void load_hfrag_direct(const double *hb, int32_t s,
 }
 
 // First factor, wide ranks: as k_sts_mass, but each wave takes whole
-// FIRST_SUB-row blocks (four 16-row tiles in order, the next tile's rows in
-// flight while one tile's masses are formed) and writes their sums, so the
-// block's waves meet only once, for the group sum; every sum is formed in
-// the same order as in k_sts_mass.
+// FIRST_SUB-row blocks (four 16-row tiles in order) and writes their sums,
+// so the block's waves meet only once, for the group sum; every sum is
+// formed in the same order as in k_sts_mass.
 template <typename T, int NT>
 __global__ void __launch_bounds__(ST) __attribute__((amdgpu_waves_per_eu(2)))
 k_sts_mass_w(const T *U, int64_t I, int R, const double *Gg, int gshift,
