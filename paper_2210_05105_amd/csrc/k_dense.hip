@@ -160,8 +160,11 @@ int gram_lp_blocks(int64_t I, int64_t *rows_per_blk) {
   return (int)std::max<int64_t>(1, (I + *rows_per_blk - 1) / *rows_per_blk);
 }
 
-template <int MODE, int TPW, bool SCALE, typename XT>
+// VEC: FP32 values moved four at a time (R a multiple of 4 and 16-byte
+// aligned rows, so that four consecutive values of a chunk share a row)
+template <int MODE, int TPW, bool SCALE, typename XT, bool VEC>
 __global__ void __launch_bounds__(GL_THREADS)
+__attribute__((amdgpu_waves_per_eu(VEC && SCALE && TPW <= 4 ? 4 : 1)))
 k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
           int64_t I, int R, int Rp, int64_t rows_per_blk, double *partial) {
   constexpr int LDS_BYTES = MODE == GRAM_F32 ? GL_RC * (MAXR + 4) * 4
@@ -204,17 +207,30 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
   // row f / R, column f % R (the float quotient is exact to well under the
   // 0.5 / R margin for f < GL_RC * MAXR)
   using V = typename std::conditional<SCALE, XT, float>::type;
-  // two chunks of values in flight: while one is staged and multiplied, the
-  // next but one is being loaded
+  static_assert(!VEC || std::is_same<V, float>::value, "FP32 values only");
+  constexpr int VW = VEC ? 4 : 1;      // values per load
+  constexpr int NL = GL_PE / VW;       // loads per thread per chunk
+  // DEPTH chunks of values in flight: while one is staged and multiplied,
+  // the one DEPTH chunks ahead is being loaded (one for the 16-byte scaling
+  // pass, whose 128-register bound lets two blocks share a CU)
+  constexpr int DEPTH = VEC && SCALE && TPW <= 4 ? 1 : 2;
   V va[GL_PE], vb[GL_PE];
   auto load = [&](int64_t c0, V (&v)[GL_PE]) {
     const int nv = (int)std::min<int64_t>(GL_RC, r1 - c0) * R;
+    const V *src;
+    if constexpr (SCALE) src = X + c0 * R;
+    else src = U + c0 * R;
 #pragma unroll
-    for (int q = 0; q < GL_PE; ++q) {
-      const int f = q * GL_THREADS + threadIdx.x;
+    for (int q = 0; q < NL; ++q) {
+      const int f = (q * GL_THREADS + threadIdx.x) * VW;
       if (f < nv) {
-        if constexpr (SCALE) v[q] = X[c0 * R + f];
-        else v[q] = U[c0 * R + f];
+        if constexpr (VEC) {
+          const float4_t x = *reinterpret_cast<const float4_t *>(src + f);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[4 * q + j] = x[j];
+        } else {
+          v[q] = src[f];
+        }
       }
     }
   };
@@ -229,28 +245,37 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
         else hiT[cc * GL_CS + rr] = loT[cc * GL_CS + rr] = 0;
       }
 #pragma unroll
-    for (int q = 0; q < GL_PE; ++q) {
-      const int f = q * GL_THREADS + threadIdx.x;
+    for (int q = 0; q < NL; ++q) {
+      const int f = (q * GL_THREADS + threadIdx.x) * VW;
       if (f < nv) {
         const int rr = (int)(((float)f + 0.5f) * rinv), cc = f - rr * R;
-        float x;
-        if constexpr (SCALE) {
-          x = (float)((double)v[q] * ssg[cc]);
-          Uout[c0 * R + f] = x;
-        } else {
-          x = v[q];
+        float x[VW];
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          if constexpr (SCALE) x[j] = (float)((double)v[VW * q + j] * ssg[cc + j]);
+          else x[j] = v[VW * q + j];
         }
-        if constexpr (MODE == GRAM_F32) {
-          ldsf[rr * RS + cc] = x;
-        } else {
-          const short h = bf16_rne(x);
-          hiT[cc * GL_CS + rr] = h;
-          loT[cc * GL_CS + rr] = bf16_rne(x - bf16_val(h));
+        if constexpr (SCALE) {
+          if constexpr (VEC)
+            *reinterpret_cast<float4_t *>(Uout + c0 * R + f) =
+                float4_t{x[0], x[1], x[2], x[3]};
+          else
+            Uout[c0 * R + f] = x[0];
+        }
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          if constexpr (MODE == GRAM_F32) {
+            ldsf[rr * RS + cc + j] = x[j];
+          } else {
+            const short h = bf16_rne(x[j]);
+            hiT[(cc + j) * GL_CS + rr] = h;
+            loT[(cc + j) * GL_CS + rr] = bf16_rne(x[j] - bf16_val(h));
+          }
         }
       }
     }
     __syncthreads();
-    if (c0 + 2 * GL_RC < r1) load(c0 + 2 * GL_RC, v);
+    if (c0 + DEPTH * GL_RC < r1) load(c0 + DEPTH * GL_RC, v);
     if constexpr (MODE == GRAM_F32) {
 #pragma unroll 2
       for (int k0 = 0; k0 < GL_RC; k0 += 4) {
@@ -289,10 +314,14 @@ k_gram_lp(const float *U, const XT *X, const double *sigma, float *Uout,
     }
   };
   if (r0 < r1) load(r0, va);
-  if (r0 + GL_RC < r1) load(r0 + GL_RC, vb);
-  for (int64_t c0 = r0; c0 < r1; c0 += 2 * GL_RC) {
-    step(c0, va);
-    if (c0 + GL_RC < r1) step(c0 + GL_RC, vb);
+  if constexpr (DEPTH == 1) {
+    for (int64_t c0 = r0; c0 < r1; c0 += GL_RC) step(c0, va);
+  } else {
+    if (r0 + GL_RC < r1) load(r0 + GL_RC, vb);
+    for (int64_t c0 = r0; c0 < r1; c0 += 2 * GL_RC) {
+      step(c0, va);
+      if (c0 + GL_RC < r1) step(c0 + GL_RC, vb);
+    }
   }
   double *out = partial + (int64_t)blockIdx.x * R * R;
 #pragma unroll
@@ -1256,10 +1285,26 @@ void gram_any(const T *U, const XT *X, const double *sigma, T *Uout,
     if (mode != GRAM_F64) {
       const int nbl = gram_lp_blocks(I, &rpb);
       const int tpl = (ntri + GL_THREADS / WAVE - 1) / (GL_THREADS / WAVE);
-#define CPR_GRAM_LP(M, K)                                                   \
-  hipLaunchKernelGGL((k_gram_lp<M, K, SCALE, XT>), dim3(nbl),              \
-                     dim3(GL_THREADS), 0, s, U, X, sigma, Uout, I, R, Rp, rpb, \
-                     partial)
+      // four values per load: FP32 values, R a multiple of 4, 16-byte
+      // aligned arrays (rows then start on 16-byte boundaries)
+      constexpr bool V32 = !SCALE || std::is_same<XT, float>::value;
+      const bool vec = V32 && R % 4 == 0 &&
+                       ((uintptr_t)(SCALE ? (const void *)X : (const void *)U) |
+                        (uintptr_t)(SCALE ? (void *)Uout : nullptr)) % 16 == 0;
+#define CPR_GRAM_LP(M, K)                                                     \
+  if constexpr (V32) {                                                        \
+    if (vec)                                                                  \
+      hipLaunchKernelGGL((k_gram_lp<M, K, SCALE, XT, V32>), dim3(nbl),       \
+                         dim3(GL_THREADS), 0, s, U, X, sigma, Uout, I, R, Rp, \
+                         rpb, partial);                                       \
+    else                                                                      \
+      hipLaunchKernelGGL((k_gram_lp<M, K, SCALE, XT, false>), dim3(nbl),     \
+                         dim3(GL_THREADS), 0, s, U, X, sigma, Uout, I, R, Rp, \
+                         rpb, partial);                                       \
+  } else                                                                      \
+    hipLaunchKernelGGL((k_gram_lp<M, K, SCALE, XT, false>), dim3(nbl),       \
+                       dim3(GL_THREADS), 0, s, U, X, sigma, Uout, I, R, Rp,   \
+                       rpb, partial)
 #define CPR_GRAM_LP_T(M)              \
   switch (tpl) {                      \
     case 1: CPR_GRAM_LP(M, 1); break; \
