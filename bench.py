@@ -31,6 +31,8 @@ import tensorgen as tg  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 FP64_PEAK_TFS = 78.6      # MI355X FP64 vector / matrix
+N_SIMD = 256 * 4          # MI355X: 256 compute units of 4 SIMDs
+N_XCD = 8                 # accelerator dies (each counts GRBM_GUI_ACTIVE)
 
 # per workload: precision and STS leaf size when not given (0: the library
 # chooses it per tree factor)
@@ -70,6 +72,11 @@ def parse():
     p.add_argument("--kernel-stats", metavar="DB",
                    help="print per-kernel totals of a rocprofv3 "
                         "--kernel-trace database as a markdown table and exit")
+    p.add_argument("--counter-table", metavar="DB",
+                   help="print per-dispatch averages of every counter of a "
+                        "rocprofv3 --pmc database per kernel (with the "
+                        "matrix-core busy fraction when SQ_VALU_MFMA_BUSY_"
+                        "CYCLES and GRBM_GUI_ACTIVE are among them) and exit")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="also copy MIB MiB device to device (a plain copy "
                         "kernel of known size, to scale HBM counters)")
@@ -253,6 +260,49 @@ def kernel_stats(db, top=60):
                    f"{tot[k] / cnt[k] / 1e3:.1f} | {100 * tot[k] / allt:.1f} |")
     out.append(f"\ntotal kernel time {allt / 1e6:.1f} ms over "
                f"{sum(cnt.values())} dispatches")
+    return "\n".join(out)
+
+
+def counter_table(db):
+    """Markdown table: per kernel, the dispatch count, the average duration
+    and the per-dispatch average of every counter in a rocprofv3 --pmc
+    database.  With SQ_VALU_MFMA_BUSY_CYCLES (summed over the SIMDs) and
+    GRBM_GUI_ACTIVE (summed over the dies) it adds the matrix cores' busy
+    fraction: busy cycles / (SIMDs x active cycles of one die)."""
+    import sqlite3
+    from collections import defaultdict
+    cur = sqlite3.connect(db).cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)")]
+    cn = "counter_name" if "counter_name" in cols else "name"
+    kn = "kernel_name" if "kernel_name" in cols else "name"
+    tot = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    for k, c, v, d in cur.execute(
+            f"select {kn}, {cn}, value, dispatch_id from counters_collection"):
+        k = short_kernel_name(k)
+        tot[k][c] += v
+        disp[k].add(d)
+    dur = defaultdict(list)
+    kc = [r[1] for r in cur.execute("pragma table_info(kernels)")]
+    if kc:
+        kk = "kernel_name" if "kernel_name" in kc else "name"
+        for k, b, e in cur.execute(f"select {kk}, start, end from kernels"):
+            dur[short_kernel_name(k)].append((e - b) / 1e3)
+    names = sorted({c for k in tot for c in tot[k]})
+    mf = "SQ_VALU_MFMA_BUSY_CYCLES" in names and "GRBM_GUI_ACTIVE" in names
+    head = ["kernel", "n", "avg us"] + names + (["MFMA busy"] if mf else [])
+    out = ["| " + " | ".join(head) + " |",
+           "|---|" + "---:|" * (len(head) - 1)]
+    for k in sorted(tot, key=lambda k: -sum(dur.get(k, [0]))):
+        n = len(disp[k])
+        avg = {c: tot[k][c] / n for c in names}
+        row = [k, str(n), f"{sum(dur[k]) / len(dur[k]):.1f}" if dur.get(k)
+               else "-"] + [f"{avg[c]:.4g}" for c in names]
+        if mf:
+            act = avg["GRBM_GUI_ACTIVE"] / N_XCD
+            row.append(f"{avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (N_SIMD * act):.1%}"
+                       if act > 0 else "-")
+        out.append("| " + " | ".join(row) + " |")
     return "\n".join(out)
 
 
@@ -495,6 +545,9 @@ def main():
     a = parse()
     if a.kernel_stats:
         print(kernel_stats(a.kernel_stats))
+        return
+    if a.counter_table:
+        print(counter_table(a.counter_table))
         return
     if a.reduce_counters:
         fdb, wdb, solves = a.reduce_counters
