@@ -16,14 +16,29 @@ namespace {
 // l_i for 16 rows per wave and tile: C = U_tile (16 x R) G^+ (R x R) on
 // FP64 MFMA, then l_i = sum_j C[i][j] U[i][j].  Waves stride over the row
 // tiles; the last row of positive mass is reduced per block and published
-// with one atomicMax.
+// with one atomicMax.  Up to 64 columns the B operand (G^+, zero beyond R)
+// is staged once per block in LDS in fragment order (k-step, column tile,
+// lane: 32 KiB at most), so a tile reads it with one conflict-free 8-byte
+// LDS load per product instead of from global memory.
+constexpr int LV_LDS_NT = 4;  // column tiles staged in LDS at most
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(256)
 k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
            unsigned long long *last, uint32_t *err) {
-  __shared__ unsigned long long smax[4];
-  const int l = lane_id(), w = threadIdx.x / WAVE;
+  constexpr bool SB = NT <= LV_LDS_NT;
   constexpr int Rp = NT * 16;
+  __shared__ unsigned long long smax[4];
+  __shared__ double sB[SB ? (Rp / 4) * NT * WAVE : 1];
+  const int l = lane_id(), w = threadIdx.x / WAVE;
+  if constexpr (SB) {
+    for (int e = threadIdx.x; e < (Rp / 4) * NT * WAVE; e += 256) {
+      const int ln = e % WAVE, t = (e / WAVE) % NT, ks = e / (WAVE * NT);
+      const int ka = 4 * ks + ln / 16, jb = t * 16 + ln % 16;
+      sB[e] = (ka < R && jb < R) ? Gp[ka * R + jb] : 0.0;
+    }
+    __syncthreads();
+  }
   const int64_t ntiles = (I + 15) / 16;
   unsigned long long mx = 0;
   for (int64_t tile = (int64_t)blockIdx.x * 4 + w; tile < ntiles;
@@ -34,7 +49,9 @@ k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
     for (int t = 0; t < NT; ++t) acc[t] = double4_t{0, 0, 0, 0};
     const int64_t ra = row0 + (l % 16);  // A operand row
     const int64_t rac = ra < I ? ra : I - 1;
-#pragma unroll
+    // four k-steps per pass: a full unroll would hoist every load of the
+    // tile (all registers at four column tiles, spills beyond six)
+#pragma unroll 4
     for (int k0 = 0; k0 < Rp; k0 += 4) {
       const int ka = k0 + l / 16;
       const int kac = ka < R ? ka : R - 1;
@@ -42,10 +59,15 @@ k_leverage(const T *U, int64_t I, int R, const double *Gp, double *lev,
       const double a = (ra < I && ka < R) ? av : 0.0;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const int jb = t * 16 + (l % 16);
-        const int jbc = jb < R ? jb : R - 1;
-        const double bv = Gp[kac * R + jbc];
-        const double b = (ka < R && jb < R) ? bv : 0.0;
+        double b;
+        if constexpr (SB) {
+          b = sB[((k0 / 4) * NT + t) * WAVE + l];
+        } else {
+          const int jb = t * 16 + (l % 16);
+          const int jbc = jb < R ? jb : R - 1;
+          const double bv = Gp[kac * R + jbc];
+          b = (ka < R && jb < R) ? bv : 0.0;
+        }
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
@@ -194,7 +216,10 @@ void arls_build(const T *U, int64_t I, int R, const double *Gp, double *lev,
   zero_fill<int64_t>(reinterpret_cast<int64_t *>(lastp1), 1, s);
   const int nt = (R + 15) / 16;
   const int64_t ntiles = (I + 15) / 16;
-  const dim3 g((unsigned)std::min<int64_t>(ceil_div(ntiles, 4), 512)), b(256);
+  // one round of resident blocks: four per CU up to four column tiles
+  // (G^+ in LDS, at most 91 registers), two beyond
+  const int64_t gmax = nt <= LV_LDS_NT ? 1024 : 512;
+  const dim3 g((unsigned)std::min<int64_t>(ceil_div(ntiles, 4), gmax)), b(256);
   switch (nt) {
     case 1: hipLaunchKernelGGL((k_leverage<T, 1>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
     case 2: hipLaunchKernelGGL((k_leverage<T, 2>), g, b, 0, s, U, I, R, Gp, lev, lastp1, err); break;
