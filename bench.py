@@ -556,8 +556,8 @@ def main():
                                          a.copy_calibration or 256), indent=1))
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the "
-              f"multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); this "
+              f"library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2210_05105_amd import load_library
